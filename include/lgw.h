@@ -1,0 +1,156 @@
+/* lgw — Sternheimer polarizability and Lanczos dielectric matrix on MI355X.
+ *
+ * C ABI of the hot path of the Lanczos/Sternheimer G0W0 scheme of
+ * Laflamme Janssen, Rousseau and Cote (arXiv:1408.3036):
+ *
+ *   * chi0(z) applied to a potential perturbation by one Sternheimer linear
+ *     system per valence band instead of a sum over conduction states
+ *     (Sec. III.A: projected conjugate gradients on the squared Hermitian
+ *     equation on the imaginary axis, SQMR on the two shifted equations on
+ *     the real axis);
+ *   * the Lanczos tridiagonalisation, with full reorthogonalisation, of the
+ *     symmetrised dielectric operator eps - 1 = -v^1/2 chi0 v^1/2 (Sec. II
+ *     footnote on the symmetric form, Sec. IV);
+ *   * eps(z) - 1 projected on that static Lanczos basis (Sec. VI).
+ *
+ * Discretisation (the paper leaves ABINIT's conventions implicit; this is the
+ * reading implemented): orthorhombic box with edges L = (Lx, Ly, Lz), a cubic
+ * N^3 grid r_n = (n_x Lx, n_y Ly, n_z Lz) / N, Omega = Lx Ly Lz, dV = Omega/N^3;
+ * plane waves K_m = 2 pi (m_x/Lx, m_y/Ly, m_z/Lz) with 0.5 |K_m|^2 <= ecut;
+ * H = -Laplacian/2 + V_loc with V_loc applied on the grid; Coulomb kernel
+ * truncated at R = min(L)/2 (Sec. IX): v(K) = 4 pi (1 - cos(K R)) / K^2,
+ * v(0) = 2 pi R^2, applied on the full grid; spin factor 2.
+ *
+ * Memory: when opts.mem == LGW_MEM_DEVICE (default) every bulk array
+ * (V_loc, psi_v, dV, dn, q0, Q, alpha, beta, E, x, y) is a device pointer on
+ * the context's device; with LGW_MEM_HOST they are host pointers.  Small
+ * parameter arrays (cell, grid, eps_v, z) and k_done are always host memory.
+ * Grid arrays are row-major [x][y][z] (z fastest), complex values are
+ * interleaved (re, im) doubles, i.e. C99 double _Complex / torch.complex128.
+ * The caller owns every buffer; the library copies its inputs.
+ *
+ * Errors: every call returns an lgw_status.  LGW_EINVAL and LGW_ENAN from
+ * argument checks leave outputs untouched.  LGW_ENOCONV / LGW_EBREAKDOWN
+ * still write every output (each system holds its best iterate) and
+ * lgw_get_stats tells which solves failed.  lgw_last_error gives a message.
+ * A context is bound to one device and one stream and is not thread-safe.
+ */
+#ifndef LGW_H
+#define LGW_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lgw_ctx lgw_ctx;
+typedef struct { double re, im; } lgw_c128;
+
+typedef enum { LGW_FP64 = 0, LGW_MIXED = 1 } lgw_precision;
+typedef enum { LGW_MEM_DEVICE = 0, LGW_MEM_HOST = 1 } lgw_mem;
+typedef enum {
+  LGW_OK = 0, LGW_EINVAL = 1, LGW_ENOMEM = 2, LGW_EDEVICE = 3, LGW_ENAN = 4,
+  LGW_ENOCONV = 5, LGW_EBREAKDOWN = 6
+} lgw_status;
+
+typedef struct {
+  int    precision;    /* LGW_FP64 (default) or LGW_MIXED: FP32 transforms and
+                          projector inside FP64 iterative refinement          */
+  double tol;          /* relative residual of every Sternheimer solve
+                          |b - A x| / |b|; default 1e-13                      */
+  int    max_iter;     /* iterations per solve (per refinement sweep); 5000  */
+  int    check_every;  /* iterations between host convergence polls; 8       */
+  int    precond;      /* reserved, must be 0 (no preconditioner, as in the
+                          paper's unpreconditioned CG/SQMR)                   */
+  int    deterministic;/* reductions are always in a fixed order; kept for
+                          interface stability                                 */
+  int    mem;          /* LGW_MEM_DEVICE (default) or LGW_MEM_HOST            */
+  void*  stream;       /* hipStream_t to run on; NULL = a stream the context
+                          creates                                             */
+  double mem_budget_gb;/* device workspace cap for batched solves; 16        */
+  double inner_tol;    /* mixed mode: relative tolerance of each FP32 inner
+                          solve; default 1e-5                                 */
+  int    max_sweeps;   /* mixed mode: maximum FP64 refinement sweeps; 8      */
+} lgw_opts;
+
+/* Fill *opts with the defaults listed above. */
+void lgw_default_opts(lgw_opts* opts);
+
+/* Create a context for one system (Sec. III.A: H, the valence set).
+ *   cell   [9]  lattice vectors as rows, bohr; must be diagonal (orthorhombic)
+ *   grid   [3]  N, N, N: equal, one of 16, 24, 32, 40, 48, 64, 72
+ *   ecut        plane-wave cut-off in Ha; the sphere must fit: max|m_i| <= N/2-1
+ *   V_loc  [N^3] local potential, Ha, real
+ *   n_v         valence bands, 1..32
+ *   psi_v  [n_v][N^3] valence orbitals on the grid, dV sum |psi|^2 = 1,
+ *               band-limited to the sphere
+ *   eps_v  [n_v] (host) their energies, Ha, ascending
+ *   opts        NULL for defaults
+ * Checks: shapes and ranges (EINVAL), finite inputs (ENAN), then on the
+ * device orthonormality of the sphere coefficients (|<i|j> - delta| <= 1e-8;
+ * leakage outside the sphere shows up here) and the eigen-residual
+ * |H psi_v - eps_v psi_v| <= 1e-8 Ha (EINVAL).  On error *out is NULL. */
+lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], double ecut,
+                     const double* V_loc, int n_v, const lgw_c128* psi_v, const double* eps_v,
+                     const lgw_opts* opts);
+
+/* dn = chi0(z) dV for every column and frequency (Sec. III.A).
+ *   dV [n_rhs][N^3]      perturbing potentials (complex allowed)
+ *   z  [n_z] (host)      frequencies: (0, w) = i w on the imaginary axis
+ *                        (CG on the squared equation; w = 0: CG on
+ *                        (H - e_v) f = 2 P_c b); (w, eta) with w != 0: SQMR on
+ *                        (H - e_v -+ (w + i eta)) g = P_c b
+ *   dn [n_z][n_rhs][N^3] output, chi0(z) dV as a density (1 / bohr^3 / Ha)
+ * Spin factor 2; chi0(z) x = -2 sum_v psi_v Scatter(f_v), f_v = g_- + g_+. */
+lgw_status lgw_chi0_apply(lgw_ctx* ctx, int n_rhs, const lgw_c128* dV, int n_z,
+                          const lgw_c128* z, lgw_c128* dn);
+
+/* k steps of Lanczos with full (twice classical Gram-Schmidt)
+ * reorthogonalisation on M = eps(0) - 1 = -v^1/2 chi0(0) v^1/2 (Sec. IV),
+ * Euclidean norm on grid values, started from q0/|q0|.
+ *   alpha [k]      diagonal of T
+ *   beta  [k]      beta[j] couples q_j and q_{j+1}; beta[k_done-1] is the
+ *                  norm of the final residual
+ *   Q     [k][N^3] Lanczos vectors q_0..q_{k-1}, or NULL
+ *   k_done (host)  steps done: < k when beta < 1e-14 max|alpha| (invariant
+ *                  subspace); status stays LGW_OK.  Entries past k_done are
+ *                  left untouched. */
+lgw_status lgw_lanczos(lgw_ctx* ctx, const lgw_c128* q0, int k, double* alpha, double* beta,
+                       lgw_c128* Q, int* k_done);
+
+/* E[z] = Q^H (eps(z) - 1) Q for every z of the list (the static basis reused
+ * for all frequencies, Sec. VI).  Q [k][N^3] (orthonormal rows, e.g. from
+ * lgw_lanczos), E [n_z][k][k] with E[z][a][b] = <q_a, (eps(z)-1) q_b>. */
+lgw_status lgw_project(lgw_ctx* ctx, int k, const lgw_c128* Q, int n_z, const lgw_c128* z,
+                       lgw_c128* E);
+
+/* y = (H - shift) x on sphere coefficients (the operator inside every
+ * Sternheimer solve, Sec. III.A), in the context's precision.
+ *   x, y [n][npw] in the library's sphere order (lgw_sphere). */
+lgw_status lgw_hpsi(lgw_ctx* ctx, int n, lgw_c128 shift, const lgw_c128* x, lgw_c128* y);
+
+/* y = v^1/2 x on grid vectors [n][N^3] (truncated Coulomb square root). */
+lgw_status lgw_vhalf(lgw_ctx* ctx, int n, const lgw_c128* x, lgw_c128* y);
+
+typedef struct { int N, npw, ncols, n_v; double omega; } lgw_info;
+lgw_status lgw_get_info(const lgw_ctx* ctx, lgw_info* out);
+/* Signed integer triples of the sphere in library order (host, [npw][3]). */
+lgw_status lgw_sphere(const lgw_ctx* ctx, int* m);
+
+typedef struct {
+  int n_solves;             /* solves of the last chi0_apply / lanczos step */
+  const int* iters;         /* [n_solves] Krylov iterations (all sweeps)    */
+  const double* rel_resid;  /* [n_solves] final FP64 |b - A x| / |b|        */
+  const int* refine_sweeps; /* [n_solves] FP64 refinement sweeps (mixed)    */
+  const int* flags;         /* [n_solves] 1 converged, 2 breakdown, 4 max_iter */
+  long long total_iters;    /* all Krylov iterations of the call            */
+  long long total_happly;   /* FP64 + FP32 H applications of the call       */
+} lgw_stats;
+/* Views owned by the context, valid until the next call on it. */
+lgw_status lgw_get_stats(const lgw_ctx* ctx, lgw_stats* out);
+const char* lgw_last_error(const lgw_ctx* ctx);
+void lgw_free(lgw_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

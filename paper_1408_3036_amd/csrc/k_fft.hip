@@ -1,0 +1,352 @@
+// Transform kernels: pruned z-column passes, xy-plane passes with fused
+// pointwise work, and full-grid passes (gfx950).
+#include "fft_lds.h"
+#include "kernels.h"
+
+namespace lgw {
+
+namespace {
+
+constexpr int kZCols = 32;           // z-columns per workgroup in column passes
+
+template <int N> constexpr int plane_threads() { return N >= 64 ? 512 : 256; }
+
+template <typename T, int N>
+__device__ __forceinline__ void load_tw(cplx<T>* tw_s, const cplx<T>* tw) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) tw_s[i] = tw[i];
+}
+
+// sequence t of a pruned set {-h..h} mapped to its index mod N
+template <int N>
+__device__ __forceinline__ int pruned(int t, int h) { return t <= h ? t : t + N - 2 * h - 1; }
+
+// ------------------------------------------------------------------ zinv
+template <typename T, int N>
+__global__ void __launch_bounds__(256)
+k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, long ldx,
+       cplx<T>* __restrict__ Tb, long ldt, T scale, const int* __restrict__ act) {
+  constexpr int LDZ = N + 1;
+  __shared__ cplx<T> buf[kZCols * LDZ];
+  __shared__ cplx<T> tws[N];
+  const int sys = sys_of(act, blockIdx.y);
+  const int c0 = blockIdx.x * kZCols;
+  const int nc = min(kZCols, g.ncols - c0);
+  const cplx<T>* Xs = X + (long)sys * ldx;
+  cplx<T>* Ts = Tb + (long)sys * ldt;
+  load_tw<T, N>(tws, tw);
+  for (int i = threadIdx.x; i < kZCols * LDZ; i += 256) buf[i] = cplx<T>{0, 0};
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int cl = wv; cl < nc; cl += 4) {
+    const int h = g.col_h[c0 + cl];
+    const int st = g.col_start[c0 + cl];
+    for (int m = lane; m <= 2 * h; m += 64) {
+      const int mz = m - h;
+      buf[cl * LDZ + (mz < 0 ? mz + N : mz)] = Xs[st + m];
+    }
+  }
+  __syncthreads();
+  fft_lds<T, N, +1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + e; });
+  for (int i = threadIdx.x; i < N * nc; i += 256) {
+    const int z = i / nc, cl = i - z * nc;
+    Ts[(long)z * g.ncols + c0 + cl] = scale * buf[cl * LDZ + z];
+  }
+}
+
+// ------------------------------------------------------------------ zfwd
+template <typename T, int N>
+__global__ void __launch_bounds__(256)
+k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, long ldt, T scale,
+       const cplx<T>* __restrict__ X, long ldx, const cplx<T>* __restrict__ shift,
+       const cplx<T>* __restrict__ E, long lde, const T* __restrict__ ecoef,
+       cplx<T>* __restrict__ Y, long ldy, const int* __restrict__ act) {
+  constexpr int LDZ = N + 1;
+  __shared__ cplx<T> buf[kZCols * LDZ];
+  __shared__ cplx<T> tws[N];
+  const int sys = sys_of(act, blockIdx.y);
+  const int c0 = blockIdx.x * kZCols;
+  const int nc = min(kZCols, g.ncols - c0);
+  const cplx<T>* Ts = Tb + (long)sys * ldt;
+  load_tw<T, N>(tws, tw);
+  for (int i = threadIdx.x; i < N * nc; i += 256) {
+    const int z = i / nc, cl = i - z * nc;
+    buf[cl * LDZ + z] = Ts[(long)z * g.ncols + c0 + cl];
+  }
+  __syncthreads();
+  fft_lds<T, N, -1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + e; });
+  const cplx<T>* Xs = X ? X + (long)sys * ldx : nullptr;
+  const cplx<T>* Es = E ? E + (long)sys * lde : nullptr;
+  cplx<T>* Ys = Y + (long)sys * ldy;
+  const cplx<T> sh = shift ? shift[sys] : cplx<T>{0, 0};
+  const T ec = ecoef ? ecoef[sys] : T(0);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int cl = wv; cl < nc; cl += 4) {
+    const int h = g.col_h[c0 + cl];
+    const int st = g.col_start[c0 + cl];
+    for (int m = lane; m <= 2 * h; m += 64) {
+      const int mz = m - h;
+      const int i = st + m;
+      cplx<T> v = scale * buf[cl * LDZ + (mz < 0 ? mz + N : mz)];
+      if (Xs) {
+        const cplx<T> xv = Xs[i];
+        const cplx<T> k = cplx<T>{static_cast<T>(g.kin[i]) - sh.x, -sh.y};
+        v = v + k * xv;
+      }
+      if (Es) v = v + ec * Es[i];
+      Ys[i] = v;
+    }
+  }
+}
+
+// --------------------------------------------------------------- plane_hv
+template <typename T, int N>
+__global__ void __launch_bounds__(plane_threads<N>())
+k_plane_hv(Geom g, const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ Tb, long ldt,
+           const T* __restrict__ Vt, const int* __restrict__ act) {
+  constexpr int NT = plane_threads<N>();
+  __shared__ cplx<T> pl[N * N];
+  __shared__ cplx<T> tws[N];
+  const int z = blockIdx.x;
+  const int sys = sys_of(act, blockIdx.y);
+  cplx<T>* Ts = Tb + (long)sys * ldt + (long)z * g.ncols;
+  load_tw<T, N>(tws, tw);
+  for (int i = threadIdx.x; i < N * N; i += NT) pl[i] = cplx<T>{0, 0};
+  __syncthreads();
+  for (int c = threadIdx.x; c < g.ncols; c += NT) pl[g.col_pos[c]] = Ts[c];
+  __syncthreads();
+  const int hy = g.hy;
+  const int ny = 2 * hy + 1;
+  // inverse along x on the columns y that carry data
+  fft_lds<T, N, +1, NT, N, true>(pl, tws, ny, [hy](int t, int e) { return e * N + pruned<N>(t, hy); });
+  // inverse along y on every row x
+  fft_lds<T, N, +1, NT, N, false>(pl, tws, N, [](int t, int e) { return t * N + e; });
+  const T* Vz = Vt + (long)z * N * N;
+  for (int i = threadIdx.x; i < N * N; i += NT) pl[i] = Vz[i] * pl[i];
+  __syncthreads();
+  fft_lds<T, N, -1, NT, N, false>(pl, tws, N, [](int t, int e) { return t * N + e; });
+  fft_lds<T, N, -1, NT, N, true>(pl, tws, ny, [hy](int t, int e) { return e * N + pruned<N>(t, hy); });
+  for (int c = threadIdx.x; c < g.ncols; c += NT) Ts[c] = pl[g.col_pos[c]];
+}
+
+// --------------------------------------------------------- plane_pair_fwd
+template <typename T, int N>
+__global__ void __launch_bounds__(plane_threads<N>())
+k_plane_pair_fwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ U, int nv,
+                 const cplx<T>* __restrict__ X, long ldx, cplx<T>* __restrict__ Tb, long ldt) {
+  constexpr int NT = plane_threads<N>();
+  constexpr long NN = (long)N * N;
+  __shared__ cplx<T> pl[N * N];
+  __shared__ cplx<T> tws[N];
+  const int z = blockIdx.x;
+  const int s = blockIdx.y;           // s = j * nv + v
+  const int j = s / nv, v = s - j * nv;
+  const long n3 = NN * N;
+  const cplx<T>* Uz = U + (long)v * n3 + z * NN;
+  const cplx<T>* Xz = X + (long)j * ldx + z * NN;
+  load_tw<T, N>(tws, tw);
+  for (int i = threadIdx.x; i < N * N; i += NT) pl[i] = Uz[i] * Xz[i];
+  __syncthreads();
+  const int hy = g.hy;
+  fft_lds<T, N, -1, NT, N, false>(pl, tws, N, [](int t, int e) { return t * N + e; });
+  fft_lds<T, N, -1, NT, N, true>(pl, tws, 2 * hy + 1, [hy](int t, int e) { return e * N + pruned<N>(t, hy); });
+  cplx<T>* Ts = Tb + (long)s * ldt + (long)z * g.ncols;
+  for (int c = threadIdx.x; c < g.ncols; c += NT) Ts[c] = pl[g.col_pos[c]];
+}
+
+// --------------------------------------------------------------- plane_acc
+template <typename T, int N>
+__global__ void __launch_bounds__(plane_threads<N>())
+k_plane_acc(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, long ldt,
+            const cplx<T>* __restrict__ Psi, int nv, cplx<T>* __restrict__ out, long ldo, T coef,
+            int accumulate) {
+  constexpr int NT = plane_threads<N>();
+  constexpr long NN = (long)N * N;
+  constexpr int EPT = (N * N + NT - 1) / NT;
+  __shared__ cplx<T> pl[N * N];
+  __shared__ cplx<T> tws[N];
+  const int z = blockIdx.x;
+  const int j = blockIdx.y;
+  const long n3 = NN * N;
+  load_tw<T, N>(tws, tw);
+  cplx<T> acc[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) acc[k] = cplx<T>{0, 0};
+  const int hy = g.hy;
+  for (int v = 0; v < nv; ++v) {
+    for (int i = threadIdx.x; i < N * N; i += NT) pl[i] = cplx<T>{0, 0};
+    __syncthreads();
+    const cplx<T>* Ts = Tb + (long)(j * nv + v) * ldt + (long)z * g.ncols;
+    for (int c = threadIdx.x; c < g.ncols; c += NT) pl[g.col_pos[c]] = Ts[c];
+    __syncthreads();
+    fft_lds<T, N, +1, NT, N, true>(pl, tws, 2 * hy + 1, [hy](int t, int e) { return e * N + pruned<N>(t, hy); });
+    fft_lds<T, N, +1, NT, N, false>(pl, tws, N, [](int t, int e) { return t * N + e; });
+    const cplx<T>* Pz = Psi + (long)v * n3 + z * NN;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int i = threadIdx.x + k * NT;
+      if (i < N * N) acc[k] = acc[k] + Pz[i] * pl[i];
+    }
+    __syncthreads();
+  }
+  cplx<T>* Oz = out + (long)j * ldo + z * NN;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int i = threadIdx.x + k * NT;
+    if (i < N * N) {
+      cplx<T> r = coef * acc[k];
+      if (accumulate) r = r + Oz[i];
+      Oz[i] = r;
+    }
+  }
+}
+
+// -------------------------------------------------------------- plane_full
+template <typename T, int N, int SIGN>
+__global__ void __launch_bounds__(plane_threads<N>())
+k_plane_full(const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ G, long ldg) {
+  constexpr int NT = plane_threads<N>();
+  constexpr long NN = (long)N * N;
+  __shared__ cplx<T> pl[N * N];
+  __shared__ cplx<T> tws[N];
+  cplx<T>* Gz = G + (long)blockIdx.y * ldg + blockIdx.x * NN;
+  load_tw<T, N>(tws, tw);
+  for (int i = threadIdx.x; i < N * N; i += NT) pl[i] = Gz[i];
+  __syncthreads();
+  fft_lds<T, N, SIGN, NT, N, false>(pl, tws, N, [](int t, int e) { return t * N + e; });
+  fft_lds<T, N, SIGN, NT, N, true>(pl, tws, N, [](int t, int e) { return e * N + t; });
+  for (int i = threadIdx.x; i < N * N; i += NT) Gz[i] = pl[i];
+}
+
+// --------------------------------------------------------------- zfull_mul
+template <typename T, int N>
+__global__ void __launch_bounds__(256)
+k_zfull_mul(const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ G, long ldg,
+            const T* __restrict__ mul, T scale) {
+  constexpr int LDZ = N + 1;
+  constexpr int NN = N * N;
+  __shared__ cplx<T> buf[kZCols * LDZ];
+  __shared__ cplx<T> tws[N];
+  const int c0 = blockIdx.x * kZCols;
+  const int nc = min(kZCols, NN - c0);
+  cplx<T>* Gs = G + (long)blockIdx.y * ldg;
+  load_tw<T, N>(tws, tw);
+  for (int i = threadIdx.x; i < N * nc; i += 256) {
+    const int z = i / nc, cl = i - z * nc;
+    buf[cl * LDZ + z] = Gs[(long)z * NN + c0 + cl];
+  }
+  __syncthreads();
+  fft_lds<T, N, -1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + e; });
+  for (int i = threadIdx.x; i < N * nc; i += 256) {
+    const int z = i / nc, cl = i - z * nc;
+    buf[cl * LDZ + z] = (scale * mul[(long)z * NN + c0 + cl]) * buf[cl * LDZ + z];
+  }
+  __syncthreads();
+  fft_lds<T, N, +1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + e; });
+  for (int i = threadIdx.x; i < N * nc; i += 256) {
+    const int z = i / nc, cl = i - z * nc;
+    Gs[(long)z * NN + c0 + cl] = buf[cl * LDZ + z];
+  }
+}
+
+}  // namespace
+
+bool grid_supported(int N) {
+  switch (N) {
+    case 16: case 24: case 32: case 40: case 48: case 64: case 72: return true;
+    default: return false;
+  }
+}
+
+#define LGW_DISPATCH_N(N, CALL)                 \
+  switch (N) {                                  \
+    case 16: { constexpr int NN_ = 16; CALL; } break; \
+    case 24: { constexpr int NN_ = 24; CALL; } break; \
+    case 32: { constexpr int NN_ = 32; CALL; } break; \
+    case 40: { constexpr int NN_ = 40; CALL; } break; \
+    case 48: { constexpr int NN_ = 48; CALL; } break; \
+    case 64: { constexpr int NN_ = 64; CALL; } break; \
+    case 72: { constexpr int NN_ = 72; CALL; } break; \
+    default: break;                             \
+  }
+
+template <typename T>
+void launch_zinv(const Geom& g, const cplx<T>* tw, const cplx<T>* X, long ldx, cplx<T>* Tb, long ldt,
+                 T scale, const int* act, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  dim3 grid((g.ncols + kZCols - 1) / kZCols, nsys);
+  LGW_DISPATCH_N(g.N, (k_zinv<T, NN_><<<grid, 256, 0, s>>>(g, tw, X, ldx, Tb, ldt, scale, act)));
+}
+
+template <typename T>
+void launch_plane_hv(const Geom& g, const cplx<T>* tw, cplx<T>* Tb, long ldt, const T* Vt,
+                     const int* act, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  dim3 grid(g.N, nsys);
+  LGW_DISPATCH_N(g.N, (k_plane_hv<T, NN_><<<grid, plane_threads<NN_>(), 0, s>>>(g, tw, Tb, ldt, Vt, act)));
+}
+
+template <typename T>
+void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, T scale,
+                 const cplx<T>* X, long ldx, const cplx<T>* shift, const cplx<T>* E, long lde,
+                 const T* ecoef, cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  dim3 grid((g.ncols + kZCols - 1) / kZCols, nsys);
+  LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E, lde,
+                                                        ecoef, Y, ldy, act)));
+}
+
+template <typename T>
+void launch_plane_pair_fwd(const Geom& g, const cplx<T>* tw, const cplx<T>* U, int nv, const cplx<T>* X,
+                           long ldx, int nj, cplx<T>* Tb, long ldt, hipStream_t s) {
+  if (nj <= 0) return;
+  dim3 grid(g.N, nj * nv);
+  LGW_DISPATCH_N(g.N, (k_plane_pair_fwd<T, NN_><<<grid, plane_threads<NN_>(), 0, s>>>(g, tw, U, nv, X, ldx, Tb, ldt)));
+}
+
+template <typename T>
+void launch_plane_acc(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, const cplx<T>* Psi,
+                      int nv, cplx<T>* out, long ldo, T coef, int nj, bool accumulate, hipStream_t s) {
+  if (nj <= 0) return;
+  dim3 grid(g.N, nj);
+  LGW_DISPATCH_N(g.N, (k_plane_acc<T, NN_><<<grid, plane_threads<NN_>(), 0, s>>>(g, tw, Tb, ldt, Psi, nv, out, ldo,
+                                                                              coef, accumulate ? 1 : 0)));
+}
+
+template <typename T>
+void launch_plane_full(int N, const cplx<T>* tw, cplx<T>* G, long ldg, int nvec, int sign, hipStream_t s) {
+  if (nvec <= 0) return;
+  dim3 grid(N, nvec);
+  if (sign < 0) {
+    LGW_DISPATCH_N(N, (k_plane_full<T, NN_, -1><<<grid, plane_threads<NN_>(), 0, s>>>(tw, G, ldg)));
+  } else {
+    LGW_DISPATCH_N(N, (k_plane_full<T, NN_, +1><<<grid, plane_threads<NN_>(), 0, s>>>(tw, G, ldg)));
+  }
+}
+
+template <typename T>
+void launch_zfull_mul(int N, const cplx<T>* tw, cplx<T>* G, long ldg, const T* mul, T scale, int nvec,
+                      hipStream_t s) {
+  if (nvec <= 0) return;
+  dim3 grid((N * N + kZCols - 1) / kZCols, nvec);
+  LGW_DISPATCH_N(N, (k_zfull_mul<T, NN_><<<grid, 256, 0, s>>>(tw, G, ldg, mul, scale)));
+}
+
+#define LGW_INST(T)                                                                                   \
+  template void launch_zinv<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, cplx<T>*, long, T,  \
+                               const int*, int, hipStream_t);                                         \
+  template void launch_plane_hv<T>(const Geom&, const cplx<T>*, cplx<T>*, long, const T*, const int*, \
+                                   int, hipStream_t);                                                 \
+  template void launch_zfwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, T, const cplx<T>*,  \
+                               long, const cplx<T>*, const cplx<T>*, long, const T*, cplx<T>*, long,  \
+                               const int*, int, hipStream_t);                                         \
+  template void launch_plane_pair_fwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, int,            \
+                                         const cplx<T>*, long, int, cplx<T>*, long, hipStream_t);     \
+  template void launch_plane_acc<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, const cplx<T>*, \
+                                    int, cplx<T>*, long, T, int, bool, hipStream_t);                  \
+  template void launch_plane_full<T>(int, const cplx<T>*, cplx<T>*, long, int, int, hipStream_t);     \
+  template void launch_zfull_mul<T>(int, const cplx<T>*, cplx<T>*, long, const T*, T, int, hipStream_t);
+
+LGW_INST(double)
+LGW_INST(float)
+
+}  // namespace lgw

@@ -1,0 +1,684 @@
+// Projector, batched CG / SQMR updates, residuals, Lanczos BLAS-1 and layout
+// kernels (gfx950).  One workgroup owns one system in the per-system kernels:
+// its reductions are exact block reductions in a fixed order (deterministic).
+#include "kernels.h"
+
+namespace lgw {
+
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum K values over the workgroup; every thread gets the totals in v[].
+template <typename T, int K>
+__device__ __forceinline__ void block_sum(T (&v)[K], T* sm /* >= K*NT/64 */) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    T s = wave_sum(v[k]);
+    if (lane == 0) sm[k * (NT / 64) + w] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += sm[k * (NT / 64) + i];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- projector
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_proj(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, cplx<T>* __restrict__ Y,
+       long ldy, const int* __restrict__ act) {
+  constexpr int VB = 8;
+  __shared__ T sm[2 * VB * (NT / 64)];
+  __shared__ cplx<T> c[kMaxBands];
+  const int sys = sys_of(act, blockIdx.x);
+  cplx<T>* Ys = Y + (long)sys * ldy;
+  for (int v0 = 0; v0 < nv; v0 += VB) {
+    T acc[2 * VB];
+#pragma unroll
+    for (int u = 0; u < 2 * VB; ++u) acc[u] = T(0);
+    for (int i = threadIdx.x; i < npw; i += NT) {
+      const cplx<T> y = Ys[i];
+#pragma unroll
+      for (int u = 0; u < VB; ++u) {
+        if (v0 + u < nv) {
+          const cplx<T> p = Phi[(long)(v0 + u) * ldphi + i];
+          acc[2 * u] += p.x * y.x + p.y * y.y;
+          acc[2 * u + 1] += p.x * y.y - p.y * y.x;
+        }
+      }
+    }
+    block_sum<T, 2 * VB>(acc, sm);
+    if (threadIdx.x == 0) {
+      for (int u = 0; u < VB && v0 + u < nv; ++u) c[v0 + u] = cplx<T>{acc[2 * u], acc[2 * u + 1]};
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < npw; i += NT) {
+    cplx<T> y = Ys[i];
+    for (int v = 0; v < nv; ++v) y = y - c[v] * Phi[(long)v * ldphi + i];
+    Ys[i] = y;
+  }
+}
+
+// ---------------------------------------------------------------- CG
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_cg_init(SolveVecs<T> v, const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx,
+          int npw, int keep_x, const int* __restrict__ act) {
+  __shared__ T sm[NT / 64];
+  const int sys = sys_of(act, blockIdx.x);
+  const cplx<T>* bs = b + (long)(bidx ? bidx[sys] : sys) * ldb;
+  cplx<T>* x = v.x + (long)sys * v.ld;
+  cplx<T>* r = v.r + (long)sys * v.ld;
+  cplx<T>* p = v.p + (long)sys * v.ld;
+  T acc[1] = {T(0)};
+  for (int i = threadIdx.x; i < npw; i += NT) {
+    const cplx<T> bi = bs[i];
+    if (!keep_x) x[i] = cplx<T>{0, 0};
+    r[i] = bi;
+    p[i] = bi;
+    acc[0] += norm2(bi);
+  }
+  block_sum<T, 1>(acc, sm);
+  if (threadIdx.x == 0) {
+    v.rr[sys] = acc[0];
+    if (!keep_x) { v.bb[sys] = acc[0]; v.iters[sys] = 0; }
+    v.flag[sys] = acc[0] == T(0) ? FLAG_CONV : 0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_cg_step(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act) {
+  __shared__ T sm[NT / 64];
+  const int sys = sys_of(act, blockIdx.x);
+  if (v.flag[sys]) return;
+  cplx<T>* x = v.x + (long)sys * v.ld;
+  cplx<T>* r = v.r + (long)sys * v.ld;
+  cplx<T>* p = v.p + (long)sys * v.ld;
+  const cplx<T>* Ap = v.Ap + (long)sys * v.ld;
+  T acc[1] = {T(0)};
+  for (int i = threadIdx.x; i < npw; i += NT) {
+    const cplx<T> a = p[i], b = Ap[i];
+    acc[0] += a.x * b.x + a.y * b.y;
+  }
+  block_sum<T, 1>(acc, sm);
+  const T pAp = acc[0];
+  const T rr = v.rr[sys];
+  if (!(pAp > T(0))) {
+    if (threadIdx.x == 0) v.flag[sys] = FLAG_BREAK;
+    return;
+  }
+  const T alpha = rr / pAp;
+  acc[0] = T(0);
+  for (int i = threadIdx.x; i < npw; i += NT) {
+    const cplx<T> pi = p[i];
+    x[i] = x[i] + alpha * pi;
+    const cplx<T> ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    acc[0] += norm2(ri);
+  }
+  block_sum<T, 1>(acc, sm);
+  const T rrn = acc[0];
+  const T beta = rrn / rr;
+  for (int i = threadIdx.x; i < npw; i += NT) p[i] = r[i] + beta * p[i];
+  if (threadIdx.x == 0) {
+    v.rr[sys] = rrn;
+    v.iters[sys] += 1;
+    if (rrn <= tol2 * v.bb[sys]) v.flag[sys] = FLAG_CONV;
+  }
+}
+
+// ---------------------------------------------------------------- SQMR
+// Symmetric QMR without look-ahead for the complex-symmetric projected
+// systems, with the bilinear form (a, b)_J = sum_i a[npw-1-i] b[i] (the
+// unconjugated grid product: index npw-1-i holds -m).
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_sqmr_init(SolveVecs<T> v, const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx,
+            int npw, int keep_x, const int* __restrict__ act) {
+  __shared__ T sm[3 * (NT / 64)];
+  const int sys = sys_of(act, blockIdx.x);
+  const cplx<T>* bs = b + (long)(bidx ? bidx[sys] : sys) * ldb;
+  cplx<T>* x = v.x + (long)sys * v.ld;
+  cplx<T>* r = v.r + (long)sys * v.ld;
+  cplx<T>* q = v.p + (long)sys * v.ld;
+  cplx<T>* d = v.d + (long)sys * v.ld;
+  T acc[3] = {T(0), T(0), T(0)};
+  for (int i = threadIdx.x; i < npw; i += NT) {
+    const cplx<T> bi = bs[i];
+    const cplx<T> bj = bs[npw - 1 - i];
+    if (!keep_x) x[i] = cplx<T>{0, 0};
+    d[i] = cplx<T>{0, 0};
+    r[i] = bi;
+    q[i] = bi;
+    acc[0] += norm2(bi);
+    const cplx<T> pr = bi * bj;
+    acc[1] += pr.x;
+    acc[2] += pr.y;
+  }
+  block_sum<T, 3>(acc, sm);
+  if (threadIdx.x == 0) {
+    const T nb = sqrt(acc[0]);
+    v.rr[sys] = nb;                 // tau
+    v.theta[sys] = T(0);
+    v.rho[sys] = cplx<T>{acc[1], acc[2]};
+    if (!keep_x) { v.bb[sys] = acc[0]; v.iters[sys] = 0; }
+    v.flag[sys] = acc[0] == T(0) ? FLAG_CONV : 0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_sqmr_step(SolveVecs<T> v, int npw, T tol, const int* __restrict__ act) {
+  __shared__ T sm[3 * (NT / 64)];
+  const int sys = sys_of(act, blockIdx.x);
+  if (v.flag[sys]) return;
+  cplx<T>* x = v.x + (long)sys * v.ld;
+  cplx<T>* r = v.r + (long)sys * v.ld;
+  cplx<T>* q = v.p + (long)sys * v.ld;
+  cplx<T>* d = v.d + (long)sys * v.ld;
+  const cplx<T>* t = v.Ap + (long)sys * v.ld;
+  // sigma = (q, t)_J
+  T acc[3] = {T(0), T(0), T(0)};
+  for (int i = threadIdx.x; i < npw; i += NT) {
+    const cplx<T> pr = q[npw - 1 - i] * t[i];
+    acc[0] += pr.x;
+    acc[1] += pr.y;
+  }
+  {
+    T a2[2] = {acc[0], acc[1]};
+    block_sum<T, 2>(a2, sm);
+    acc[0] = a2[0];
+    acc[1] = a2[1];
+  }
+  const cplx<T> sigma = cplx<T>{acc[0], acc[1]};
+  const cplx<T> rho = v.rho[sys];
+  const T sn = norm2(sigma);
+  if (!(sn > T(0))) {
+    if (threadIdx.x == 0) v.flag[sys] = FLAG_BREAK;
+    return;
+  }
+  // alpha = rho / sigma
+  const cplx<T> alpha = cplx<T>{(rho.x * sigma.x + rho.y * sigma.y) / sn,
+                                (rho.y * sigma.x - rho.x * sigma.y) / sn};
+  // r -= alpha t on the pairs (i, npw-1-i); accumulate |r|^2 and (r, r)_J
+  acc[0] = acc[1] = acc[2] = T(0);
+  const int half = (npw + 1) / 2;
+  for (int i = threadIdx.x; i < half; i += NT) {
+    const int j = npw - 1 - i;
+    const cplx<T> ri = r[i] - alpha * t[i];
+    r[i] = ri;
+    if (j != i) {
+      const cplx<T> rj = r[j] - alpha * t[j];
+      r[j] = rj;
+      acc[0] += norm2(ri) + norm2(rj);
+      const cplx<T> pr = ri * rj;
+      acc[1] += T(2) * pr.x;
+      acc[2] += T(2) * pr.y;
+    } else {
+      acc[0] += norm2(ri);
+      const cplx<T> pr = ri * ri;
+      acc[1] += pr.x;
+      acc[2] += pr.y;
+    }
+  }
+  block_sum<T, 3>(acc, sm);
+  const T tau = v.rr[sys];
+  const T th_old = v.theta[sys];
+  const T th = sqrt(acc[0]) / tau;
+  const T c2 = T(1) / (T(1) + th * th);
+  const T tau_n = tau * th * sqrt(c2);
+  const cplx<T> rho_n = cplx<T>{acc[1], acc[2]};
+  const T rn = norm2(rho);
+  const cplx<T> beta = cplx<T>{(rho_n.x * rho.x + rho_n.y * rho.y) / rn,
+                               (rho_n.y * rho.x - rho_n.x * rho.y) / rn};
+  const T f1 = c2 * th_old * th_old;
+  const cplx<T> f2 = c2 * alpha;
+  for (int i = threadIdx.x; i < npw; i += NT) {
+    const cplx<T> qi = q[i];
+    const cplx<T> di = f1 * d[i] + f2 * qi;
+    d[i] = di;
+    x[i] = x[i] + di;
+    q[i] = r[i] + beta * qi;
+  }
+  if (threadIdx.x == 0) {
+    const int it = v.iters[sys] + 1;
+    v.iters[sys] = it;
+    v.rr[sys] = tau_n;
+    v.theta[sys] = th;
+    v.rho[sys] = rho_n;
+    if (tau_n * sqrt(T(it + 1)) <= tol * sqrt(v.bb[sys])) v.flag[sys] = FLAG_CONV;
+    else if (!(norm2(rho_n) > T(0))) v.flag[sys] = FLAG_BREAK;
+  }
+}
+
+// ---------------------------------------------------------------- residual
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_resid(const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx,
+        const cplx<T>* __restrict__ AX, long lda, cplx<T>* __restrict__ R, long ldr,
+        double* __restrict__ res, int npw, const int* __restrict__ act) {
+  __shared__ double sm[NT / 64];
+  const int sys = sys_of(act, blockIdx.x);
+  const cplx<T>* bs = b + (long)(bidx ? bidx[sys] : sys) * ldb;
+  const cplx<T>* as = AX + (long)sys * lda;
+  cplx<T>* rs = R ? R + (long)sys * ldr : nullptr;
+  double acc[1] = {0.0};
+  for (int i = threadIdx.x; i < npw; i += NT) {
+    const cplx<T> ri = bs[i] - as[i];
+    if (rs) rs[i] = ri;
+    acc[0] += (double)norm2(ri);
+  }
+  block_sum<double, 1>(acc, sm);
+  if (threadIdx.x == 0) res[sys] = acc[0];
+}
+
+// ---------------------------------------------------------------- BLAS-1
+constexpr int kDotBlocks = 64;
+
+// partial[i][blk] = sum over the block's share of conj(A_i) w
+__global__ void __launch_bounds__(NT)
+k_dots_partial(const z64* __restrict__ A, long lda, const z64* __restrict__ w, long n,
+               z64* __restrict__ partial) {
+  __shared__ double sm[2 * (NT / 64)];
+  const int i = blockIdx.y;
+  const z64* a = A + (long)i * lda;
+  double acc[2] = {0.0, 0.0};
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
+    const z64 p = cmulc(a[e], w[e]);
+    acc[0] += p.x;
+    acc[1] += p.y;
+  }
+  block_sum<double, 2>(acc, sm);
+  if (threadIdx.x == 0) partial[(long)i * gridDim.x + blockIdx.x] = z64{acc[0], acc[1]};
+}
+
+__global__ void k_dots_final(const z64* __restrict__ partial, int nblk, z64* __restrict__ h) {
+  const int i = blockIdx.x;
+  if (threadIdx.x == 0) {
+    z64 s{0, 0};
+    for (int b = 0; b < nblk; ++b) s = s + partial[(long)i * nblk + b];
+    h[i] = s;
+  }
+}
+
+__global__ void __launch_bounds__(NT)
+k_gemv_sub(const z64* __restrict__ A, long lda, int m, const z64* __restrict__ h,
+           z64* __restrict__ w, long n) {
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
+    z64 acc = w[e];
+    for (int i = 0; i < m; ++i) acc = acc - h[i] * A[(long)i * lda + e];
+    w[e] = acc;
+  }
+}
+
+__global__ void k_alpha_final(const z64* __restrict__ partial, int nblk, double* __restrict__ alpha) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[b].x;
+    *alpha = s;
+  }
+}
+
+__global__ void __launch_bounds__(NT)
+k_lanczos_sub(z64* __restrict__ w, const z64* __restrict__ q, const z64* __restrict__ qprev,
+              const double* __restrict__ alpha, const double* __restrict__ beta_prev, long n) {
+  const double a = *alpha;
+  const double b = beta_prev ? *beta_prev : 0.0;
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
+    z64 r = w[e] - a * q[e];
+    if (qprev) r = r - b * qprev[e];
+    w[e] = r;
+  }
+}
+
+__global__ void k_norm_final(const z64* __restrict__ partial, int nblk, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[b].x;
+    *out = sqrt(s);
+  }
+}
+
+__global__ void __launch_bounds__(NT)
+k_scale_into(const z64* __restrict__ w, const double* __restrict__ nrm, z64* __restrict__ q, long n) {
+  const double s = 1.0 / *nrm;
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) q[e] = s * w[e];
+}
+
+__global__ void __launch_bounds__(NT)
+k_axpby(z64* __restrict__ y, const z64* __restrict__ x, z64 a, z64 b, long n) {
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT)
+    y[e] = a * x[e] + b * y[e];
+}
+
+__global__ void __launch_bounds__(NT)
+k_add(z64* __restrict__ y, const z64* __restrict__ a, const z64* __restrict__ b, long n) {
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) y[e] = a[e] + b[e];
+}
+
+__global__ void __launch_bounds__(NT)
+k_finite(const double* __restrict__ x, long n, int* __restrict__ flag) {
+  bool bad = false;
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT)
+    bad |= !isfinite(x[e]);
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ void __launch_bounds__(NT)
+k_cvt_64_32(const z64* __restrict__ in, z32* __restrict__ out, long n) {
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT)
+    out[e] = cvt<float>(in[e]);
+}
+
+// x[sys] += scale[sys] * e[sys] (e in single precision)
+__global__ void __launch_bounds__(NT)
+k_cvt_32_64_axpy(const z32* __restrict__ e, z64* __restrict__ x, const double* __restrict__ scale,
+                 const int* __restrict__ act, long ld, int npw) {
+  const int sys = sys_of(act, blockIdx.y);
+  const double s = scale[sys];
+  for (int i = blockIdx.x * NT + threadIdx.x; i < npw; i += gridDim.x * NT) {
+    const z64 ev = cvt<double>(e[(long)sys * ld + i]);
+    x[(long)sys * ld + i] = x[(long)sys * ld + i] + s * ev;
+  }
+}
+
+// ------------------------------------------------------------- transposes
+// [v][a][b] -> [v][b][a] with a = N*N (x,y), b = N (z); 32x32 LDS tiles.
+template <bool CONJ>
+__global__ void __launch_bounds__(NT)
+k_transpose(const z64* __restrict__ in, long ldi, z64* __restrict__ out, long ldo, int A, int B) {
+  __shared__ z64 tile[32][33];
+  const z64* src = in + (long)blockIdx.z * ldi;
+  z64* dst = out + (long)blockIdx.z * ldo;
+  const int a0 = blockIdx.x * 32, b0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int a = a0 + k, b = b0 + tx;
+    if (a < A && b < B) {
+      z64 v = src[(long)a * B + b];
+      if (CONJ) v.y = -v.y;
+      tile[k][tx] = v;
+    }
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int b = b0 + k, a = a0 + tx;
+    if (a < A && b < B) dst[(long)b * A + a] = tile[tx][k];
+  }
+}
+
+__global__ void __launch_bounds__(NT)
+k_transpose_real(const double* __restrict__ in, double* __restrict__ out, int A, int B) {
+  __shared__ double tile[32][33];
+  const int a0 = blockIdx.x * 32, b0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int a = a0 + k, b = b0 + tx;
+    if (a < A && b < B) tile[k][tx] = in[(long)a * B + b];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int b = b0 + k, a = a0 + tx;
+    if (a < A && b < B) out[(long)b * A + a] = tile[tx][k];
+  }
+}
+
+inline int blocks_for(long n) {
+  long b = (n + NT - 1) / NT;
+  return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+template <typename T>
+void launch_proj(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy, const int* act,
+                 int nsys, hipStream_t s) {
+  if (nsys <= 0 || nv <= 0) return;
+  k_proj<T><<<nsys, NT, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act);
+}
+
+template <typename T>
+void launch_cg_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw, int nsys,
+                    bool keep_x, const int* act, hipStream_t s) {
+  if (nsys <= 0) return;
+  k_cg_init<T><<<nsys, NT, 0, s>>>(v, b, ldb, bidx, npw, keep_x ? 1 : 0, act);
+}
+
+template <typename T>
+void launch_cg_step(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  k_cg_step<T><<<nsys, NT, 0, s>>>(v, npw, tol2, act);
+}
+
+template <typename T>
+void launch_sqmr_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw, int nsys,
+                      bool keep_x, const int* act, hipStream_t s) {
+  if (nsys <= 0) return;
+  k_sqmr_init<T><<<nsys, NT, 0, s>>>(v, b, ldb, bidx, npw, keep_x ? 1 : 0, act);
+}
+
+template <typename T>
+void launch_sqmr_step(const SolveVecs<T>& v, int npw, T tol, const int* act, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  k_sqmr_step<T><<<nsys, NT, 0, s>>>(v, npw, tol, act);
+}
+
+template <typename T>
+void launch_resid(const cplx<T>* b, long ldb, const int* bidx, const cplx<T>* AX, long lda, cplx<T>* R,
+                  long ldr, double* res, int npw, const int* act, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  k_resid<T><<<nsys, NT, 0, s>>>(b, ldb, bidx, AX, lda, R, ldr, res, npw, act);
+}
+
+void launch_dots(const z64* A, long lda, int m, const z64* w, long n, z64* h, z64* partial, hipStream_t s) {
+  if (m <= 0) return;
+  k_dots_partial<<<dim3(kDotBlocks, m), NT, 0, s>>>(A, lda, w, n, partial);
+  k_dots_final<<<m, 64, 0, s>>>(partial, kDotBlocks, h);
+}
+
+void launch_gemv_sub(const z64* A, long lda, int m, const z64* h, z64* w, long n, hipStream_t s) {
+  if (m <= 0) return;
+  k_gemv_sub<<<blocks_for(n), NT, 0, s>>>(A, lda, m, h, w, n);
+}
+
+void launch_lanczos_alpha(const z64* q, const z64* w, long n, double* alpha_j, z64* partial, hipStream_t s) {
+  k_dots_partial<<<dim3(kDotBlocks, 1), NT, 0, s>>>(q, 0, w, n, partial);
+  k_alpha_final<<<1, 64, 0, s>>>(partial, kDotBlocks, alpha_j);
+}
+
+void launch_lanczos_sub(z64* w, const z64* q, const z64* qprev, const double* alpha_j, const double* beta_prev,
+                        long n, hipStream_t s) {
+  k_lanczos_sub<<<blocks_for(n), NT, 0, s>>>(w, q, qprev, alpha_j, beta_prev, n);
+}
+
+void launch_norm(const z64* w, long n, double* out, z64* partial, hipStream_t s) {
+  k_dots_partial<<<dim3(kDotBlocks, 1), NT, 0, s>>>(w, 0, w, n, partial);
+  k_norm_final<<<1, 64, 0, s>>>(partial, kDotBlocks, out);
+}
+
+void launch_scale_into(const z64* w, const double* nrm, z64* q, long n, hipStream_t s) {
+  k_scale_into<<<blocks_for(n), NT, 0, s>>>(w, nrm, q, n);
+}
+
+void launch_axpby(z64* y, const z64* x, z64 a, z64 b, long n, hipStream_t s) {
+  k_axpby<<<blocks_for(n), NT, 0, s>>>(y, x, a, b, n);
+}
+
+void launch_add(z64* y, const z64* a, const z64* b, long n, hipStream_t s) {
+  k_add<<<blocks_for(n), NT, 0, s>>>(y, a, b, n);
+}
+
+void launch_finite_check(const double* x, long n, int* flag, hipStream_t s) {
+  k_finite<<<blocks_for(n), NT, 0, s>>>(x, n, flag);
+}
+
+void launch_cvt_64_32(const z64* in, z32* out, long n, hipStream_t s) {
+  k_cvt_64_32<<<blocks_for(n), NT, 0, s>>>(in, out, n);
+}
+
+void launch_cvt_32_64_axpy(const z32* e, z64* x, const double* scale, const int* act, long ld, int npw,
+                           int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  k_cvt_32_64_axpy<<<dim3((npw + NT - 1) / NT, nsys), NT, 0, s>>>(e, x, scale, act, ld, npw);
+}
+
+void launch_xyz_to_zxy(int N, const z64* in, long ldi, z64* out, long ldo, int nvec, bool conj_in,
+                       hipStream_t s) {
+  if (nvec <= 0) return;
+  const int A = N * N, B = N;
+  dim3 grid((A + 31) / 32, (B + 31) / 32, nvec);
+  if (conj_in) k_transpose<true><<<grid, NT, 0, s>>>(in, ldi, out, ldo, A, B);
+  else k_transpose<false><<<grid, NT, 0, s>>>(in, ldi, out, ldo, A, B);
+}
+
+void launch_zxy_to_xyz(int N, const z64* in, long ldi, z64* out, long ldo, int nvec, hipStream_t s) {
+  if (nvec <= 0) return;
+  const int A = N, B = N * N;
+  dim3 grid((A + 31) / 32, (B + 31) / 32, nvec);
+  k_transpose<false><<<grid, NT, 0, s>>>(in, ldi, out, ldo, A, B);
+}
+
+void launch_real_xyz_to_zxy(int N, const double* in, double* out, hipStream_t s) {
+  const int A = N * N, B = N;
+  dim3 grid((A + 31) / 32, (B + 31) / 32);
+  k_transpose_real<<<grid, NT, 0, s>>>(in, out, A, B);
+}
+
+#define LGW_INST_S(T)                                                                                  \
+  template void launch_proj<T>(const cplx<T>*, long, int, int, cplx<T>*, long, const int*, int,         \
+                               hipStream_t);                                                           \
+  template void launch_cg_init<T>(const SolveVecs<T>&, const cplx<T>*, long, const int*, int, int, bool,\
+                                  const int*, hipStream_t);                                                        \
+  template void launch_cg_step<T>(const SolveVecs<T>&, int, T, const int*, int, hipStream_t);          \
+  template void launch_sqmr_init<T>(const SolveVecs<T>&, const cplx<T>*, long, const int*, int, int,    \
+                                    bool, const int*, hipStream_t);                                                \
+  template void launch_sqmr_step<T>(const SolveVecs<T>&, int, T, const int*, int, hipStream_t);        \
+  template void launch_resid<T>(const cplx<T>*, long, const int*, const cplx<T>*, long, cplx<T>*, long, \
+                                double*, int, const int*, int, hipStream_t);
+
+LGW_INST_S(double)
+LGW_INST_S(float)
+
+}  // namespace lgw
+
+namespace lgw {
+namespace {
+// dst[didx[p]] = src[a[p]] (+ src[b[p]])
+__global__ void __launch_bounds__(256)
+k_rows_out(const z64* __restrict__ src, long lds, z64* __restrict__ dst, long ldd,
+           const int* __restrict__ didx, const int* __restrict__ a, const int* __restrict__ b, int n) {
+  const int p = blockIdx.y;
+  const z64* sa = src + (long)a[p] * lds;
+  const z64* sb = b ? src + (long)b[p] * lds : nullptr;
+  z64* d = dst + (long)didx[p] * ldd;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    z64 v = sa[i];
+    if (sb) v = v + sb[i];
+    d[i] = v;
+  }
+}
+
+// out32[sys] = in64[sys] * inv[sys]
+__global__ void __launch_bounds__(256)
+k_scale_cvt(const z64* __restrict__ in, long ldi, z32* __restrict__ out, long ldo,
+            const double* __restrict__ scale, const int* __restrict__ act, int n) {
+  const int sys = sys_of(act, blockIdx.y);
+  const double s = scale[sys];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    out[(long)sys * ldo + i] = cvt<float>(s * in[(long)sys * ldi + i]);
+}
+
+// sum_b conj(A[a]) B[b] over n for a < m, b < p: C[b][a]; one workgroup per (a-tile, b)
+__global__ void __launch_bounds__(256)
+k_gemm_hn_partial(const z64* __restrict__ A, long lda, int m, const z64* __restrict__ B, long ldb,
+                  long n, int nsplit, z64* __restrict__ partial) {
+  // grid: (nsplit, p); each workgroup handles one B row and all m A rows over a slice of n
+  __shared__ double sm[2 * 8 * 4];
+  const int bcol = blockIdx.y;
+  const long chunk = (n + nsplit - 1) / nsplit;
+  const long e0 = (long)blockIdx.x * chunk;
+  const long e1 = e0 + chunk < n ? e0 + chunk : n;
+  const z64* bb = B + (long)bcol * ldb;
+  for (int a0 = 0; a0 < m; a0 += 8) {
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    for (long e = e0 + threadIdx.x; e < e1; e += 256) {
+      const z64 bv = bb[e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (a0 + u < m) {
+          const z64 p = cmulc(A[(long)(a0 + u) * lda + e], bv);
+          acc[2 * u] += p.x;
+          acc[2 * u + 1] += p.y;
+        }
+      }
+    }
+    // block reduce 16 values
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      double s = acc[u];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if (lane == 0) sm[u * 4 + w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && a0 + (int)threadIdx.x < m) {
+      const int u = threadIdx.x;
+      const double re = sm[(2 * u) * 4 + 0] + sm[(2 * u) * 4 + 1] + sm[(2 * u) * 4 + 2] + sm[(2 * u) * 4 + 3];
+      const double im = sm[(2 * u + 1) * 4 + 0] + sm[(2 * u + 1) * 4 + 1] + sm[(2 * u + 1) * 4 + 2] +
+                        sm[(2 * u + 1) * 4 + 3];
+      partial[((long)bcol * m + a0 + u) * nsplit + blockIdx.x] = z64{re, im};
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_gemm_hn_final(const z64* __restrict__ partial, int nsplit, z64* __restrict__ C, int total) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < total) {
+    z64 s{0, 0};
+    for (int k = 0; k < nsplit; ++k) s = s + partial[(long)i * nsplit + k];
+    C[i] = s;
+  }
+}
+}  // namespace
+
+void launch_rows_out(const z64* src, long lds, z64* dst, long ldd, const int* didx, const int* a, const int* b,
+                     int n, int np, hipStream_t s) {
+  if (np <= 0) return;
+  k_rows_out<<<dim3((n + 255) / 256, np), 256, 0, s>>>(src, lds, dst, ldd, didx, a, b, n);
+}
+
+void launch_scale_cvt(const z64* in, long ldi, z32* out, long ldo, const double* scale, const int* act, int n,
+                      int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  k_scale_cvt<<<dim3((n + 255) / 256, nsys), 256, 0, s>>>(in, ldi, out, ldo, scale, act, n);
+}
+
+// C[b][a] = sum_e conj(A[a][e]) B[b][e], a < m, b < p; partial needs m*p*64 entries
+void launch_gemm_hn(const z64* A, long lda, int m, const z64* B, long ldb, int p, long n, z64* C, z64* partial,
+                    hipStream_t s) {
+  if (m <= 0 || p <= 0) return;
+  const int nsplit = 64;
+  k_gemm_hn_partial<<<dim3(nsplit, p), 256, 0, s>>>(A, lda, m, B, ldb, n, nsplit, partial);
+  k_gemm_hn_final<<<(m * p + 255) / 256, 256, 0, s>>>(partial, nsplit, C, m * p);
+}
+}  // namespace lgw

@@ -1,0 +1,123 @@
+// Host-side launchers of the lgw HIP kernels.  All pointers are device
+// pointers; every launch goes to the given stream.  Grid vectors are stored
+// plane-major ([z][x][y], "zxy"), sphere vectors in the column order of Geom,
+// z-column intermediates as [z][col].
+#pragma once
+#include "common.h"
+
+namespace lgw {
+
+constexpr int kMaxBands = 32;   // bands handled by the projector kernels
+
+bool grid_supported(int N);
+
+// ---- transforms (T = double or float) -----------------------------------
+// sphere -> columns: Tb[z][c] = scale * IFFT_z(X column c)
+template <typename T>
+void launch_zinv(const Geom& g, const cplx<T>* tw, const cplx<T>* X, long ldx,
+                 cplx<T>* Tb, long ldt, T scale, const int* act, int nsys, hipStream_t s);
+// middle pass of H: Tb <- FFT_xy(Vt[z] * IFFT_xy(Tb)) on every z plane (unscaled)
+template <typename T>
+void launch_plane_hv(const Geom& g, const cplx<T>* tw, cplx<T>* Tb, long ldt, const T* Vt,
+                     const int* act, int nsys, hipStream_t s);
+// columns -> sphere: Y = scale * FFT_z(Tb) [+ (kin - shift[sys]) X] [+ ecoef[sys] E]
+template <typename T>
+void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, T scale,
+                 const cplx<T>* X, long ldx, const cplx<T>* shift,
+                 const cplx<T>* E, long lde, const T* ecoef,
+                 cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s);
+// Tb[j*nv+v][z][c] = FFT_xy(U[v][z] * X[j][z]) at the column positions (unscaled)
+template <typename T>
+void launch_plane_pair_fwd(const Geom& g, const cplx<T>* tw, const cplx<T>* U, int nv,
+                           const cplx<T>* X, long ldx, int nj, cplx<T>* Tb, long ldt,
+                           hipStream_t s);
+// out[j][z] (+)= coef * sum_v Psi[v][z] * IFFT_xy(Tb[j*nv+v][z] placed at columns)
+template <typename T>
+void launch_plane_acc(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt,
+                      const cplx<T>* Psi, int nv, cplx<T>* out, long ldo, T coef, int nj,
+                      bool accumulate, hipStream_t s);
+// full in-place 2D transform of every z plane of nvec grid vectors
+template <typename T>
+void launch_plane_full(int N, const cplx<T>* tw, cplx<T>* G, long ldg, int nvec, int sign,
+                       hipStream_t s);
+// every z-line of nvec grid vectors: G <- IFFT_z(scale * mul * FFT_z(G))
+template <typename T>
+void launch_zfull_mul(int N, const cplx<T>* tw, cplx<T>* G, long ldg, const T* mul, T scale,
+                      int nvec, hipStream_t s);
+
+// ---- layout -------------------------------------------------------------
+// out[v][z][x][y] = (conj? conj : id)(in[v][x][y][z]) (and the inverse)
+void launch_xyz_to_zxy(int N, const z64* in, long ldi, z64* out, long ldo, int nvec, bool conj_in,
+                       hipStream_t s);
+void launch_zxy_to_xyz(int N, const z64* in, long ldi, z64* out, long ldo, int nvec,
+                       hipStream_t s);
+void launch_real_xyz_to_zxy(int N, const double* in, double* out, hipStream_t s);
+
+// ---- projector and solvers ----------------------------------------------
+// Y <- Y - Phi (Phi^H Y) for every listed system
+template <typename T>
+void launch_proj(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy,
+                 const int* act, int nsys, hipStream_t s);
+
+enum : int { FLAG_CONV = 1, FLAG_BREAK = 2, FLAG_MAXIT = 4 };
+
+template <typename T>
+struct SolveVecs {
+  cplx<T>* x; cplx<T>* r; cplx<T>* p; cplx<T>* Ap; cplx<T>* d;  // d only for SQMR
+  long ld;
+  T* rr;          // CG: r^H r      SQMR: tau
+  T* bb;          // |b|^2
+  T* theta;       // SQMR theta
+  cplx<T>* rho;   // SQMR rho
+  int* flag;
+  int* iters;
+};
+template <typename T>
+void launch_cg_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw,
+                    int nsys, bool keep_x, const int* act, hipStream_t s);
+template <typename T>
+void launch_cg_step(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, hipStream_t s);
+template <typename T>
+void launch_sqmr_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw,
+                      int nsys, bool keep_x, const int* act, hipStream_t s);
+template <typename T>
+void launch_sqmr_step(const SolveVecs<T>& v, int npw, T tol, const int* act, int nsys, hipStream_t s);
+
+// res[sys] = |b[bidx[sys]] - AX[sys]|^2, optionally R[sys] = b - AX
+template <typename T>
+void launch_resid(const cplx<T>* b, long ldb, const int* bidx, const cplx<T>* AX, long lda,
+                  cplx<T>* R, long ldr, double* res, int npw, const int* act, int nsys,
+                  hipStream_t s);
+
+// ---- BLAS-1 style helpers on long vectors --------------------------------
+// out[i*m + j]... generic dot products: h[i] = sum_e conj(A[i][e]) w[e], i < m
+void launch_dots(const z64* A, long lda, int m, const z64* w, long n, z64* h, z64* partial,
+                 hipStream_t s);
+// w -= sum_i A[i] h[i]
+void launch_gemv_sub(const z64* A, long lda, int m, const z64* h, z64* w, long n, hipStream_t s);
+// scalar Lanczos helpers (device scalars)
+void launch_lanczos_alpha(const z64* q, const z64* w, long n, double* alpha_j, z64* partial,
+                          hipStream_t s);
+void launch_lanczos_sub(z64* w, const z64* q, const z64* qprev, const double* alpha_j,
+                        const double* beta_prev, long n, hipStream_t s);
+void launch_norm(const z64* w, long n, double* out, z64* partial, hipStream_t s);
+void launch_scale_into(const z64* w, const double* nrm, z64* q, long n, hipStream_t s);
+void launch_axpby(z64* y, const z64* x, z64 a, z64 b, long n, hipStream_t s);
+void launch_add(z64* y, const z64* a, const z64* b, long n, hipStream_t s);
+// any non-finite value -> *flag = 1
+void launch_finite_check(const double* x, long n, int* flag, hipStream_t s);
+// mixed precision conversions
+void launch_cvt_64_32(const z64* in, z32* out, long n, hipStream_t s);
+void launch_cvt_32_64_axpy(const z32* e, z64* x, const double* scale, const int* sys_of_vec,
+                           long ld, int npw, int nsys, hipStream_t s);
+
+}  // namespace lgw
+
+namespace lgw {
+void launch_rows_out(const z64* src, long lds, z64* dst, long ldd, const int* didx, const int* a, const int* b,
+                     int n, int np, hipStream_t s);
+void launch_scale_cvt(const z64* in, long ldi, z32* out, long ldo, const double* scale, const int* act, int n,
+                      int nsys, hipStream_t s);
+void launch_gemm_hn(const z64* A, long lda, int m, const z64* B, long ldb, int p, long n, z64* C, z64* partial,
+                    hipStream_t s);
+}  // namespace lgw

@@ -1,0 +1,1077 @@
+// Host side of the lgw library: context set-up, batched Sternheimer solves,
+// chi0 application, Lanczos and projection (C ABI in include/lgw.h).
+#include "lgw.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace lgw;
+
+namespace {
+
+struct Fail {
+  lgw_status st;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      throw Fail{e_ == hipErrorOutOfMemory ? LGW_ENOMEM : LGW_EDEVICE,                     \
+                 std::string(#x) + ": " + hipGetErrorString(e_)};                          \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void ensure(size_t bytes) {
+    if (bytes <= n && p) return;
+    release();
+    HIPCHK(hipMalloc(&p, bytes < 256 ? 256 : bytes));
+    n = bytes < 256 ? 256 : bytes;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+enum Kind { K_CGLIN = 0, K_CGSQ = 1, K_SQMR = 2 };
+
+}  // namespace
+
+struct lgw_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  lgw_opts opts{};
+  double L[3] = {0, 0, 0};
+  int N = 0;
+  long n3 = 0;
+  double ecut = 0, omega = 0, dV = 0;
+  int nv = 0, npw = 0, ncols = 0, hx = 0, hy = 0;
+  std::vector<int> m, col_start, col_h, col_pos;
+  std::vector<double> kin, eps;
+  DevBuf d_col_start, d_col_h, d_col_pos, d_kin, d_Vt, d_Vt32, d_sqrtv, d_tw64, d_tw32, d_psi, d_u, d_Phi,
+      d_Phi32;
+  Geom geom{};
+  std::map<std::string, DevBuf> ws;
+  std::vector<int> st_iters, st_flags, st_sweeps;
+  std::vector<double> st_res;
+  long long tot_iters = 0, tot_h = 0;
+  std::string err;
+
+  template <class T>
+  T* buf(const std::string& name, size_t count) {
+    DevBuf& b = ws[name];
+    b.ensure(count * sizeof(T));
+    return b.as<T>();
+  }
+  void sync() { HIPCHK(hipStreamSynchronize(stream)); }
+  void check_launch() { HIPCHK(hipGetLastError()); }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- helpers
+template <class T>
+const cplx<T>* tw_of(lgw_ctx* c);
+template <> const z64* tw_of<double>(lgw_ctx* c) { return c->d_tw64.as<z64>(); }
+template <> const z32* tw_of<float>(lgw_ctx* c) { return c->d_tw32.as<z32>(); }
+template <class T>
+const T* vt_of(lgw_ctx* c);
+template <> const double* vt_of<double>(lgw_ctx* c) { return c->d_Vt.as<double>(); }
+template <> const float* vt_of<float>(lgw_ctx* c) { return c->d_Vt32.as<float>(); }
+template <class T>
+const cplx<T>* phi_of(lgw_ctx* c);
+template <> const z64* phi_of<double>(lgw_ctx* c) { return c->d_Phi.as<z64>(); }
+template <> const z32* phi_of<float>(lgw_ctx* c) { return c->d_Phi32.as<z32>(); }
+
+// host -> device copy that has finished reading the host buffer on return
+void h2d(lgw_ctx* c, void* dst, const void* src, size_t bytes) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+template <class T>
+void upload(lgw_ctx* c, DevBuf& b, const std::vector<T>& h) {
+  b.ensure(h.size() * sizeof(T));
+  h2d(c, b.p, h.data(), h.size() * sizeof(T));
+}
+
+// y = (H - shift) x [+ ecoef E] for nsys systems (device per-system arrays)
+template <class T>
+void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const cplx<T>* shift,
+            const cplx<T>* E, long lde, const T* ecoef, cplx<T>* Tb, const int* act, int nsys) {
+  const long ldt = (long)c->N * c->ncols;
+  launch_zinv<T>(c->geom, tw_of<T>(c), X, ldx, Tb, ldt, T(1), act, nsys, c->stream);
+  launch_plane_hv<T>(c->geom, tw_of<T>(c), Tb, ldt, vt_of<T>(c), act, nsys, c->stream);
+  launch_zfwd<T>(c->geom, tw_of<T>(c), Tb, ldt, T(1.0 / (double)c->n3), X, ldx, shift, E, lde, ecoef, Y, ldy,
+                 act, nsys, c->stream);
+  c->tot_h += nsys;
+}
+
+template <class T>
+void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
+  launch_proj<T>(phi_of<T>(c), c->npw, c->nv, c->npw, Y, ldy, act, nsys, c->stream);
+}
+
+// Y = A X for the projected operator of the given kind (X is in range(P_c)).
+template <class T>
+void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, cplx<T>* Tb, long ld,
+              const cplx<T>* shift, const T* w2, const int* act, int nsys) {
+  if (kind == K_CGSQ) {
+    happly<T>(c, X, ld, tmp, ld, shift, nullptr, 0, nullptr, Tb, act, nsys);
+    proj<T>(c, tmp, ld, act, nsys);
+    happly<T>(c, tmp, ld, Y, ld, shift, X, ld, w2, Tb, act, nsys);
+  } else {
+    happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys);
+  }
+  proj<T>(c, Y, ld, act, nsys);
+}
+
+// Batched Krylov state for one precision.
+template <class T>
+struct Batch {
+  int kind = 0, nsys = 0;
+  long ld = 0;
+  SolveVecs<T> v{};
+  cplx<T>* tmp = nullptr;
+  cplx<T>* Tb = nullptr;
+  cplx<T>* shift = nullptr;
+  T* w2 = nullptr;
+  int* act = nullptr;
+  std::vector<int> h_iters, h_flags;
+};
+
+template <class T>
+Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::vector<cplx<T>>& shift,
+                    const std::vector<T>& w2) {
+  Batch<T> b;
+  b.kind = kind;
+  b.nsys = nsys;
+  b.ld = c->npw;
+  const size_t nv = (size_t)nsys * b.ld;
+  const std::string t(tag);
+  b.v.x = c->buf<cplx<T>>(t + ".x", nv);
+  b.v.r = c->buf<cplx<T>>(t + ".r", nv);
+  b.v.p = c->buf<cplx<T>>(t + ".p", nv);
+  b.v.Ap = c->buf<cplx<T>>(t + ".Ap", nv);
+  b.v.d = kind == K_SQMR ? c->buf<cplx<T>>(t + ".d", nv) : nullptr;
+  b.tmp = kind == K_CGSQ ? c->buf<cplx<T>>(t + ".tmp", nv) : nullptr;
+  b.Tb = c->buf<cplx<T>>(t + ".Tb", (size_t)nsys * c->N * c->ncols);
+  b.v.ld = b.ld;
+  b.v.rr = c->buf<T>(t + ".rr", nsys);
+  b.v.bb = c->buf<T>(t + ".bb", nsys);
+  b.v.theta = c->buf<T>(t + ".th", nsys);
+  b.v.rho = c->buf<cplx<T>>(t + ".rho", nsys);
+  b.v.flag = c->buf<int>(t + ".flag", nsys);
+  b.v.iters = c->buf<int>(t + ".iters", nsys);
+  b.shift = c->buf<cplx<T>>(t + ".shift", nsys);
+  b.w2 = c->buf<T>(t + ".w2", nsys);
+  b.act = c->buf<int>(t + ".act", nsys);
+  h2d(c, b.shift, shift.data(), nsys * sizeof(cplx<T>));
+  std::vector<T> w(w2);
+  w.resize(nsys, T(0));
+  h2d(c, b.w2, w.data(), nsys * sizeof(T));
+  b.h_iters.assign(nsys, 0);
+  b.h_flags.assign(nsys, 0);
+  return b;
+}
+
+// Iterate the listed systems of a batch from (re)initialisation with rhs B[bidx]
+// until every one is converged, broken down or at max_iter.
+template <class T>
+void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* bidx_dev, bool keep_x, double tol,
+               const std::vector<int>& start) {
+  std::vector<int> act(start);
+  if (act.empty()) return;
+  const int npw = c->npw;
+  h2d(c, b.act, act.data(), act.size() * sizeof(int));
+  if (b.kind == K_SQMR)
+    launch_sqmr_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream);
+  else
+    launch_cg_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream);
+  c->check_launch();
+  const int check = std::max(1, c->opts.check_every);
+  const int maxit = std::max(1, c->opts.max_iter);
+  std::vector<int> flags(b.nsys), iters(b.nsys);
+  int it = 0;
+  while (!act.empty()) {
+    // drop systems converged at initialisation or in the last chunk
+    HIPCHK(hipMemcpyAsync(flags.data(), b.v.flag, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    std::vector<int> next;
+    for (int s : act)
+      if (!flags[s]) next.push_back(s);
+    act.swap(next);
+    if (act.empty() || it >= maxit) break;
+    h2d(c, b.act, act.data(), act.size() * sizeof(int));
+    const int chunk = std::min(check, maxit - it);
+    const int na = (int)act.size();
+    for (int k = 0; k < chunk; ++k) {
+      apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na);
+      if (b.kind == K_SQMR)
+        launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
+      else
+        launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
+    }
+    c->check_launch();
+    it += chunk;
+  }
+  HIPCHK(hipMemcpyAsync(flags.data(), b.v.flag, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(iters.data(), b.v.iters, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  for (int s : start) {
+    b.h_flags[s] = flags[s] ? flags[s] : FLAG_MAXIT;
+    b.h_iters[s] = iters[s];
+  }
+}
+
+struct SolveOut {
+  std::vector<int> iters, flags, sweeps;
+  std::vector<double> rel;
+};
+
+// Solve A_s x_s = B[bidx[s]] for s < nsys in FP64 (true-residual restarts) or
+// mixed precision (FP32 inner Krylov solves inside FP64 iterative refinement).
+// X receives the solutions [nsys][npw].
+void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, const std::vector<z64>& shift,
+           const std::vector<double>& w2, z64* X, SolveOut& out) {
+  const int nsys = (int)bidx.size();
+  const int npw = c->npw;
+  const double tol = c->opts.tol;
+  out.iters.assign(nsys, 0);
+  out.flags.assign(nsys, 0);
+  out.sweeps.assign(nsys, 0);
+  out.rel.assign(nsys, 0.0);
+  int* d_bidx = c->buf<int>("sv.bidx", nsys);
+  h2d(c, d_bidx, bidx.data(), nsys * sizeof(int));
+  z64* R = c->buf<z64>("sv.R", (size_t)nsys * npw);
+  z64* AX = c->buf<z64>("sv.AX", (size_t)nsys * npw);
+  z64* tmp = c->buf<z64>("sv.tmp", kind == K_CGSQ ? (size_t)nsys * npw : 1);
+  z64* Tb = c->buf<z64>("sv.Tb", (size_t)nsys * c->N * c->ncols);
+  double* res = c->buf<double>("sv.res", nsys);
+  double* bb = c->buf<double>("sv.bb", nsys);
+  z64* d_shift = c->buf<z64>("sv.shift", nsys);
+  double* d_w2 = c->buf<double>("sv.w2", nsys);
+  int* d_act = c->buf<int>("sv.act", nsys);
+  h2d(c, d_shift, shift.data(), nsys * sizeof(z64));
+  std::vector<double> w2v(w2);
+  w2v.resize(nsys, 0.0);
+  h2d(c, d_w2, w2v.data(), nsys * sizeof(double));
+  std::vector<int> all(nsys);
+  for (int s = 0; s < nsys; ++s) all[s] = s;
+  h2d(c, d_act, all.data(), nsys * sizeof(int));
+  // |b|^2 per system
+  std::vector<double> h_bb(nsys), h_res(nsys);
+  {
+    // res = |B - 0|^2 computed with a zero AX
+    HIPCHK(hipMemsetAsync(AX, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
+    launch_resid<double>(B, npw, d_bidx, AX, npw, nullptr, 0, bb, npw, d_act, nsys, c->stream);
+    HIPCHK(hipMemcpyAsync(h_bb.data(), bb, nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+  }
+  // true residual R = B - A X over the listed systems; returns rel. residuals
+  auto true_resid = [&](const std::vector<int>& lst) {
+    if (lst.empty()) return;
+    h2d(c, d_act, lst.data(), lst.size() * sizeof(int));
+    apply_op<double>(c, kind, X, AX, tmp, Tb, npw, d_shift, d_w2, d_act, (int)lst.size());
+    launch_resid<double>(B, npw, d_bidx, AX, npw, R, npw, res, npw, d_act, (int)lst.size(), c->stream);
+    HIPCHK(hipMemcpyAsync(h_res.data(), res, nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    for (int s : lst) out.rel[s] = h_bb[s] > 0 ? std::sqrt(h_res[s] / h_bb[s]) : 0.0;
+  };
+
+  if (c->opts.precision == LGW_FP64) {
+    std::vector<z64> sh(shift);
+    sh.resize(nsys);
+    std::vector<double> w(w2v);
+    Batch<double> b = make_batch<double>(c, "b64", kind, nsys, sh, w);
+    // solve into the batch's x, then refine by restarts on the true residual
+    run_batch<double>(c, b, B, npw, d_bidx, false, tol, all);
+    HIPCHK(hipMemcpyAsync(X, b.v.x, (size_t)nsys * npw * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    std::vector<int> lst = all;
+    for (int restart = 0; restart < 3; ++restart) {
+      true_resid(lst);
+      std::vector<int> bad;
+      for (int s : lst)
+        if (out.rel[s] > tol && b.h_flags[s] != FLAG_BREAK) bad.push_back(s);
+      if (bad.empty()) break;
+      // restart from x with the true residual: b.v.x already holds X
+      h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
+      run_batch<double>(c, b, R, npw, nullptr, true, tol, bad);
+      HIPCHK(hipMemcpyAsync(X, b.v.x, (size_t)nsys * npw * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+      lst = bad;
+    }
+    for (int s = 0; s < nsys; ++s) {
+      out.iters[s] = b.h_iters[s];
+      int f = b.h_flags[s];
+      if (out.rel[s] > 10 * tol && f == FLAG_CONV) f = FLAG_MAXIT;
+      out.flags[s] = f;
+      out.sweeps[s] = 1;
+    }
+  } else {
+    // mixed precision: X = 0, R = B
+    HIPCHK(hipMemsetAsync(X, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
+    launch_rows_out(B, npw, R, npw, d_act /*identity rows*/, d_bidx, nullptr, npw, nsys, c->stream);
+    for (int s = 0; s < nsys; ++s) {
+      h_res[s] = h_bb[s];
+      out.rel[s] = h_bb[s] > 0 ? 1.0 : 0.0;
+    }
+    std::vector<cplx<float>> sh32(nsys);
+    std::vector<float> w32(nsys);
+    for (int s = 0; s < nsys; ++s) {
+      sh32[s] = cplx<float>{(float)shift[s].x, (float)shift[s].y};
+      w32[s] = (float)w2v[s];
+    }
+    Batch<float> b = make_batch<float>(c, "b32", kind, nsys, sh32, w32);
+    double* rs = c->buf<double>("sv.rs", nsys);
+    double* irs = c->buf<double>("sv.irs", nsys);
+    z32* R32 = c->buf<z32>("sv.R32", (size_t)nsys * npw);
+    std::vector<double> h_rs(nsys), h_irs(nsys);
+    const double inner = std::max(c->opts.inner_tol, 1e-7);
+    std::vector<int> lst = all;
+    for (int sweep = 0; sweep < std::max(1, c->opts.max_sweeps); ++sweep) {
+      std::vector<int> bad;
+      for (int s : lst)
+        if (out.rel[s] > tol && out.flags[s] != FLAG_BREAK) bad.push_back(s);
+      if (bad.empty()) break;
+      for (int s : bad) {
+        h_rs[s] = std::sqrt(h_res[s]);
+        h_irs[s] = h_rs[s] > 0 ? 1.0 / h_rs[s] : 0.0;
+        out.sweeps[s] += 1;
+      }
+      h2d(c, rs, h_rs.data(), nsys * sizeof(double));
+      h2d(c, irs, h_irs.data(), nsys * sizeof(double));
+      h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
+      launch_scale_cvt(R, npw, R32, npw, irs, d_act, npw, (int)bad.size(), c->stream);
+      run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad);
+      h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
+      launch_cvt_32_64_axpy(b.v.x, X, rs, d_act, npw, npw, (int)bad.size(), c->stream);
+      true_resid(bad);
+      for (int s : bad) {
+        out.iters[s] += b.h_iters[s];
+        if (b.h_flags[s] == FLAG_BREAK && out.rel[s] > tol) out.flags[s] = FLAG_BREAK;
+      }
+      lst = bad;
+    }
+    for (int s = 0; s < nsys; ++s)
+      if (out.flags[s] != FLAG_BREAK) out.flags[s] = out.rel[s] <= 10 * tol ? FLAG_CONV : FLAG_MAXIT;
+  }
+  for (int s = 0; s < nsys; ++s) c->tot_iters += out.iters[s];
+}
+
+// ---------------------------------------------------------------- v^1/2
+// in-place on zxy grid vectors: G <- scale_sign * v^1/2 G
+void vhalf_inplace(lgw_ctx* c, z64* G, int n, double sign) {
+  launch_plane_full<double>(c->N, c->d_tw64.as<z64>(), G, c->n3, n, -1, c->stream);
+  launch_zfull_mul<double>(c->N, c->d_tw64.as<z64>(), G, c->n3, c->d_sqrtv.as<double>(), sign / (double)c->n3, n,
+                           c->stream);
+  launch_plane_full<double>(c->N, c->d_tw64.as<z64>(), G, c->n3, n, +1, c->stream);
+}
+
+// ---------------------------------------------------------------- chi0
+// out[z][j] = chi0(z) X[j] on zxy grid vectors.
+lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c128* zl, z64* out, long ldz) {
+  const int nv = c->nv, npw = c->npw;
+  const long n3 = c->n3;
+  const int nb = nrhs * nv;                 // (j, v) pairs, index j*nv + v
+  const long ldt = (long)c->N * c->ncols;
+  c->st_iters.clear();
+  c->st_flags.clear();
+  c->st_sweeps.clear();
+  c->st_res.clear();
+  // right-hand sides b_{j,v} = P_c Gather(conj(psi_v) x_j)
+  z64* Tb = c->buf<z64>("c.Tb", (size_t)nb * ldt);
+  z64* B0 = c->buf<z64>("c.B0", (size_t)nb * npw);     // b
+  z64* B2 = c->buf<z64>("c.B2", (size_t)nb * npw);     // 2 b
+  launch_plane_pair_fwd<double>(c->geom, c->d_tw64.as<z64>(), c->d_u.as<z64>(), nv, X, n3, nrhs, Tb, ldt, c->stream);
+  launch_zfwd<double>(c->geom, c->d_tw64.as<z64>(), Tb, ldt, std::sqrt(c->omega) / (double)n3, nullptr, 0, nullptr,
+                      nullptr, 0, nullptr, B0, npw, nullptr, nb, c->stream);
+  proj<double>(c, B0, npw, nullptr, nb);
+  launch_add(B2, B0, B0, (long)nb * npw, c->stream);
+  bool any_imag = false;
+  for (int k = 0; k < nz; ++k)
+    if (zl[k].re == 0.0 && zl[k].im != 0.0) any_imag = true;
+  z64* B1 = nullptr;   // 2 P (H - e_v) b
+  std::vector<z64> eps_shift(nb);
+  for (int p = 0; p < nb; ++p) eps_shift[p] = z64{c->eps[p % nv], 0.0};
+  if (any_imag) {
+    B1 = c->buf<z64>("c.B1", (size_t)nb * npw);
+    z64* d_sh = c->buf<z64>("c.sh", nb);
+    h2d(c, d_sh, eps_shift.data(), nb * sizeof(z64));
+    happly<double>(c, B2, npw, B1, npw, d_sh, nullptr, 0, nullptr, Tb, nullptr, nb);
+    proj<double>(c, B1, npw, nullptr, nb);
+  }
+  c->check_launch();
+  // solutions f[z][j*nv+v]
+  z64* F = c->buf<z64>("c.F", (size_t)nz * nb * npw);
+  // systems by kind
+  struct Sys { int z, p, sign; };
+  std::vector<Sys> lin, sq, qm;
+  for (int k = 0; k < nz; ++k) {
+    for (int p = 0; p < nb; ++p) {
+      if (zl[k].re == 0.0 && zl[k].im == 0.0) lin.push_back({k, p, 0});
+      else if (zl[k].re == 0.0) sq.push_back({k, p, 0});
+      else {
+        qm.push_back({k, p, -1});
+        qm.push_back({k, p, +1});
+      }
+    }
+  }
+  // per-system workspace in bytes (FP64 vectors, FP32 state in mixed mode)
+  const double vec = 16.0 * npw, tb = 16.0 * ldt;
+  const double per = 10 * vec + 2 * tb;
+  const double budget = std::max(0.25, c->opts.mem_budget_gb) * 1e9;
+  const int cap = std::max(2, (int)std::min(1e6, budget / per)) & ~1;
+  lgw_status st = LGW_OK;
+  auto run_kind = [&](int kind, const std::vector<Sys>& sy) {
+    for (size_t s0 = 0; s0 < sy.size(); s0 += cap) {
+      const int n = (int)std::min<size_t>(cap, sy.size() - s0);
+      std::vector<int> bidx(n);
+      std::vector<z64> sh(n);
+      std::vector<double> w2(n, 0.0);
+      for (int i = 0; i < n; ++i) {
+        const Sys& q = sy[s0 + i];
+        const double e = c->eps[q.p % nv];
+        bidx[i] = q.p;
+        if (kind == K_SQMR) sh[i] = z64{e + q.sign * zl[q.z].re, q.sign * zl[q.z].im};
+        else sh[i] = z64{e, 0.0};
+        if (kind == K_CGSQ) w2[i] = zl[q.z].im * zl[q.z].im;
+      }
+      const z64* B = kind == K_CGLIN ? B2 : (kind == K_CGSQ ? B1 : B0);
+      z64* Xs = c->buf<z64>("c.Xs", (size_t)n * npw);
+      SolveOut so;
+      solve(c, kind, B, bidx, sh, w2, Xs, so);
+      // write f into F
+      std::vector<int> didx, a, b;
+      if (kind == K_SQMR) {
+        for (int i = 0; i < n; i += 2) {
+          didx.push_back(sy[s0 + i].z * nb + sy[s0 + i].p);
+          a.push_back(i);
+          b.push_back(i + 1);
+        }
+      } else {
+        for (int i = 0; i < n; ++i) {
+          didx.push_back(sy[s0 + i].z * nb + sy[s0 + i].p);
+          a.push_back(i);
+        }
+      }
+      const int np = (int)didx.size();
+      int* d_idx = c->buf<int>("c.idx", 3 * (size_t)np);
+      std::vector<int> all(didx);
+      all.insert(all.end(), a.begin(), a.end());
+      all.insert(all.end(), b.begin(), b.end());
+      h2d(c, d_idx, all.data(), all.size() * sizeof(int));
+      launch_rows_out(Xs, npw, F, npw, d_idx, d_idx + np, kind == K_SQMR ? d_idx + 2 * np : nullptr, npw, np,
+                      c->stream);
+      c->sync();
+      for (int i = 0; i < n; ++i) {
+        c->st_iters.push_back(so.iters[i]);
+        c->st_flags.push_back(so.flags[i]);
+        c->st_sweeps.push_back(so.sweeps[i]);
+        c->st_res.push_back(so.rel[i]);
+        if (so.flags[i] == FLAG_BREAK) st = LGW_EBREAKDOWN;
+        else if (so.flags[i] != FLAG_CONV && st == LGW_OK) st = LGW_ENOCONV;
+      }
+    }
+  };
+  run_kind(K_CGLIN, lin);
+  run_kind(K_CGSQ, sq);
+  run_kind(K_SQMR, qm);
+  // dn_j(z) = -2 sum_v psi_v Scatter(f_{j,v}(z))
+  for (int k = 0; k < nz; ++k) {
+    launch_zinv<double>(c->geom, c->d_tw64.as<z64>(), F + (size_t)k * nb * npw, npw, Tb, ldt, 1.0, nullptr, nb,
+                        c->stream);
+    launch_plane_acc<double>(c->geom, c->d_tw64.as<z64>(), Tb, ldt, c->d_psi.as<z64>(), nv, out + (size_t)k * ldz,
+                             n3, -2.0 / std::sqrt(c->omega), nrhs, false, c->stream);
+  }
+  c->check_launch();
+  return st;
+}
+
+lgw_status worst(lgw_status a, lgw_status b) {
+  if (a == LGW_EBREAKDOWN || b == LGW_EBREAKDOWN) return LGW_EBREAKDOWN;
+  if (a == LGW_ENOCONV || b == LGW_ENOCONV) return LGW_ENOCONV;
+  return LGW_OK;
+}
+
+// stage a user array on the device (copy when the context works on host memory)
+const void* stage_in(lgw_ctx* c, const void* user, size_t bytes, const char* name) {
+  if (c->opts.mem == LGW_MEM_DEVICE) return user;
+  void* d = c->buf<char>(name, bytes);
+  h2d(c, d, user, bytes);
+  return d;
+}
+void* stage_out(lgw_ctx* c, void* user, size_t bytes, const char* name) {
+  if (c->opts.mem == LGW_MEM_DEVICE) return user;
+  return c->buf<char>(name, bytes);
+}
+void finish_out(lgw_ctx* c, void* user, const void* dev, size_t bytes) {
+  if (c->opts.mem == LGW_MEM_DEVICE) return;
+  HIPCHK(hipMemcpyAsync(user, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+}
+
+lgw_status set_err(lgw_ctx* c, lgw_status st, const std::string& m) {
+  if (c) c->err = m;
+  return st;
+}
+
+thread_local std::string g_setup_err;
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+void lgw_default_opts(lgw_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = LGW_FP64;
+  o->tol = 1e-13;
+  o->max_iter = 5000;
+  o->check_every = 8;
+  o->precond = 0;
+  o->deterministic = 1;
+  o->mem = LGW_MEM_DEVICE;
+  o->stream = nullptr;
+  o->mem_budget_gb = 16.0;
+  o->inner_tol = 1e-5;
+  o->max_sweeps = 8;
+}
+
+lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], double ecut, const double* V_loc,
+                     int n_v, const lgw_c128* psi_v, const double* eps_v, const lgw_opts* opts) {
+  if (!out) return LGW_EINVAL;
+  *out = nullptr;
+  lgw_opts o;
+  lgw_default_opts(&o);
+  if (opts) o = *opts;
+  auto bad = [&](const std::string& m) {
+    g_setup_err = m;
+    return LGW_EINVAL;
+  };
+  if (!cell || !grid || !V_loc || !psi_v || !eps_v) return bad("null argument");
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (i != j && cell[3 * i + j] != 0.0) return bad("cell must be orthorhombic (diagonal)");
+  for (int i = 0; i < 3; ++i)
+    if (!(cell[4 * i] > 0.0) || !std::isfinite(cell[4 * i])) return bad("cell lengths must be positive");
+  if (grid[0] != grid[1] || grid[1] != grid[2]) return bad("grid must be cubic (N, N, N)");
+  if (!grid_supported(grid[0])) return bad("grid N must be one of 16, 24, 32, 40, 48, 64, 72");
+  if (!(ecut > 0.0) || !std::isfinite(ecut)) return bad("ecut must be positive");
+  if (n_v < 1 || n_v > kMaxBands) return bad("n_v must be in 1..32");
+  for (int v = 0; v < n_v; ++v) {
+    if (!std::isfinite(eps_v[v])) { g_setup_err = "non-finite eps_v"; return LGW_ENAN; }
+    if (v > 0 && eps_v[v] < eps_v[v - 1]) return bad("eps_v must be ascending");
+  }
+  if (!(o.tol > 0.0) || o.max_iter < 1 || o.check_every < 1) return bad("invalid solver options");
+  if (o.precision != LGW_FP64 && o.precision != LGW_MIXED) return bad("invalid precision");
+  if (o.precond != 0) return bad("precond must be 0");
+  if (o.mem != LGW_MEM_DEVICE && o.mem != LGW_MEM_HOST) return bad("invalid mem mode");
+  const int N = grid[0];
+  const long n3 = (long)N * N * N;
+  if (o.mem == LGW_MEM_HOST) {
+    for (long i = 0; i < n3; ++i)
+      if (!std::isfinite(V_loc[i])) { g_setup_err = "non-finite V_loc"; return LGW_ENAN; }
+    for (long i = 0; i < n3 * n_v; ++i)
+      if (!std::isfinite(psi_v[i].re) || !std::isfinite(psi_v[i].im)) { g_setup_err = "non-finite psi_v"; return LGW_ENAN; }
+  }
+  // plane-wave sphere in lexicographic (mx, my, mz) order
+  const double L[3] = {cell[0], cell[4], cell[8]};
+  const double g0[3] = {2 * M_PI / L[0], 2 * M_PI / L[1], 2 * M_PI / L[2]};
+  const int hmax = N / 2 - 1;
+  std::vector<int> m, col_start, col_h, col_pos;
+  std::vector<double> kin;
+  int hx = 0, hy = 0;
+  const int lim = N;  // search range beyond the grid to detect overflow
+  for (int mx = -lim; mx <= lim; ++mx)
+    for (int my = -lim; my <= lim; ++my) {
+      const double exy = 0.5 * (std::pow(g0[0] * mx, 2) + std::pow(g0[1] * my, 2));
+      if (exy > ecut) continue;
+      int h = 0;
+      while (0.5 * std::pow(g0[2] * (h + 1), 2) + exy <= ecut) ++h;
+      if (std::abs(mx) > hmax || std::abs(my) > hmax || h > hmax)
+        return bad("plane-wave sphere does not fit the grid (max|m_i| must be <= N/2-1)");
+      col_start.push_back((int)kin.size());
+      col_h.push_back(h);
+      col_pos.push_back(((mx + N) % N) * N + ((my + N) % N));
+      hx = std::max(hx, std::abs(mx));
+      hy = std::max(hy, std::abs(my));
+      for (int mz = -h; mz <= h; ++mz) {
+        m.push_back(mx);
+        m.push_back(my);
+        m.push_back(mz);
+        kin.push_back(exy + 0.5 * std::pow(g0[2] * mz, 2));
+      }
+    }
+  if (kin.size() <= (size_t)n_v) return bad("plane-wave sphere smaller than the valence set");
+
+  std::unique_ptr<lgw_ctx> c(new lgw_ctx);
+  try {
+    c->opts = o;
+    HIPCHK(hipGetDevice(&c->device));
+    if (o.stream) c->stream = (hipStream_t)o.stream;
+    else {
+      HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    c->L[0] = L[0]; c->L[1] = L[1]; c->L[2] = L[2];
+    c->N = N;
+    c->n3 = n3;
+    c->ecut = ecut;
+    c->omega = L[0] * L[1] * L[2];
+    c->dV = c->omega / (double)n3;
+    c->nv = n_v;
+    c->npw = (int)kin.size();
+    c->ncols = (int)col_start.size();
+    c->hx = hx;
+    c->hy = hy;
+    c->m = m;
+    c->col_start = col_start;
+    c->col_h = col_h;
+    c->col_pos = col_pos;
+    c->kin = kin;
+    c->eps.assign(eps_v, eps_v + n_v);
+    upload(c.get(), c->d_col_start, col_start);
+    upload(c.get(), c->d_col_h, col_h);
+    upload(c.get(), c->d_col_pos, col_pos);
+    upload(c.get(), c->d_kin, kin);
+    c->geom = Geom{N, c->npw, c->ncols, hx, hy, c->d_col_start.as<int>(), c->d_col_h.as<int>(),
+                   c->d_col_pos.as<int>(), c->d_kin.as<double>()};
+    // twiddles exp(-2 pi i j / N)
+    std::vector<z64> tw(N);
+    std::vector<z32> tw32(N);
+    for (int j = 0; j < N; ++j) {
+      const double a = 2.0 * M_PI * (double)j / (double)N;
+      tw[j] = z64{std::cos(a), -std::sin(a)};
+      tw32[j] = z32{(float)tw[j].x, (float)tw[j].y};
+    }
+    upload(c.get(), c->d_tw64, tw);
+    upload(c.get(), c->d_tw32, tw32);
+    // truncated Coulomb square root on the zxy grid
+    {
+      const double R = 0.5 * std::min(L[0], std::min(L[1], L[2]));
+      std::vector<double> s(n3);
+      for (int z = 0; z < N; ++z)
+        for (int x = 0; x < N; ++x)
+          for (int y = 0; y < N; ++y) {
+            const int fx = x <= N / 2 - (N % 2 == 0 ? 1 : 0) ? x : x - N;
+            const int fy = y <= N / 2 - (N % 2 == 0 ? 1 : 0) ? y : y - N;
+            const int fz = z <= N / 2 - (N % 2 == 0 ? 1 : 0) ? z : z - N;
+            // signed FFT frequencies: 0..N/2-1, -N/2..-1
+            const double kx = g0[0] * fx, ky = g0[1] * fy, kz = g0[2] * fz;
+            const double k2 = kx * kx + ky * ky + kz * kz;
+            double v;
+            if (k2 == 0.0) v = 2.0 * M_PI * R * R;
+            else v = 4.0 * M_PI * (1.0 - std::cos(std::sqrt(k2) * R)) / k2;
+            s[(long)z * N * N + (long)x * N + y] = std::sqrt(v);
+          }
+      upload(c.get(), c->d_sqrtv, s);
+    }
+    lgw_ctx* cp = c.get();
+    // potential
+    const double* dVloc = static_cast<const double*>(stage_in(cp, V_loc, n3 * sizeof(double), "in.V"));
+    int* d_flag = cp->buf<int>("flag", 1);
+    HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), cp->stream));
+    launch_finite_check(dVloc, n3, d_flag, cp->stream);
+    c->d_Vt.ensure(n3 * sizeof(double));
+    launch_real_xyz_to_zxy(N, dVloc, c->d_Vt.as<double>(), cp->stream);
+    {
+      std::vector<double> hv(n3);
+      HIPCHK(hipMemcpyAsync(hv.data(), c->d_Vt.p, n3 * sizeof(double), hipMemcpyDeviceToHost, cp->stream));
+      cp->sync();
+      std::vector<float> hf(n3);
+      for (long i = 0; i < n3; ++i) hf[i] = (float)hv[i];
+      upload(cp, c->d_Vt32, hf);
+    }
+    // orbitals
+    const z64* dpsi = static_cast<const z64*>(stage_in(cp, psi_v, (size_t)n_v * n3 * sizeof(z64), "in.psi"));
+    launch_finite_check(reinterpret_cast<const double*>(dpsi), 2 * n3 * n_v, d_flag, cp->stream);
+    c->d_psi.ensure((size_t)n_v * n3 * sizeof(z64));
+    c->d_u.ensure((size_t)n_v * n3 * sizeof(z64));
+    launch_xyz_to_zxy(N, dpsi, n3, c->d_psi.as<z64>(), n3, n_v, false, cp->stream);
+    launch_xyz_to_zxy(N, dpsi, n3, c->d_u.as<z64>(), n3, n_v, true, cp->stream);
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, d_flag, sizeof(int), hipMemcpyDeviceToHost, cp->stream));
+    cp->sync();
+    if (hflag) {
+      g_setup_err = "non-finite V_loc or psi_v";
+      return LGW_ENAN;
+    }
+    // Phi = Gather(conj(psi_v)) via the pair transform with a unit potential
+    const int npw = c->npw;
+    const long ldt = (long)N * c->ncols;
+    {
+      z64* ones = cp->buf<z64>("tmp.ones", n3);
+      std::vector<z64> h1(n3, z64{1.0, 0.0});
+      h2d(cp, ones, h1.data(), n3 * sizeof(z64));
+      z64* Tb = cp->buf<z64>("tmp.Tb", (size_t)n_v * ldt);
+      c->d_Phi.ensure((size_t)n_v * npw * sizeof(z64));
+      launch_plane_pair_fwd<double>(c->geom, c->d_tw64.as<z64>(), c->d_u.as<z64>(), n_v, ones, n3, 1, Tb, ldt,
+                                    cp->stream);
+      launch_zfwd<double>(c->geom, c->d_tw64.as<z64>(), Tb, ldt, std::sqrt(c->omega) / (double)n3, nullptr, 0,
+                          nullptr, nullptr, 0, nullptr, c->d_Phi.as<z64>(), npw, nullptr, n_v, cp->stream);
+      // overlaps <Phi_a, Phi_b> and grid norms
+      z64* ov = cp->buf<z64>("tmp.ov", (size_t)n_v * n_v);
+      z64* part = cp->buf<z64>("tmp.part", (size_t)n_v * n_v * 64 + 64 * n_v);
+      launch_gemm_hn(c->d_Phi.as<z64>(), npw, n_v, c->d_Phi.as<z64>(), npw, n_v, npw, ov, part, cp->stream);
+      z64* gn = cp->buf<z64>("tmp.gn", n_v);
+      for (int v = 0; v < n_v; ++v)
+        launch_dots(c->d_psi.as<z64>() + (size_t)v * n3, 0, 1, c->d_psi.as<z64>() + (size_t)v * n3, n3, gn + v,
+                    part + (size_t)n_v * n_v * 64, cp->stream);
+      // eigen-residual |H phi - e phi|
+      z64* R = cp->buf<z64>("tmp.R", (size_t)n_v * npw);
+      z64* Tb2 = cp->buf<z64>("tmp.Tb2", (size_t)n_v * ldt);
+      z64* sh = cp->buf<z64>("tmp.sh", n_v);
+      std::vector<z64> hs(n_v);
+      for (int v = 0; v < n_v; ++v) hs[v] = z64{eps_v[v], 0.0};
+      h2d(cp, sh, hs.data(), n_v * sizeof(z64));
+      happly<double>(cp, c->d_Phi.as<z64>(), npw, R, npw, sh, nullptr, 0, nullptr, Tb2, nullptr, n_v);
+      double* rn = cp->buf<double>("tmp.rn", n_v);
+      z64* zero = cp->buf<z64>("tmp.zero", (size_t)n_v * npw);
+      HIPCHK(hipMemsetAsync(zero, 0, (size_t)n_v * npw * sizeof(z64), cp->stream));
+      launch_resid<double>(R, npw, nullptr, zero, npw, nullptr, 0, rn, npw, nullptr, n_v, cp->stream);
+      cp->check_launch();
+      std::vector<z64> h_ov(n_v * n_v), h_gn(n_v);
+      std::vector<double> h_rn(n_v);
+      HIPCHK(hipMemcpyAsync(h_ov.data(), ov, h_ov.size() * sizeof(z64), hipMemcpyDeviceToHost, cp->stream));
+      HIPCHK(hipMemcpyAsync(h_gn.data(), gn, n_v * sizeof(z64), hipMemcpyDeviceToHost, cp->stream));
+      HIPCHK(hipMemcpyAsync(h_rn.data(), rn, n_v * sizeof(double), hipMemcpyDeviceToHost, cp->stream));
+      cp->sync();
+      for (int a = 0; a < n_v; ++a) {
+        for (int b = 0; b < n_v; ++b) {
+          const z64 x = h_ov[(size_t)b * n_v + a];
+          const double target = a == b ? 1.0 : 0.0;
+          if (std::abs(x.x - target) > 1e-8 || std::abs(x.y) > 1e-8) {
+            char msg[160];
+            std::snprintf(msg, sizeof msg, "valence orbitals not orthonormal on the sphere (<%d|%d> = %.3e%+.3ei)",
+                          a, b, x.x, x.y);
+            return bad(msg);
+          }
+        }
+        if (std::abs(h_gn[a].x * c->dV - 1.0) > 1e-8) return bad("psi_v not normalised or not band-limited");
+        if (std::sqrt(h_rn[a]) > 1e-8) {
+          char msg[160];
+          std::snprintf(msg, sizeof msg, "eigen-residual of band %d is %.3e Ha", a, std::sqrt(h_rn[a]));
+          return bad(msg);
+        }
+      }
+      c->d_Phi32.ensure((size_t)n_v * npw * sizeof(z32));
+      launch_cvt_64_32(c->d_Phi.as<z64>(), c->d_Phi32.as<z32>(), (long)n_v * npw, cp->stream);
+      cp->sync();
+    }
+    c->ws.clear();
+    *out = c.release();
+    return LGW_OK;
+  } catch (const Fail& f) {
+    g_setup_err = f.msg;
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    g_setup_err = "host allocation failed";
+    return LGW_ENOMEM;
+  }
+}
+
+lgw_status lgw_chi0_apply(lgw_ctx* c, int n_rhs, const lgw_c128* dV, int n_z, const lgw_c128* z, lgw_c128* dn) {
+  if (!c) return LGW_EINVAL;
+  if (n_rhs < 0 || n_z < 0 || (n_rhs > 0 && (!dV || !dn)) || (n_z > 0 && !z))
+    return set_err(c, LGW_EINVAL, "invalid arguments");
+  for (int k = 0; k < n_z; ++k) {
+    if (!std::isfinite(z[k].re) || !std::isfinite(z[k].im)) return set_err(c, LGW_ENAN, "non-finite frequency");
+    if (z[k].re != 0.0 && z[k].im < 0.0) return set_err(c, LGW_EINVAL, "real-axis broadening must be >= 0");
+  }
+  if (n_rhs == 0 || n_z == 0) return LGW_OK;
+  try {
+    const long n3 = c->n3;
+    const size_t in_bytes = (size_t)n_rhs * n3 * sizeof(z64);
+    const z64* d_in = static_cast<const z64*>(stage_in(c, dV, in_bytes, "io.in"));
+    int* d_flag = c->buf<int>("flag", 1);
+    HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), c->stream));
+    launch_finite_check(reinterpret_cast<const double*>(d_in), 2 * (long)n_rhs * n3, d_flag, c->stream);
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    if (hflag) return set_err(c, LGW_ENAN, "non-finite value in dV");
+    c->tot_iters = c->tot_h = 0;
+    z64* X = c->buf<z64>("io.X", (size_t)n_rhs * n3);
+    launch_xyz_to_zxy(c->N, d_in, n3, X, n3, n_rhs, false, c->stream);
+    z64* O = c->buf<z64>("io.O", (size_t)n_z * n_rhs * n3);
+    lgw_status st = chi0_internal(c, n_rhs, X, n_z, z, O, (long)n_rhs * n3);
+    const size_t out_bytes = (size_t)n_z * n_rhs * n3 * sizeof(z64);
+    z64* d_out = static_cast<z64*>(stage_out(c, dn, out_bytes, "io.out"));
+    launch_zxy_to_xyz(c->N, O, n3, d_out, n3, n_z * n_rhs, c->stream);
+    c->check_launch();
+    c->sync();
+    finish_out(c, dn, d_out, out_bytes);
+    if (st != LGW_OK) c->err = st == LGW_ENOCONV ? "some Sternheimer solves did not converge" : "Krylov breakdown";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_lanczos(lgw_ctx* c, const lgw_c128* q0, int k, double* alpha, double* beta, lgw_c128* Q,
+                       int* k_done) {
+  if (!c) return LGW_EINVAL;
+  if (k < 1 || !q0 || !alpha || !beta || !k_done) return set_err(c, LGW_EINVAL, "invalid arguments");
+  try {
+    const long n3 = c->n3;
+    const z64* d_q0 = static_cast<const z64*>(stage_in(c, q0, n3 * sizeof(z64), "io.q0"));
+    int* d_flag = c->buf<int>("flag", 1);
+    HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), c->stream));
+    launch_finite_check(reinterpret_cast<const double*>(d_q0), 2 * n3, d_flag, c->stream);
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    if (hflag) return set_err(c, LGW_ENAN, "non-finite value in q0");
+    z64* Qd = c->buf<z64>("lz.Q", (size_t)k * n3);
+    z64* w = c->buf<z64>("lz.w", n3);
+    z64* x1 = c->buf<z64>("lz.x1", n3);
+    z64* h = c->buf<z64>("lz.h", k);
+    z64* part = c->buf<z64>("lz.part", (size_t)64 * (k + 1));
+    double* ab = c->buf<double>("lz.ab", 2 * (size_t)k + 1);   // alpha[0..k), beta[0..k), norm
+    double* d_alpha = ab;
+    double* d_beta = ab + k;
+    double* d_nrm = ab + 2 * k;
+    launch_xyz_to_zxy(c->N, d_q0, n3, w, n3, 1, false, c->stream);
+    launch_norm(w, n3, d_nrm, part, c->stream);
+    double h_nrm = 0;
+    HIPCHK(hipMemcpyAsync(&h_nrm, d_nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    if (!(h_nrm > 0)) return set_err(c, LGW_EINVAL, "q0 is zero");
+    launch_scale_into(w, d_nrm, Qd, n3, c->stream);
+    const lgw_c128 z0{0.0, 0.0};
+    lgw_status st = LGW_OK;
+    std::vector<int> all_it, all_fl, all_sw;
+    std::vector<double> all_res;
+    long long tot_it = 0, tot_h = 0;
+    double amax = 0.0;
+    int done = 0;
+    for (int j = 0; j < k; ++j) {
+      z64* qj = Qd + (size_t)j * n3;
+      // w = -v^1/2 chi0(0) v^1/2 q_j
+      HIPCHK(hipMemcpyAsync(x1, qj, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+      vhalf_inplace(c, x1, 1, 1.0);
+      c->tot_iters = c->tot_h = 0;
+      lgw_status s1 = chi0_internal(c, 1, x1, 1, &z0, w, n3);
+      st = worst(st, s1);
+      all_it.insert(all_it.end(), c->st_iters.begin(), c->st_iters.end());
+      all_fl.insert(all_fl.end(), c->st_flags.begin(), c->st_flags.end());
+      all_sw.insert(all_sw.end(), c->st_sweeps.begin(), c->st_sweeps.end());
+      all_res.insert(all_res.end(), c->st_res.begin(), c->st_res.end());
+      tot_it += c->tot_iters;
+      tot_h += c->tot_h;
+      vhalf_inplace(c, w, 1, -1.0);
+      // alpha_j = Re <q_j, w>; w -= alpha_j q_j + beta_{j-1} q_{j-1}
+      launch_lanczos_alpha(qj, w, n3, d_alpha + j, part, c->stream);
+      launch_lanczos_sub(w, qj, j > 0 ? qj - n3 : nullptr, d_alpha + j, j > 0 ? d_beta + j - 1 : nullptr, n3,
+                         c->stream);
+      // full reorthogonalisation: classical Gram-Schmidt, twice
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_dots(Qd, n3, j + 1, w, n3, h, part, c->stream);
+        launch_gemv_sub(Qd, n3, j + 1, h, w, n3, c->stream);
+      }
+      launch_norm(w, n3, d_beta + j, part, c->stream);
+      double hb[2];
+      HIPCHK(hipMemcpyAsync(&hb[0], d_alpha + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(&hb[1], d_beta + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      amax = std::max(amax, std::abs(hb[0]));
+      done = j + 1;
+      if (hb[1] < 1e-14 * amax) break;
+      if (j + 1 < k) launch_scale_into(w, d_beta + j, Qd + (size_t)(j + 1) * n3, n3, c->stream);
+    }
+    c->st_iters = all_it;
+    c->st_flags = all_fl;
+    c->st_sweeps = all_sw;
+    c->st_res = all_res;
+    c->tot_iters = tot_it;
+    c->tot_h = tot_h;
+    // outputs
+    if (c->opts.mem == LGW_MEM_DEVICE) {
+      HIPCHK(hipMemcpyAsync(alpha, d_alpha, done * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(beta, d_beta, done * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(alpha, d_alpha, done * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(beta, d_beta, done * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    if (Q) {
+      const size_t qb = (size_t)done * n3 * sizeof(z64);
+      z64* dq = static_cast<z64*>(stage_out(c, Q, qb, "io.Qout"));
+      launch_zxy_to_xyz(c->N, Qd, n3, dq, n3, done, c->stream);
+      c->check_launch();
+      c->sync();
+      finish_out(c, Q, dq, qb);
+    }
+    c->sync();
+    *k_done = done;
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_project(lgw_ctx* c, int k, const lgw_c128* Q, int n_z, const lgw_c128* z, lgw_c128* E) {
+  if (!c) return LGW_EINVAL;
+  if (k < 1 || n_z < 1 || !Q || !z || !E) return set_err(c, LGW_EINVAL, "invalid arguments");
+  for (int i = 0; i < n_z; ++i) {
+    if (!std::isfinite(z[i].re) || !std::isfinite(z[i].im)) return set_err(c, LGW_ENAN, "non-finite frequency");
+    if (z[i].re != 0.0 && z[i].im < 0.0) return set_err(c, LGW_EINVAL, "real-axis broadening must be >= 0");
+  }
+  try {
+    const long n3 = c->n3;
+    const z64* dQ = static_cast<const z64*>(stage_in(c, Q, (size_t)k * n3 * sizeof(z64), "io.Qin"));
+    z64* Qz = c->buf<z64>("pj.Q", (size_t)k * n3);
+    z64* X = c->buf<z64>("pj.X", (size_t)k * n3);
+    launch_xyz_to_zxy(c->N, dQ, n3, Qz, n3, k, false, c->stream);
+    HIPCHK(hipMemcpyAsync(X, Qz, (size_t)k * n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    vhalf_inplace(c, X, k, 1.0);
+    z64* D = c->buf<z64>("pj.D", (size_t)n_z * k * n3);
+    c->tot_iters = c->tot_h = 0;
+    lgw_status st = chi0_internal(c, k, X, n_z, z, D, (long)k * n3);
+    vhalf_inplace(c, D, n_z * k, -1.0);
+    z64* Et = c->buf<z64>("pj.E", (size_t)n_z * k * k);
+    z64* part = c->buf<z64>("pj.part", (size_t)k * k * 64);
+    for (int i = 0; i < n_z; ++i)
+      launch_gemm_hn(Qz, n3, k, D + (size_t)i * k * n3, n3, k, n3, Et + (size_t)i * k * k, part, c->stream);
+    c->check_launch();
+    std::vector<z64> h((size_t)n_z * k * k);
+    HIPCHK(hipMemcpyAsync(h.data(), Et, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    // Et[z][b][a] = <q_a, M q_b>  ->  E[z][a][b]
+    std::vector<z64> e(h.size());
+    for (int i = 0; i < n_z; ++i)
+      for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) e[((size_t)i * k + a) * k + b] = h[((size_t)i * k + b) * k + a];
+    if (c->opts.mem == LGW_MEM_DEVICE)
+      h2d(c, E, e.data(), e.size() * sizeof(z64));
+    else
+      std::memcpy(E, e.data(), e.size() * sizeof(z64));
+    c->sync();
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_hpsi(lgw_ctx* c, int n, lgw_c128 shift, const lgw_c128* x, lgw_c128* y) {
+  if (!c) return LGW_EINVAL;
+  if (n < 0 || (n > 0 && (!x || !y))) return set_err(c, LGW_EINVAL, "invalid arguments");
+  if (n == 0) return LGW_OK;
+  try {
+    const int npw = c->npw;
+    const size_t bytes = (size_t)n * npw * sizeof(z64);
+    const z64* dx = static_cast<const z64*>(stage_in(c, x, bytes, "io.hx"));
+    z64* dy = static_cast<z64*>(stage_out(c, y, bytes, "io.hy"));
+    const long ldt = (long)c->N * c->ncols;
+    std::vector<z64> sh(n, z64{shift.re, shift.im});
+    if (c->opts.precision == LGW_FP64) {
+      z64* d_sh = c->buf<z64>("h.sh", n);
+      z64* Tb = c->buf<z64>("h.Tb", (size_t)n * ldt);
+      h2d(c, d_sh, sh.data(), n * sizeof(z64));
+      happly<double>(c, dx, npw, dy, npw, d_sh, nullptr, 0, nullptr, Tb, nullptr, n);
+    } else {
+      z32* x32 = c->buf<z32>("h.x32", (size_t)n * npw);
+      z32* y32 = c->buf<z32>("h.y32", (size_t)n * npw);
+      z32* Tb = c->buf<z32>("h.Tb32", (size_t)n * ldt);
+      z32* d_sh = c->buf<z32>("h.sh32", n);
+      std::vector<z32> s32(n, z32{(float)shift.re, (float)shift.im});
+      h2d(c, d_sh, s32.data(), n * sizeof(z32));
+      launch_cvt_64_32(dx, x32, (long)n * npw, c->stream);
+      happly<float>(c, x32, npw, y32, npw, d_sh, nullptr, 0, nullptr, Tb, nullptr, n);
+      double* one = c->buf<double>("h.one", n);
+      std::vector<double> h1(n, 1.0);
+      h2d(c, one, h1.data(), n * sizeof(double));
+      HIPCHK(hipMemsetAsync(dy, 0, bytes, c->stream));
+      launch_cvt_32_64_axpy(y32, dy, one, nullptr, npw, npw, n, c->stream);
+    }
+    c->check_launch();
+    c->sync();
+    finish_out(c, y, dy, bytes);
+    return LGW_OK;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_vhalf(lgw_ctx* c, int n, const lgw_c128* x, lgw_c128* y) {
+  if (!c) return LGW_EINVAL;
+  if (n < 0 || (n > 0 && (!x || !y))) return set_err(c, LGW_EINVAL, "invalid arguments");
+  if (n == 0) return LGW_OK;
+  try {
+    const long n3 = c->n3;
+    const size_t bytes = (size_t)n * n3 * sizeof(z64);
+    const z64* dx = static_cast<const z64*>(stage_in(c, x, bytes, "io.vx"));
+    z64* dy = static_cast<z64*>(stage_out(c, y, bytes, "io.vy"));
+    z64* G = c->buf<z64>("v.G", (size_t)n * n3);
+    launch_xyz_to_zxy(c->N, dx, n3, G, n3, n, false, c->stream);
+    vhalf_inplace(c, G, n, 1.0);
+    launch_zxy_to_xyz(c->N, G, n3, dy, n3, n, c->stream);
+    c->check_launch();
+    c->sync();
+    finish_out(c, y, dy, bytes);
+    return LGW_OK;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_get_info(const lgw_ctx* c, lgw_info* out) {
+  if (!c || !out) return LGW_EINVAL;
+  out->N = c->N;
+  out->npw = c->npw;
+  out->ncols = c->ncols;
+  out->n_v = c->nv;
+  out->omega = c->omega;
+  return LGW_OK;
+}
+
+lgw_status lgw_sphere(const lgw_ctx* c, int* m) {
+  if (!c || !m) return LGW_EINVAL;
+  std::memcpy(m, c->m.data(), c->m.size() * sizeof(int));
+  return LGW_OK;
+}
+
+lgw_status lgw_get_stats(const lgw_ctx* c, lgw_stats* out) {
+  if (!c || !out) return LGW_EINVAL;
+  out->n_solves = (int)c->st_iters.size();
+  out->iters = c->st_iters.data();
+  out->rel_resid = c->st_res.data();
+  out->refine_sweeps = c->st_sweeps.data();
+  out->flags = c->st_flags.data();
+  out->total_iters = c->tot_iters;
+  out->total_happly = c->tot_h;
+  return LGW_OK;
+}
+
+const char* lgw_last_error(const lgw_ctx* c) { return c ? c->err.c_str() : g_setup_err.c_str(); }
+
+void lgw_free(lgw_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->ws.clear();
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+"""ctypes binding of liblgw.so.
+
+Argument marshalling only: torch tensors supply device memory, every step of
+the computation runs in the library's HIP kernels.  There is no fallback: if
+the library is missing or cannot load, this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+STATUS = {0: "LGW_OK", 1: "LGW_EINVAL", 2: "LGW_ENOMEM", 3: "LGW_EDEVICE", 4: "LGW_ENAN",
+          5: "LGW_ENOCONV", 6: "LGW_EBREAKDOWN"}
+FLAG_CONV, FLAG_BREAK, FLAG_MAXIT = 1, 2, 4
+
+EXPORTS = ["lgw_default_opts", "lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project",
+           "lgw_hpsi", "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats",
+           "lgw_last_error", "lgw_free"]
+
+
+class LgwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class c128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("check_every", C.c_int), ("precond", C.c_int), ("deterministic", C.c_int),
+                ("mem", C.c_int), ("stream", C.c_void_p), ("mem_budget_gb", C.c_double),
+                ("inner_tol", C.c_double), ("max_sweeps", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("N", C.c_int), ("npw", C.c_int), ("ncols", C.c_int), ("n_v", C.c_int),
+                ("omega", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_solves", C.c_int), ("iters", C.POINTER(C.c_int)),
+                ("rel_resid", C.POINTER(C.c_double)), ("refine_sweeps", C.POINTER(C.c_int)),
+                ("flags", C.POINTER(C.c_int)), ("total_iters", C.c_longlong),
+                ("total_happly", C.c_longlong)]
+
+
+def library_path() -> str:
+    return os.environ.get("LGW_LIBRARY", os.path.join(HERE, "liblgw.so"))
+
+
+_lib = None
+
+
+def load_library():
+    """Load liblgw.so and declare its signatures; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python -m paper_1408_3036_amd.build`")
+    lib = C.CDLL(path)
+    P, I, D = C.c_void_p, C.c_int, C.c_double
+    lib.lgw_default_opts.argtypes = [C.POINTER(Opts)]
+    lib.lgw_default_opts.restype = None
+    lib.lgw_setup.argtypes = [C.POINTER(P), C.POINTER(D), C.POINTER(I), D, P, I, P,
+                              C.POINTER(D), C.POINTER(Opts)]
+    lib.lgw_chi0_apply.argtypes = [P, I, P, I, C.POINTER(c128), P]
+    lib.lgw_lanczos.argtypes = [P, P, I, P, P, P, C.POINTER(I)]
+    lib.lgw_project.argtypes = [P, I, P, I, C.POINTER(c128), P]
+    lib.lgw_hpsi.argtypes = [P, I, c128, P, P]
+    lib.lgw_vhalf.argtypes = [P, I, P, P]
+    lib.lgw_get_info.argtypes = [P, C.POINTER(Info)]
+    lib.lgw_sphere.argtypes = [P, C.POINTER(I)]
+    lib.lgw_get_stats.argtypes = [P, C.POINTER(Stats)]
+    lib.lgw_last_error.argtypes = [P]
+    lib.lgw_last_error.restype = C.c_char_p
+    lib.lgw_free.argtypes = [P]
+    lib.lgw_free.restype = None
+    for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_hpsi",
+                 "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats"]:
+        getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _z(zs) -> tuple:
+    zs = np.atleast_1d(np.asarray(zs, dtype=np.complex128))
+    arr = (c128 * len(zs))(*[c128(float(z.real), float(z.imag)) for z in zs])
+    return arr, len(zs)
+
+
+class Lgw:
+    """One system (H, valence set) on the current HIP device.
+
+    V: real [N, N, N] float64 CUDA tensor; psi: [n_v, N^3] complex128 CUDA
+    tensor; eps: n_v floats; cell: box edges (Lx, Ly, Lz) in bohr.
+    """
+
+    def __init__(self, L, N: int, ecut: float, V, psi, eps, precision: str = "fp64",
+                 tol: float | None = None, max_iter: int | None = None,
+                 check_every: int | None = None, mem_budget_gb: float | None = None,
+                 inner_tol: float | None = None, max_sweeps: int | None = None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        Ls = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+        cell = (C.c_double * 9)(*np.diag(Ls).ravel().tolist())
+        grid = (C.c_int * 3)(N, N, N)
+        opts = Opts()
+        self.lib.lgw_default_opts(C.byref(opts))
+        opts.precision = {"fp64": 0, "mixed": 1}[precision]
+        if tol is not None:
+            opts.tol = tol
+        if max_iter is not None:
+            opts.max_iter = max_iter
+        if check_every is not None:
+            opts.check_every = check_every
+        if mem_budget_gb is not None:
+            opts.mem_budget_gb = mem_budget_gb
+        if inner_tol is not None:
+            opts.inner_tol = inner_tol
+        if max_sweeps is not None:
+            opts.max_sweeps = max_sweeps
+        self.opts = opts
+        V = self._dev(V, torch.float64).reshape(-1)
+        psi = self._dev(psi, torch.complex128).reshape(len(eps), -1)
+        eps_arr = (C.c_double * len(eps))(*[float(e) for e in eps])
+        ctx = C.c_void_p()
+        torch.cuda.synchronize()
+        st = self.lib.lgw_setup(C.byref(ctx), cell, grid, float(ecut), V.data_ptr(), len(eps),
+                                psi.data_ptr(), eps_arr, C.byref(opts))
+        if st != 0:
+            raise LgwError(st, self.lib.lgw_last_error(None).decode())
+        self.ctx = ctx
+        self.N = N
+        self.n_v = len(eps)
+        info = Info()
+        self.lib.lgw_get_info(ctx, C.byref(info))
+        self.npw, self.ncols, self.omega = info.npw, info.ncols, info.omega
+
+    def _dev(self, x, dtype):
+        t = self.torch
+        if not isinstance(x, t.Tensor):
+            x = t.as_tensor(np.asarray(x))
+        return x.to(device="cuda", dtype=dtype).contiguous()
+
+    def _check(self, st: int, allow_partial: bool = False):
+        if st != 0 and not (allow_partial and st in (5, 6)):
+            raise LgwError(st, self.lib.lgw_last_error(self.ctx).decode())
+        return STATUS[st]
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.lgw_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- calls
+    def chi0_apply(self, dV, z, allow_partial: bool = False):
+        """dn[z, j] = chi0(z) dV[j]; dV [n_rhs, N^3] complex128 (CUDA)."""
+        t = self.torch
+        dV = self._dev(dV, t.complex128)
+        dV = dV.reshape(-1, self.N ** 3)
+        zarr, nz = _z(z)
+        out = t.empty((nz, dV.shape[0], self.N ** 3), dtype=t.complex128, device="cuda")
+        t.cuda.synchronize()
+        self.last_status = self._check(
+            self.lib.lgw_chi0_apply(self.ctx, dV.shape[0], dV.data_ptr(), nz, zarr, out.data_ptr()),
+            allow_partial)
+        return out
+
+    def lanczos(self, q0, k: int, want_Q: bool = True):
+        t = self.torch
+        q0 = self._dev(q0, t.complex128).reshape(-1)
+        alpha = t.zeros(k, dtype=t.float64, device="cuda")
+        beta = t.zeros(k, dtype=t.float64, device="cuda")
+        Q = t.zeros((k, self.N ** 3), dtype=t.complex128, device="cuda") if want_Q else None
+        kd = C.c_int(0)
+        t.cuda.synchronize()
+        self.last_status = self._check(self.lib.lgw_lanczos(
+            self.ctx, q0.data_ptr(), k, alpha.data_ptr(), beta.data_ptr(),
+            Q.data_ptr() if Q is not None else None, C.byref(kd)))
+        n = kd.value
+        return alpha[:n], beta[:n], (Q[:n] if Q is not None else None), n
+
+    def project(self, Q, z):
+        t = self.torch
+        Q = self._dev(Q, t.complex128)
+        k = Q.shape[0]
+        zarr, nz = _z(z)
+        E = t.empty((nz, k, k), dtype=t.complex128, device="cuda")
+        t.cuda.synchronize()
+        self.last_status = self._check(
+            self.lib.lgw_project(self.ctx, k, Q.data_ptr(), nz, zarr, E.data_ptr()))
+        return E
+
+    def hpsi(self, x, shift: complex = 0.0):
+        t = self.torch
+        x = self._dev(x, t.complex128).reshape(-1, self.npw)
+        y = t.empty_like(x)
+        t.cuda.synchronize()
+        self._check(self.lib.lgw_hpsi(self.ctx, x.shape[0], c128(shift.real, shift.imag),
+                                      x.data_ptr(), y.data_ptr()))
+        return y
+
+    def vhalf(self, x):
+        t = self.torch
+        x = self._dev(x, t.complex128).reshape(-1, self.N ** 3)
+        y = t.empty_like(x)
+        t.cuda.synchronize()
+        self._check(self.lib.lgw_vhalf(self.ctx, x.shape[0], x.data_ptr(), y.data_ptr()))
+        return y
+
+    def sphere(self) -> np.ndarray:
+        m = (C.c_int * (3 * self.npw))()
+        self._check(self.lib.lgw_sphere(self.ctx, m))
+        return np.frombuffer(m, dtype=np.int32).reshape(self.npw, 3).copy()
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.lgw_get_stats(self.ctx, C.byref(s)))
+        n = s.n_solves
+
+        def arr(p, dt):
+            return np.ctypeslib.as_array(p, shape=(n,)).astype(dt).copy() if n else np.zeros(0, dt)
+        return {"n_solves": n, "iters": arr(s.iters, np.int64),
+                "rel_resid": arr(s.rel_resid, np.float64),
+                "refine_sweeps": arr(s.refine_sweeps, np.int64),
+                "flags": arr(s.flags, np.int64), "total_iters": s.total_iters,
+                "total_happly": s.total_happly}

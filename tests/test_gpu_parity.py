@@ -1,0 +1,125 @@
+"""GPU parity of the HIP path against the CPU oracle (c1-size system).
+
+Tolerances: the FP64 path is held to 1e-10 relative on chi0 applies, Lanczos
+coefficients and projections (the bar for the plain FP64 method); kernel-level
+operators (H psi, v^1/2) to 1e-12; mixed precision to 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.pw import Basis
+from oracle.sos import SOS
+from oracle import lanczos as olz
+from synthetic import make_workload, random_potentials
+from tests.gpu_common import lib_order, rel, colwise_rel
+
+
+@pytest.fixture(scope="module")
+def sysc1():
+    from paper_1408_3036_amd import Lgw
+    w = make_workload(1)
+    b = Basis(w.L, w.N, w.ecut)
+    s = SOS(b, w.V, w.n_v)
+    lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps)
+    yield w, b, s, lg
+    lg.close()
+
+
+def test_sphere_matches_oracle(sysc1):
+    w, b, s, lg = sysc1
+    assert lg.npw == b.npw
+    m = lg.sphere()
+    # lexicographic order: index of -m is npw-1-index(m)
+    assert np.array_equal(m[::-1], -m)
+
+
+def test_hpsi_matches_dense_hamiltonian(sysc1):
+    w, b, s, lg = sysc1
+    order = lib_order(lg, b)
+    H = b.dense_H(w.V)
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((5, b.npw)) + 1j * rng.standard_normal((5, b.npw))
+    shift = 0.37 - 0.11j
+    Y = lg.hpsi(torch.from_numpy(X[:, order]), shift).cpu().numpy()
+    ref = (X @ H.T - shift * X)[:, order]
+    assert rel(Y, ref) < 1e-13
+
+
+def test_vhalf_matches_oracle(sysc1):
+    w, b, s, lg = sysc1
+    x = random_potentials(w.N, 3, 4, real=False)
+    y = lg.vhalf(torch.from_numpy(x)).cpu().numpy()
+    assert rel(y, b.apply_vhalf(x)) < 1e-13
+
+
+@pytest.mark.parametrize("z", [0.0, 0.3j, 2.0j])
+def test_chi0_imaginary_axis_fp64(sysc1, z):
+    w, b, s, lg = sysc1
+    x = random_potentials(w.N, 3, 5)
+    dn = lg.chi0_apply(torch.from_numpy(x), [z]).cpu().numpy()[0]
+    ref = s.chi0(z, x)
+    st = lg.stats()
+    assert np.all(st["flags"] == 1), st
+    assert colwise_rel(dn, ref) < 1e-10
+
+
+@pytest.mark.parametrize("z", [0.3 + 0.0036749j, 1.1 + 0.0036749j, -0.45 + 0.02j])
+def test_chi0_real_axis_sqmr_fp64(sysc1, z):
+    w, b, s, lg = sysc1
+    x = random_potentials(w.N, 2, 6, real=False)
+    dn = lg.chi0_apply(torch.from_numpy(x), [z]).cpu().numpy()[0]
+    ref = s.chi0(z, x)
+    assert colwise_rel(dn, ref) < 1e-9
+
+
+def test_chi0_many_columns_and_frequencies_in_one_call(sysc1):
+    w, b, s, lg = sysc1
+    zs = [0.0, 0.05j, 0.7j, 0.5 + 0.0036749j]
+    x = random_potentials(w.N, 4, 7)
+    dn = lg.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+    for k, z in enumerate(zs):
+        assert colwise_rel(dn[k], s.chi0(z, x)) < 1e-9
+
+
+def test_lanczos_matches_oracle(sysc1):
+    w, b, s, lg = sysc1
+    q0 = random_potentials(w.N, 1, 8)[0]
+    k = w.lanczos_steps
+    a, be, Q, kd = lg.lanczos(torch.from_numpy(q0), k)
+    ra, rb, RQ, rkd = olz.lanczos(lambda v: s.M(0.0, v), q0, k)
+    assert kd == rkd == k
+    a, be, Q = a.cpu().numpy(), be.cpu().numpy(), Q.cpu().numpy()
+    assert np.abs(a - ra).max() <= 1e-10 * np.abs(ra).max()
+    assert np.abs(be - rb).max() <= 1e-10 * np.abs(ra).max()
+    assert colwise_rel(Q, RQ) < 1e-9
+    assert np.abs(Q.conj() @ Q.T - np.eye(k)).max() < 1e-13
+
+
+def test_project_matches_oracle(sysc1):
+    w, b, s, lg = sysc1
+    q0 = random_potentials(w.N, 1, 9)[0]
+    _, _, RQ, _ = olz.lanczos(lambda v: s.M(0.0, v), q0, 6)
+    zs = [0.0, 0.4j, 0.6 + 0.0036749j]
+    E = lg.project(torch.from_numpy(RQ), zs).cpu().numpy()
+    Eref = olz.project(lambda z, v: s.M(z, v), RQ, zs)
+    for k in range(len(zs)):
+        assert rel(E[k], Eref[k]) < 1e-9
+
+
+def test_mixed_precision_chi0_within_1e6(sysc1):
+    from paper_1408_3036_amd import Lgw
+    w, b, s, _ = sysc1
+    lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps,
+             precision="mixed", tol=1e-10)
+    x = random_potentials(w.N, 3, 10)
+    zs = [0.0, 0.3j, 0.4 + 0.0036749j]
+    dn = lg.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+    st = lg.stats()
+    for k, z in enumerate(zs):
+        assert colwise_rel(dn[k], s.chi0(z, x)) < 1e-6
+    assert np.all(st["refine_sweeps"] >= 1)
+    lg.close()
