@@ -148,6 +148,21 @@ typedef struct {
 /* Views owned by the context, valid until the next call on it. */
 lgw_status lgw_get_stats(const lgw_ctx* ctx, lgw_stats* out);
 const char* lgw_last_error(const lgw_ctx* ctx);
+
+/* Per-kernel timing with HIP events recorded around every launch on the
+ * context's stream (off by default; enabling it resets the counters).
+ * model_bytes is the algorithmic HBM traffic of those launches:
+ *   LGW_K_PLANE_HV  xy-plane pass of H: column data read + written once, the
+ *                   potential read once per launch;
+ *   LGW_K_ZINV      sphere read + column write;  LGW_K_ZFWD column read +
+ *                   sphere input read + sphere output written;
+ *   LGW_K_PROJ      vector read + written, valence block read once;
+ *   LGW_K_CG / LGW_K_SQMR  vectors touched by one update. */
+enum { LGW_K_PLANE_HV = 0, LGW_K_ZINV = 1, LGW_K_ZFWD = 2, LGW_K_PROJ = 3, LGW_K_CG = 4,
+       LGW_K_SQMR = 5, LGW_NKERNELS = 6 };
+typedef struct { long long launches; double total_ms; double model_bytes; } lgw_timing;
+lgw_status lgw_profile(lgw_ctx* ctx, int enable);
+lgw_status lgw_kernel_timing(const lgw_ctx* ctx, int kernel, lgw_timing* out);
 void lgw_free(lgw_ctx* ctx);
 
 #ifdef __cplusplus

@@ -75,6 +75,18 @@ struct lgw_ctx {
   std::vector<double> st_res;
   long long tot_iters = 0, tot_h = 0;
   std::string err;
+  // opt-in per-kernel timing with HIP events on the context stream
+  bool prof = false;
+  struct Timed {
+    int kernel;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> pool;
+  double kt_ms[LGW_NKERNELS] = {0};
+  double kt_bytes[LGW_NKERNELS] = {0};
+  long long kt_launches[LGW_NKERNELS] = {0};
 
   template <class T>
   T* buf(const std::string& name, size_t count) {
@@ -82,8 +94,55 @@ struct lgw_ctx {
     b.ensure(count * sizeof(T));
     return b.as<T>();
   }
-  void sync() { HIPCHK(hipStreamSynchronize(stream)); }
+  void sync() {
+    HIPCHK(hipStreamSynchronize(stream));
+    harvest();
+  }
   void check_launch() { HIPCHK(hipGetLastError()); }
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  // bracket one launch: call begin() before it and end() after it
+  hipEvent_t begin() {
+    if (!prof) return nullptr;
+    hipEvent_t a = ev();
+    HIPCHK(hipEventRecord(a, stream));
+    return a;
+  }
+  void end(hipEvent_t a, int kernel, double bytes) {
+    if (!a) return;
+    hipEvent_t b = ev();
+    HIPCHK(hipEventRecord(b, stream));
+    pending.push_back({kernel, bytes, a, b});
+  }
+  // after a stream synchronisation: accumulate the elapsed times
+  void harvest() {
+    for (const Timed& t : pending) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, t.a, t.b));
+      kt_ms[t.kernel] += ms;
+      kt_bytes[t.kernel] += t.bytes;
+      kt_launches[t.kernel] += 1;
+      pool.push_back(t.a);
+      pool.push_back(t.b);
+    }
+    pending.clear();
+  }
+  ~lgw_ctx() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    for (const Timed& t : pending) {
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+  }
 };
 
 namespace {
@@ -119,16 +178,27 @@ template <class T>
 void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const cplx<T>* shift,
             const cplx<T>* E, long lde, const T* ecoef, cplx<T>* Tb, const int* act, int nsys) {
   const long ldt = (long)c->N * c->ncols;
+  const double e = 2.0 * sizeof(T);   // bytes of one complex value
+  const double cols = (double)nsys * c->N * c->ncols, sph = (double)nsys * c->npw;
+  hipEvent_t t0 = c->begin();
   launch_zinv<T>(c->geom, tw_of<T>(c), X, ldx, Tb, ldt, T(1), act, nsys, c->stream);
+  c->end(t0, LGW_K_ZINV, e * (sph + cols));
+  hipEvent_t t1 = c->begin();
   launch_plane_hv<T>(c->geom, tw_of<T>(c), Tb, ldt, vt_of<T>(c), act, nsys, c->stream);
+  c->end(t1, LGW_K_PLANE_HV, e * 2.0 * cols + sizeof(T) * (double)c->n3);
+  hipEvent_t t2 = c->begin();
   launch_zfwd<T>(c->geom, tw_of<T>(c), Tb, ldt, T(1.0 / (double)c->n3), X, ldx, shift, E, lde, ecoef, Y, ldy,
                  act, nsys, c->stream);
+  c->end(t2, LGW_K_ZFWD, e * (cols + (E ? 3.0 : 2.0) * sph));
   c->tot_h += nsys;
 }
 
 template <class T>
 void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
+  hipEvent_t t0 = c->begin();
   launch_proj<T>(phi_of<T>(c), c->npw, c->nv, c->npw, Y, ldy, act, nsys, c->stream);
+  // Y read once and written once; the valence block is read once per launch
+  c->end(t0, LGW_K_PROJ, 2.0 * sizeof(T) * ((2.0 * nsys + c->nv) * c->npw));
 }
 
 // Y = A X for the projected operator of the given kind (X is in range(P_c)).
@@ -226,10 +296,16 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     const int na = (int)act.size();
     for (int k = 0; k < chunk; ++k) {
       apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na);
-      if (b.kind == K_SQMR)
+      hipEvent_t t0 = c->begin();
+      if (b.kind == K_SQMR) {
         launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
-      else
+        // reads q, t, r, d, x (q and r twice), writes r, d, x, q
+        c->end(t0, LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
+      } else {
         launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
+        // reads p, Ap (twice), x, r (twice), p; writes x, r, p
+        c->end(t0, LGW_K_CG, 2.0 * sizeof(T) * 10.0 * na * npw);
+      }
     }
     c->check_launch();
     it += chunk;
@@ -1064,14 +1140,45 @@ lgw_status lgw_get_stats(const lgw_ctx* c, lgw_stats* out) {
   return LGW_OK;
 }
 
+lgw_status lgw_profile(lgw_ctx* c, int enable) {
+  if (!c) return LGW_EINVAL;
+  try {
+    c->sync();
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+  c->prof = enable != 0;
+  for (int k = 0; k < LGW_NKERNELS; ++k) {
+    c->kt_ms[k] = 0;
+    c->kt_bytes[k] = 0;
+    c->kt_launches[k] = 0;
+  }
+  return LGW_OK;
+}
+
+lgw_status lgw_kernel_timing(const lgw_ctx* c, int kernel, lgw_timing* out) {
+  if (!c || !out || kernel < 0 || kernel >= LGW_NKERNELS) return LGW_EINVAL;
+  out->launches = c->kt_launches[kernel];
+  out->total_ms = c->kt_ms[kernel];
+  out->model_bytes = c->kt_bytes[kernel];
+  return LGW_OK;
+}
+
 const char* lgw_last_error(const lgw_ctx* c) { return c ? c->err.c_str() : g_setup_err.c_str(); }
 
 void lgw_free(lgw_ctx* c) {
   if (!c) return;
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  hipStream_t s = c->stream;
+  const bool own = c->own_stream;
+  if (s) (void)hipStreamSynchronize(s);
+  try {
+    c->harvest();
+  } catch (const Fail&) {
+  }
   c->ws.clear();
-  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  c->stream = nullptr;
   delete c;
+  if (own && s) (void)hipStreamDestroy(s);
 }
 
 }  // extern "C"

@@ -17,9 +17,7 @@ STATUS = {0: "LGW_OK", 1: "LGW_EINVAL", 2: "LGW_ENOMEM", 3: "LGW_EDEVICE", 4: "L
           5: "LGW_ENOCONV", 6: "LGW_EBREAKDOWN"}
 FLAG_CONV, FLAG_BREAK, FLAG_MAXIT = 1, 2, 4
 
-EXPORTS = ["lgw_default_opts", "lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project",
-           "lgw_hpsi", "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats",
-           "lgw_last_error", "lgw_free"]
+KERNELS = {"plane_hv": 0, "zinv": 1, "zfwd": 2, "proj": 3, "cg": 4, "sqmr": 5}
 
 
 class LgwError(RuntimeError):
@@ -43,6 +41,10 @@ class Opts(C.Structure):
 class Info(C.Structure):
     _fields_ = [("N", C.c_int), ("npw", C.c_int), ("ncols", C.c_int), ("n_v", C.c_int),
                 ("omega", C.c_double)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("launches", C.c_longlong), ("total_ms", C.c_double), ("model_bytes", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -81,12 +83,15 @@ def load_library():
     lib.lgw_get_info.argtypes = [P, C.POINTER(Info)]
     lib.lgw_sphere.argtypes = [P, C.POINTER(I)]
     lib.lgw_get_stats.argtypes = [P, C.POINTER(Stats)]
+    lib.lgw_profile.argtypes = [P, I]
+    lib.lgw_kernel_timing.argtypes = [P, I, C.POINTER(Timing)]
     lib.lgw_last_error.argtypes = [P]
     lib.lgw_last_error.restype = C.c_char_p
     lib.lgw_free.argtypes = [P]
     lib.lgw_free.restype = None
     for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_hpsi",
-                 "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats"]:
+                 "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats", "lgw_profile",
+                 "lgw_kernel_timing"]:
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -229,6 +234,19 @@ class Lgw:
         m = (C.c_int * (3 * self.npw))()
         self._check(self.lib.lgw_sphere(self.ctx, m))
         return np.frombuffer(m, dtype=np.int32).reshape(self.npw, 3).copy()
+
+    def profile(self, enable: bool = True):
+        """Turn per-kernel HIP-event timing on/off (resets the counters)."""
+        self._check(self.lib.lgw_profile(self.ctx, int(enable)))
+
+    def kernel_timing(self) -> dict:
+        out = {}
+        for name, k in KERNELS.items():
+            t = Timing()
+            self._check(self.lib.lgw_kernel_timing(self.ctx, k, C.byref(t)))
+            out[name] = {"launches": t.launches, "total_ms": t.total_ms,
+                         "model_bytes": t.model_bytes}
+        return out
 
     def stats(self) -> dict:
         s = Stats()
