@@ -215,7 +215,9 @@ def main():
                      "hpsi_GBps": round(bh * rr["happly"] / (h_ms * 1e-3) / 1e9, 1) if h_ms else None,
                      "hpsi_frac_hbm": round(bh * rr["happly"] / (h_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
                      if h_ms else None,
-                     "kernel_ms": {n: round(v["total_ms"] / args.steps, 2) for n, v in kt.items()}}
+                     "kernel_ms": {n: round(v["total_ms"] / args.steps, 2) for n, v in kt.items()},
+                     "kernel_GBps": {n: round(v["model_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
+                                     for n, v in kt.items() if v["total_ms"] > 0}}
     if "fp64" in results and "mixed" in results:
         f, m = results["fp64"], results["mixed"]
         Em = m["E_fp64_basis"]

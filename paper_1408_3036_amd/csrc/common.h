@@ -48,6 +48,11 @@ struct Geom {
   const double* kin;     // [npw] |K|^2 / 2
 };
 
+// LDS position of element e of a length-N line with one pad slot every 8
+// elements: Stockham stages write at strides of the radix, and the pad keeps
+// 16-byte accesses at stride 8 off a single bank group.
+__host__ __device__ constexpr int skew(int e) { return e + (e >> 3); }
+
 // Map a "system" (one right-hand side of a batched solve) to its storage slot.
 __device__ __forceinline__ int sys_of(const int* act, int b) { return act ? act[b] : b; }
 

@@ -18,15 +18,18 @@ namespace lgw {
 
 template <int... Rs> struct RList {};
 
-// Radix plans of the supported grid sizes (products of 2, 3, 4, 5).
+// Radix plans of the supported grid sizes: two Stockham stages N = A * B,
+// each an in-register DFT (composite radices 6 = 3*2, 8 = 4*2, 9 = 3*3).
 template <int N> struct Plan;
 template <> struct Plan<16> { using type = RList<4, 4>; };
-template <> struct Plan<24> { using type = RList<4, 3, 2>; };
-template <> struct Plan<32> { using type = RList<4, 4, 2>; };
-template <> struct Plan<40> { using type = RList<4, 5, 2>; };
-template <> struct Plan<48> { using type = RList<4, 4, 3>; };
-template <> struct Plan<64> { using type = RList<4, 4, 4>; };
-template <> struct Plan<72> { using type = RList<4, 3, 3, 2>; };
+template <> struct Plan<24> { using type = RList<6, 4>; };
+template <> struct Plan<32> { using type = RList<8, 4>; };
+template <> struct Plan<40> { using type = RList<8, 5>; };
+template <> struct Plan<48> { using type = RList<8, 6>; };
+template <> struct Plan<64> { using type = RList<8, 8>; };
+template <> struct Plan<72> { using type = RList<8, 9>; };
+template <int R0, int R1> constexpr int first_of(RList<R0, R1>) { return R0; }
+template <int R0, int R1> constexpr int second_of(RList<R0, R1>) { return R1; }
 
 // --- small DFTs ----------------------------------------------------------
 template <int R, int SIGN, typename T> struct Dft;
@@ -86,12 +89,74 @@ template <int SIGN, typename T> struct Dft<5, SIGN, T> {
   }
 };
 
+// W_R^e = cos(2 pi e / R) + SIGN i sin(2 pi e / R) for the composite radices
+template <int R> struct TwC;
+template <> struct TwC<6> {
+  static constexpr double c[3] = {1.0, 0.5, -0.5};
+  static constexpr double s[3] = {0.0, 0.86602540378443864676, 0.86602540378443864676};
+};
+template <> struct TwC<8> {
+  static constexpr double c[4] = {1.0, 0.70710678118654752440, 0.0, -0.70710678118654752440};
+  static constexpr double s[4] = {0.0, 0.70710678118654752440, 1.0, 0.70710678118654752440};
+};
+template <> struct TwC<9> {
+  static constexpr double c[5] = {1.0, 0.76604444311897803520, 0.17364817766693034885, -0.5,
+                                  -0.93969262078590838405};
+  static constexpr double s[5] = {0.0, 0.64278760968653932632, 0.98480775301220805936,
+                                  0.86602540378443864676, 0.34202014332566873304};
+};
+
+// DFT of R = R1 * R2 points from R2 DFTs of R1 points (subsequences
+// a[R2 m + l]), twiddles W_R^(l k1), then R1 DFTs of R2 points:
+//   y[k1 + R1 k2] = sum_l W_R^(l k1) (sum_m a[R2 m + l] W_R1^(m k1)) W_R2^(l k2)
+template <int R1, int R2, int SIGN, typename T>
+__device__ __forceinline__ void dft_composite(cplx<T>* a) {
+  constexpr int R = R1 * R2;
+  cplx<T> b[R2][R1];
+#pragma unroll
+  for (int l = 0; l < R2; ++l) {
+#pragma unroll
+    for (int m = 0; m < R1; ++m) b[l][m] = a[m * R2 + l];
+    Dft<R1, SIGN, T>::run(b[l]);
+  }
+#pragma unroll
+  for (int l = 1; l < R2; ++l) {
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) {
+      const int e = l * k1;
+      const cplx<T> w{T(TwC<R>::c[e]), T(SIGN * TwC<R>::s[e])};
+      b[l][k1] = b[l][k1] * w;
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cplx<T> c[R2];
+#pragma unroll
+    for (int l = 0; l < R2; ++l) c[l] = b[l][k1];
+    Dft<R2, SIGN, T>::run(c);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) a[k1 + R1 * k2] = c[k2];
+  }
+}
+
+template <int SIGN, typename T> struct Dft<6, SIGN, T> {
+  __device__ __forceinline__ static void run(cplx<T>* a) { dft_composite<3, 2, SIGN, T>(a); }
+};
+template <int SIGN, typename T> struct Dft<8, SIGN, T> {
+  __device__ __forceinline__ static void run(cplx<T>* a) { dft_composite<4, 2, SIGN, T>(a); }
+};
+template <int SIGN, typename T> struct Dft<9, SIGN, T> {
+  __device__ __forceinline__ static void run(cplx<T>* a) { dft_composite<3, 3, SIGN, T>(a); }
+};
+
 // --- one stage ----------------------------------------------------------
+// Stage with explicit load/store functors: ld(t, e) -> value, st(t, e, v).
+// MID: barrier between the load and the store phase (in-place in LDS).
 // TFAST: consecutive threads take consecutive sequences (use when elements
 // are strided and sequences are adjacent); otherwise consecutive butterflies
 // of one sequence (elements adjacent).
-template <typename T, int N, int R, int P, int SIGN, int NT, int MAXCNT, bool TFAST, class Addr>
-__device__ __forceinline__ void fft_stage(cplx<T>* buf, const cplx<T>* tw, int cnt, Addr addr) {
+template <typename T, int N, int R, int P, int SIGN, int NT, int MAXCNT, bool TFAST, bool MID, class Ld, class St>
+__device__ __forceinline__ void fft_stage_ls(const cplx<T>* tw, int cnt, Ld ld, St st) {
   constexpr int M = N / R;
   constexpr int MAXB = (MAXCNT * M + NT - 1) / NT;
   constexpr int TWS = N / (P * R);
@@ -106,7 +171,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const cplx<T>* tw, int c
       if (TFAST) { t = b % cnt; i = b / cnt; } else { i = b % M; t = b / M; }
       const int kk = i % P;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[k][r] = buf[addr(t, i + r * M)];
+      for (int r = 0; r < R; ++r) v[k][r] = ld(t, i + r * M);
       if (P > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -118,7 +183,7 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const cplx<T>* tw, int c
       Dft<R, SIGN, T>::run(v[k]);
     }
   }
-  __syncthreads();
+  if (MID) __syncthreads();
 #pragma unroll
   for (int k = 0; k < MAXB; ++k) {
     const int b = tid + k * NT;
@@ -128,10 +193,17 @@ __device__ __forceinline__ void fft_stage(cplx<T>* buf, const cplx<T>* tw, int c
       const int kk = i % P;
       const int j = (i - kk) * R + kk;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[addr(t, j + r * P)] = v[k][r];
+      for (int r = 0; r < R; ++r) st(t, j + r * P, v[k][r]);
     }
   }
   __syncthreads();
+}
+
+template <typename T, int N, int R, int P, int SIGN, int NT, int MAXCNT, bool TFAST, class Addr>
+__device__ __forceinline__ void fft_stage(cplx<T>* buf, const cplx<T>* tw, int cnt, Addr addr) {
+  fft_stage_ls<T, N, R, P, SIGN, NT, MAXCNT, TFAST, true>(
+      tw, cnt, [&](int t, int e) { return buf[addr(t, e)]; },
+      [&](int t, int e, cplx<T> x) { buf[addr(t, e)] = x; });
 }
 
 template <typename T, int N, int P, int SIGN, int NT, int MAXCNT, bool TFAST, class Addr>
@@ -149,6 +221,64 @@ __device__ __forceinline__ void fft_run(RList<R0, Rs...>, cplx<T>* buf, const cp
 template <typename T, int N, int SIGN, int NT, int MAXCNT, bool TFAST, class Addr>
 __device__ __forceinline__ void fft_lds(cplx<T>* buf, const cplx<T>* tw, int cnt, Addr addr) {
   fft_run<T, N, 1, SIGN, NT, MAXCNT, TFAST>(typename Plan<N>::type{}, buf, tw, cnt, addr);
+}
+
+// Single stage with explicit radix R and sub-transform size P (building block
+// of kernels that fuse work between stages).
+template <typename T, int N, int R, int P, int SIGN, int NT, int MAXCNT, bool TFAST, class Addr>
+__device__ __forceinline__ void fft_one_stage(cplx<T>* buf, const cplx<T>* tw, int cnt, Addr addr) {
+  fft_stage<T, N, R, P, SIGN, NT, MAXCNT, TFAST>(buf, tw, cnt, addr);
+}
+
+// Row filter: in place on `cnt` rows, y <- FFT(m * IFFT(y)) pointwise
+// multiplier m (unnormalised transforms).  The inverse uses the reversed plan
+// {B, A} so that its last stage and the forward first stage (both radix A)
+// touch the same elements {i + r B}: that pair runs in registers around the
+// multiply, three LDS round trips in all.  mul(t, e) returns the real factor.
+template <typename T, int N, int NT, int MAXCNT, class Addr, class Mul>
+__device__ __forceinline__ void fft_filter_rows(cplx<T>* buf, const cplx<T>* tw, int cnt, Addr addr, Mul mul) {
+  constexpr int A = first_of(typename Plan<N>::type{});
+  constexpr int B = second_of(typename Plan<N>::type{});
+  // inverse stage 1: radix B, P = 1
+  fft_stage<T, N, B, 1, +1, NT, MAXCNT, false>(buf, tw, cnt, addr);
+  // inverse stage 2 (radix A, P = B) + multiply + forward stage 1 (radix A, P = 1)
+  {
+    constexpr int MAXB = (MAXCNT * B + NT - 1) / NT;
+    const int nb = cnt * B;
+    cplx<T> v[MAXB][A];
+#pragma unroll
+    for (int k = 0; k < MAXB; ++k) {
+      const int b = threadIdx.x + k * NT;
+      if (b < nb) {
+        const int i = b % B, t = b / B;
+#pragma unroll
+        for (int r = 0; r < A; ++r) v[k][r] = buf[addr(t, i + r * B)];
+#pragma unroll
+        for (int r = 1; r < A; ++r) {
+          cplx<T> w = tw[r * i];
+          w.y = -w.y;
+          v[k][r] = v[k][r] * w;
+        }
+        Dft<A, +1, T>::run(v[k]);
+#pragma unroll
+        for (int r = 0; r < A; ++r) v[k][r] = mul(t, i + r * B) * v[k][r];
+        Dft<A, -1, T>::run(v[k]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MAXB; ++k) {
+      const int b = threadIdx.x + k * NT;
+      if (b < nb) {
+        const int i = b % B, t = b / B;
+#pragma unroll
+        for (int r = 0; r < A; ++r) buf[addr(t, i * A + r)] = v[k][r];
+      }
+    }
+    __syncthreads();
+  }
+  // forward stage 2: radix B, P = A
+  fft_stage<T, N, B, A, -1, NT, MAXCNT, false>(buf, tw, cnt, addr);
 }
 
 }  // namespace lgw

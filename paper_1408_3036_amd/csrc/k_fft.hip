@@ -25,7 +25,7 @@ template <typename T, int N>
 __global__ void __launch_bounds__(256)
 k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, long ldx,
        cplx<T>* __restrict__ Tb, long ldt, T scale, const int* __restrict__ act) {
-  constexpr int LDZ = N + 1;
+  constexpr int LDZ = skew(N) + 1;
   __shared__ cplx<T> buf[kZCols * LDZ];
   __shared__ cplx<T> tws[N];
   const int sys = sys_of(act, blockIdx.y);
@@ -33,23 +33,31 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
   const int nc = min(kZCols, g.ncols - c0);
   const cplx<T>* Xs = X + (long)sys * ldx;
   cplx<T>* Ts = Tb + (long)sys * ldt;
+  __shared__ int cs[kZCols + 1];
+  __shared__ int ch[kZCols];
   load_tw<T, N>(tws, tw);
+  if (threadIdx.x < nc) {
+    cs[threadIdx.x] = g.col_start[c0 + threadIdx.x];
+    ch[threadIdx.x] = g.col_h[c0 + threadIdx.x];
+  }
+  if (threadIdx.x == 0) cs[nc] = c0 + nc < g.ncols ? g.col_start[c0 + nc] : g.npw;
   for (int i = threadIdx.x; i < kZCols * LDZ; i += 256) buf[i] = cplx<T>{0, 0};
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int cl = wv; cl < nc; cl += 4) {
-    const int h = g.col_h[c0 + cl];
-    const int st = g.col_start[c0 + cl];
-    for (int m = lane; m <= 2 * h; m += 64) {
-      const int mz = m - h;
-      buf[cl * LDZ + (mz < 0 ? mz + N : mz)] = Xs[st + m];
+  // the block's columns are one contiguous run of the sphere vector
+  for (int gi = cs[0] + threadIdx.x; gi < cs[nc]; gi += 256) {
+    int lo = 0, hi = nc;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (cs[mid] <= gi) lo = mid; else hi = mid;
     }
+    const int mz = gi - cs[lo] - ch[lo];
+    buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)] = Xs[gi];
   }
   __syncthreads();
-  fft_lds<T, N, +1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + e; });
+  fft_lds<T, N, +1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + skew(e); });
   for (int i = threadIdx.x; i < N * nc; i += 256) {
     const int z = i / nc, cl = i - z * nc;
-    Ts[(long)z * g.ncols + c0 + cl] = scale * buf[cl * LDZ + z];
+    Ts[(long)z * g.ncols + c0 + cl] = scale * buf[cl * LDZ + skew(z)];
   }
 }
 
@@ -60,45 +68,54 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
        const cplx<T>* __restrict__ X, long ldx, const cplx<T>* __restrict__ shift,
        const cplx<T>* __restrict__ E, long lde, const T* __restrict__ ecoef,
        cplx<T>* __restrict__ Y, long ldy, const int* __restrict__ act) {
-  constexpr int LDZ = N + 1;
+  constexpr int LDZ = skew(N) + 1;
   __shared__ cplx<T> buf[kZCols * LDZ];
   __shared__ cplx<T> tws[N];
   const int sys = sys_of(act, blockIdx.y);
   const int c0 = blockIdx.x * kZCols;
   const int nc = min(kZCols, g.ncols - c0);
   const cplx<T>* Ts = Tb + (long)sys * ldt;
+  __shared__ int cs[kZCols + 1];
+  __shared__ int ch[kZCols];
   load_tw<T, N>(tws, tw);
+  if (threadIdx.x < nc) {
+    cs[threadIdx.x] = g.col_start[c0 + threadIdx.x];
+    ch[threadIdx.x] = g.col_h[c0 + threadIdx.x];
+  }
+  if (threadIdx.x == 0) cs[nc] = c0 + nc < g.ncols ? g.col_start[c0 + nc] : g.npw;
   for (int i = threadIdx.x; i < N * nc; i += 256) {
     const int z = i / nc, cl = i - z * nc;
-    buf[cl * LDZ + z] = Ts[(long)z * g.ncols + c0 + cl];
+    buf[cl * LDZ + skew(z)] = Ts[(long)z * g.ncols + c0 + cl];
   }
   __syncthreads();
-  fft_lds<T, N, -1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + e; });
+  fft_lds<T, N, -1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + skew(e); });
   const cplx<T>* Xs = X ? X + (long)sys * ldx : nullptr;
   const cplx<T>* Es = E ? E + (long)sys * lde : nullptr;
   cplx<T>* Ys = Y + (long)sys * ldy;
   const cplx<T> sh = shift ? shift[sys] : cplx<T>{0, 0};
   const T ec = ecoef ? ecoef[sys] : T(0);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int cl = wv; cl < nc; cl += 4) {
-    const int h = g.col_h[c0 + cl];
-    const int st = g.col_start[c0 + cl];
-    for (int m = lane; m <= 2 * h; m += 64) {
-      const int mz = m - h;
-      const int i = st + m;
-      cplx<T> v = scale * buf[cl * LDZ + (mz < 0 ? mz + N : mz)];
-      if (Xs) {
-        const cplx<T> xv = Xs[i];
-        const cplx<T> k = cplx<T>{static_cast<T>(g.kin[i]) - sh.x, -sh.y};
-        v = v + k * xv;
-      }
-      if (Es) v = v + ec * Es[i];
-      Ys[i] = v;
+  for (int i = cs[0] + threadIdx.x; i < cs[nc]; i += 256) {
+    int lo = 0, hi = nc;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (cs[mid] <= i) lo = mid; else hi = mid;
     }
+    const int mz = i - cs[lo] - ch[lo];
+    cplx<T> v = scale * buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)];
+    if (Xs) {
+      const cplx<T> xv = Xs[i];
+      const cplx<T> k = cplx<T>{static_cast<T>(g.kin[i]) - sh.x, -sh.y};
+      v = v + k * xv;
+    }
+    if (Es) v = v + ec * Es[i];
+    Ys[i] = v;
   }
 }
 
 // --------------------------------------------------------------- plane_hv
+// One z plane of one system: x-inverse on the columns y that carry plane
+// waves, y-filter on every row (inverse, times V, forward, with the middle
+// stages fused in registers), x-forward on the same columns.
 template <typename T, int N>
 __global__ void __launch_bounds__(plane_threads<N>())
 k_plane_hv(Geom g, const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ Tb, long ldt,
@@ -116,15 +133,12 @@ k_plane_hv(Geom g, const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ Tb, lon
   __syncthreads();
   const int hy = g.hy;
   const int ny = 2 * hy + 1;
-  // inverse along x on the columns y that carry data
-  fft_lds<T, N, +1, NT, N, true>(pl, tws, ny, [hy](int t, int e) { return e * N + pruned<N>(t, hy); });
-  // inverse along y on every row x
-  fft_lds<T, N, +1, NT, N, false>(pl, tws, N, [](int t, int e) { return t * N + e; });
+  auto col = [hy](int t, int e) { return e * N + pruned<N>(t, hy); };
+  fft_lds<T, N, +1, NT, N, true>(pl, tws, ny, col);
   const T* Vz = Vt + (long)z * N * N;
-  for (int i = threadIdx.x; i < N * N; i += NT) pl[i] = Vz[i] * pl[i];
-  __syncthreads();
-  fft_lds<T, N, -1, NT, N, false>(pl, tws, N, [](int t, int e) { return t * N + e; });
-  fft_lds<T, N, -1, NT, N, true>(pl, tws, ny, [hy](int t, int e) { return e * N + pruned<N>(t, hy); });
+  fft_filter_rows<T, N, NT, N>(pl, tws, N, [](int t, int e) { return t * N + e; },
+                               [Vz](int t, int e) { return Vz[t * N + e]; });
+  fft_lds<T, N, -1, NT, N, true>(pl, tws, ny, col);
   for (int c = threadIdx.x; c < g.ncols; c += NT) Ts[c] = pl[g.col_pos[c]];
 }
 
@@ -222,7 +236,7 @@ template <typename T, int N>
 __global__ void __launch_bounds__(256)
 k_zfull_mul(const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ G, long ldg,
             const T* __restrict__ mul, T scale) {
-  constexpr int LDZ = N + 1;
+  constexpr int LDZ = skew(N) + 1;
   constexpr int NN = N * N;
   __shared__ cplx<T> buf[kZCols * LDZ];
   __shared__ cplx<T> tws[N];
@@ -232,19 +246,19 @@ k_zfull_mul(const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ G, long ldg,
   load_tw<T, N>(tws, tw);
   for (int i = threadIdx.x; i < N * nc; i += 256) {
     const int z = i / nc, cl = i - z * nc;
-    buf[cl * LDZ + z] = Gs[(long)z * NN + c0 + cl];
+    buf[cl * LDZ + skew(z)] = Gs[(long)z * NN + c0 + cl];
   }
   __syncthreads();
-  fft_lds<T, N, -1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + e; });
+  fft_lds<T, N, -1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + skew(e); });
   for (int i = threadIdx.x; i < N * nc; i += 256) {
     const int z = i / nc, cl = i - z * nc;
-    buf[cl * LDZ + z] = (scale * mul[(long)z * NN + c0 + cl]) * buf[cl * LDZ + z];
+    buf[cl * LDZ + skew(z)] = (scale * mul[(long)z * NN + c0 + cl]) * buf[cl * LDZ + skew(z)];
   }
   __syncthreads();
-  fft_lds<T, N, +1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + e; });
+  fft_lds<T, N, +1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + skew(e); });
   for (int i = threadIdx.x; i < N * nc; i += 256) {
     const int z = i / nc, cl = i - z * nc;
-    Gs[(long)z * NN + c0 + cl] = buf[cl * LDZ + z];
+    Gs[(long)z * NN + c0 + cl] = buf[cl * LDZ + skew(z)];
   }
 }
 

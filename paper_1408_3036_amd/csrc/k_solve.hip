@@ -682,3 +682,198 @@ void launch_gemm_hn(const z64* A, long lda, int m, const z64* B, long ldb, int p
   k_gemm_hn_final<<<(m * p + 255) / 256, 256, 0, s>>>(partial, nsplit, C, m * p);
 }
 }  // namespace lgw
+
+// ====================================================================
+// Projector on the matrix cores.  C = Phi^H Y (bands x systems) reduces over
+// the plane-wave index, a GEMM with a long K: one wave computes a 16 x 16
+// MFMA tile whose rows are the real and imaginary parts of 8 bands and whose
+// columns are 16 systems, over a slice of K; partial tiles are summed by the
+// update kernel, which then applies Y -= Phi C streaming Y once.
+namespace lgw {
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16], B[l/16][l%16] and
+// D[4j + l/16][l%16], j = 0..3.  Row r = 4j + q carries band q + 4(j/2),
+// real part for even j, imaginary part for odd j.
+template <> struct Mfma<double> {
+  using acc = d4v;
+  __device__ static acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static void row_role(int r, int& band, int& part) {
+    const int q = r & 3, j = r >> 2;
+    band = q + 4 * (j >> 1);
+    part = j & 1;
+  }
+  // band of accumulator pair (re-reg jr, im-reg ji) for lane l: pairs (0,1), (2,3)
+  __device__ static int out_band(int lane, int pair) { return (lane >> 4) + 4 * pair; }
+};
+// v_mfma_f32_16x16x4f32: D[4(l/16) + j][l%16].  Row r = 4q + j carries band
+// 2q + j/2, real part for even j, imaginary for odd j.
+template <> struct Mfma<float> {
+  using acc = f4v;
+  __device__ static acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static void row_role(int r, int& band, int& part) {
+    const int q = r >> 2, j = r & 3;
+    band = 2 * q + (j >> 1);
+    part = j & 1;
+  }
+  __device__ static int out_band(int lane, int pair) { return 2 * (lane >> 4) + pair; }
+};
+
+constexpr int kProjGroups = kMaxBands / 8;
+
+// grid (ks, ceil(nsys/16)), one wave: partial[ks][sys][v] = sum over the
+// slice of conj(Phi_v) Y_sys
+template <typename T, int NG>
+__global__ void __launch_bounds__(64)
+k_proj_dots(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, const cplx<T>* __restrict__ Y,
+            long ldy, const int* __restrict__ act, int nsys, int kchunk, cplx<T>* __restrict__ part) {
+  using M = Mfma<T>;
+  const int lane = threadIdx.x;
+  const int tile = blockIdx.y * 16;
+  const int col = lane & 15, kl = lane >> 4;
+  const int sidx = tile + col;
+  const bool svalid = sidx < nsys;
+  const int sys = svalid ? sys_of(act, sidx) : 0;
+  const cplx<T>* Ys = Y + (long)sys * ldy;
+  const int r = lane & 15;
+  int band, partv;
+  M::row_role(r, band, partv);
+  constexpr int ngroups = NG;
+  typename M::acc c1[NG], c2[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    c1[g] = typename M::acc{0, 0, 0, 0};
+    c2[g] = typename M::acc{0, 0, 0, 0};
+  }
+  const int k_begin = blockIdx.x * kchunk;
+  const int k_end = min(npw, k_begin + kchunk);
+  constexpr int U = 4;   // K steps of 4 loaded ahead of their MFMAs
+  for (int k0 = k_begin; k0 < k_end; k0 += 4 * U) {
+    cplx<T> y[U];
+    T a[U][NG];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = k0 + 4 * u + kl;
+      const bool kv = kk < k_end;
+      y[u] = (kv && svalid) ? Ys[kk] : cplx<T>{0, 0};
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        a[u][g] = T(0);
+        const int v = 8 * g + band;
+        if (g < ngroups && kv && v < nv) {
+          const cplx<T> p = Phi[(long)v * ldphi + kk];
+          a[u][g] = partv ? p.y : p.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        if (g < ngroups) {
+          c1[g] = M::mma(a[u][g], y[u].x, c1[g]);
+          c2[g] = M::mma(a[u][g], y[u].y, c2[g]);
+        }
+      }
+    }
+  }
+  if (!svalid) return;
+  cplx<T>* P = part + ((long)blockIdx.x * nsys + sidx) * nv;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (g < ngroups) {
+#pragma unroll
+      for (int pr = 0; pr < 2; ++pr) {
+        const int v = 8 * g + M::out_band(lane, pr);
+        const int jr = 2 * pr, ji = 2 * pr + 1;
+        if (v < nv) P[v] = cplx<T>{c1[g][jr] + c2[g][ji], c2[g][jr] - c1[g][ji]};
+      }
+    }
+  }
+}
+
+// grid (ceil(npw/256), ceil(nsys/16)): Y_sys -= sum_v Phi_v C[v][sys]
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, cplx<T>* __restrict__ Y, long ldy,
+              const int* __restrict__ act, int nsys, int ks, const cplx<T>* __restrict__ part) {
+  __shared__ cplx<T> C[16][kMaxBands];
+  const int tile = blockIdx.y * 16;
+  const int nt = min(16, nsys - tile);
+  for (int q = threadIdx.x; q < nt * nv; q += 256) {
+    const int s = q / nv, v = q - s * nv;
+    cplx<T> acc{0, 0};
+    for (int k = 0; k < ks; ++k) acc = acc + part[((long)k * nsys + tile + s) * nv + v];
+    C[s][v] = acc;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= npw) return;
+  for (int v0 = 0; v0 < nv; v0 += 8) {
+    cplx<T> ph[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ph[u] = v0 + u < nv ? Phi[(long)(v0 + u) * ldphi + i] : cplx<T>{0, 0};
+    for (int s0 = 0; s0 < nt; s0 += 4) {
+      cplx<T> y[4];
+      cplx<T>* Ys[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Ys[q] = s0 + q < nt ? Y + (long)sys_of(act, tile + s0 + q) * ldy : nullptr;
+        y[q] = Ys[q] ? Ys[q][i] : cplx<T>{0, 0};
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!Ys[q]) continue;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (v0 + u < nv) y[q] = y[q] - C[s0 + q][v0 + u] * ph[u];
+        Ys[q][i] = y[q];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+int proj_ksplit(int npw, int nsys) {
+  const int tiles = (nsys + 15) / 16;
+  int ks = (2048 + tiles - 1) / tiles;
+  const int kmax = (npw + 511) / 512;       // keep slices >= 512 plane waves
+  if (ks > kmax) ks = kmax;
+  return ks < 1 ? 1 : ks;
+}
+
+template <typename T>
+void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy, const int* act,
+                      int nsys, cplx<T>* part, hipStream_t s) {
+  if (nsys <= 0 || nv <= 0) return;
+  const int ks = proj_ksplit<T>(npw, nsys);
+  int kchunk = (npw + ks - 1) / ks;
+  kchunk = (kchunk + 3) & ~3;
+  const int tiles = (nsys + 15) / 16;
+  const dim3 grid(ks, tiles);
+  switch ((nv + 7) / 8) {
+    case 1: k_proj_dots<T, 1><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, kchunk, part); break;
+    case 2: k_proj_dots<T, 2><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, kchunk, part); break;
+    case 3: k_proj_dots<T, 3><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, kchunk, part); break;
+    default: k_proj_dots<T, 4><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, kchunk, part); break;
+  }
+  k_proj_update<T><<<dim3((npw + 255) / 256, tiles), 256, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, ks,
+                                                                   part);
+}
+
+template int proj_ksplit<double>(int, int);
+template int proj_ksplit<float>(int, int);
+template void launch_proj_mfma<double>(const z64*, long, int, int, z64*, long, const int*, int, z64*, hipStream_t);
+template void launch_proj_mfma<float>(const z32*, long, int, int, z32*, long, const int*, int, z32*, hipStream_t);
+
+}  // namespace lgw

@@ -121,3 +121,12 @@ void launch_scale_cvt(const z64* in, long ldi, z32* out, long ldo, const double*
 void launch_gemm_hn(const z64* A, long lda, int m, const z64* B, long ldb, int p, long n, z64* C, z64* partial,
                     hipStream_t s);
 }  // namespace lgw
+
+namespace lgw {
+// Y <- Y - Phi (Phi^H Y) with the dots on the matrix cores; part needs
+// proj_ksplit(npw, nsys) * nsys * nv entries of workspace.
+template <typename T> int proj_ksplit(int npw, int nsys);
+template <typename T>
+void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy, const int* act,
+                      int nsys, cplx<T>* part, hipStream_t s);
+}  // namespace lgw
