@@ -70,6 +70,9 @@ typedef struct {
   double inner_tol;    /* mixed mode: relative tolerance of each FP32 inner
                           solve; default 1e-5                                 */
   int    max_sweeps;   /* mixed mode: maximum FP64 refinement sweeps; 8      */
+  int    use_graph;    /* 1 (default): batches of at most 64 systems replay the
+                          Krylov iterations between two convergence polls as
+                          a captured HIP graph                                */
 } lgw_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -104,6 +107,15 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
 lgw_status lgw_chi0_apply(lgw_ctx* ctx, int n_rhs, const lgw_c128* dV, int n_z,
                           const lgw_c128* z, lgw_c128* dn);
 
+/* chi0_apply on several independent systems (uneven grids and band counts
+ * allowed) in one call: system i applies chi0(z) of ctx[i] to its n_rhs[i]
+ * columns dV[i] and writes dn[i], exactly as lgw_chi0_apply would.  Systems
+ * run concurrently, each on its context's stream from its own host thread.
+ * Contexts must be distinct.  Returns the worst status. */
+lgw_status lgw_chi0_apply_many(int n_sys, lgw_ctx* const* ctx, const int* n_rhs,
+                               const lgw_c128* const* dV, int n_z, const lgw_c128* z,
+                               lgw_c128* const* dn);
+
 /* k steps of Lanczos with full (twice classical Gram-Schmidt)
  * reorthogonalisation on M = eps(0) - 1 = -v^1/2 chi0(0) v^1/2 (Sec. IV),
  * Euclidean norm on grid values, started from q0/|q0|.
@@ -116,6 +128,23 @@ lgw_status lgw_chi0_apply(lgw_ctx* ctx, int n_rhs, const lgw_c128* dV, int n_z,
  *                  left untouched. */
 lgw_status lgw_lanczos(lgw_ctx* ctx, const lgw_c128* q0, int k, double* alpha, double* beta,
                        lgw_c128* Q, int* k_done);
+
+/* Block Lanczos with full reorthogonalisation on M = eps(0) - 1, the block
+ * form of the Sec. IV construction: b starting vectors (rows of Q0,
+ * orthonormalised first), nblk block steps, each applying M to b vectors in
+ * one batched chi0 solve; M Q_j = Q_{j-1} B_{j-1}^H + Q_j A_j + Q_{j+1} B_j.
+ *   b in 1..16; Q0 [b][N^3]
+ *   A [nblk][b][b]  Hermitian diagonal blocks, row-major
+ *   B [nblk][b][b]  upper-triangular QR factors (non-negative diagonal);
+ *                   B[nblk-1] is the residual block
+ *   Q [nblk*b][N^3] Lanczos vectors, or NULL
+ * Each new block is orthonormalised column by column (classical
+ * Gram-Schmidt twice against all previous vectors); a column whose remaining
+ * norm is below 1e-10 of the block norm is replaced by a fixed-seed random
+ * direction orthogonal to the basis, its row of B set to zero.  A, B are
+ * always host-side-sized blocks following opts.mem. */
+lgw_status lgw_block_lanczos(lgw_ctx* ctx, int b, const lgw_c128* Q0, int nblk, lgw_c128* A,
+                             lgw_c128* B, lgw_c128* Q, int* nblk_done);
 
 /* E[z] = Q^H (eps(z) - 1) Q for every z of the list (the static basis reused
  * for all frequencies, Sec. VI).  Q [k][N^3] (orthonormal rows, e.g. from
@@ -149,8 +178,9 @@ typedef struct {
 lgw_status lgw_get_stats(const lgw_ctx* ctx, lgw_stats* out);
 const char* lgw_last_error(const lgw_ctx* ctx);
 
-/* Per-kernel timing with HIP events recorded around every launch on the
- * context's stream (off by default; enabling it resets the counters).
+/* Per-kernel timing with HIP events recorded around every batched launch
+ * (more than 64 systems) on the context's stream (off by default; enabling it
+ * resets the counters).
  * model_bytes is the algorithmic HBM traffic of those launches:
  *   LGW_K_PLANE_HV  xy-plane pass of H: column data read + written once, the
  *                   potential read once per launch;

@@ -67,3 +67,77 @@ def project(apply_Mz, Q: np.ndarray, z_list) -> np.ndarray:
         W = np.array([apply_Mz(z, q) for q in Q])          # [k, n]
         out.append(Q.conj() @ W.T)
     return np.array(out)
+
+
+def _qr_pos(W: np.ndarray):
+    """Thin QR of the columns of W (n x b) with a non-negative diagonal of R."""
+    Qf, R = np.linalg.qr(W)
+    d = np.sign(np.real(np.diag(R)))
+    d[d == 0] = 1.0
+    return Qf * d[None, :], R * d[:, None]
+
+
+def block_lanczos(apply_M, Q0: np.ndarray, nblk: int, deflate: float = 1e-10):
+    """Block Lanczos with full reorthogonalisation on Hermitian M.
+
+    Sec. IV builds a Krylov basis with one starting vector; its block form
+    starts from b vectors (rows of Q0), so that each step applies M to b
+    vectors at once:
+
+        Q_0 R_0 = Q0^T (thin QR),  B_{-1} = 0
+        W = M Q_j;  A_j = Q_j^H W (Hermitian part);  W -= Q_j A_j + Q_{j-1} B_{j-1}^H
+        W -= Q (Q^H W)  (twice, against every previous block)
+        Q_{j+1} B_j = W  (thin QR, non-negative diagonal)
+
+    so that M Q_j = Q_{j-1} B_{j-1}^H + Q_j A_j + Q_{j+1} B_j.  A column whose
+    norm after reorthogonalisation falls below `deflate` times the block norm
+    is deflated: its row of B_j is zero and a fresh direction (a fixed-seed
+    random vector orthogonalised against the basis) replaces it.
+    Returns (A [nblk, b, b], B [nblk, b, b], Q [nblk*b, n]).
+    """
+    Q0 = np.asarray(Q0, dtype=np.complex128)
+    b, n = Q0.shape
+    Qj, _ = _qr_pos(Q0.T)                       # n x b
+    blocks = [Qj]
+    As, Bs = [], []
+    Bprev = None
+    rng = np.random.default_rng(12345)
+    for j in range(nblk):
+        W = np.stack([apply_M(Qj[:, k]) for k in range(b)], axis=1)
+        Aj = Qj.conj().T @ W
+        Aj = 0.5 * (Aj + Aj.conj().T)
+        W = W - Qj @ Aj
+        if Bprev is not None:
+            W = W - blocks[-2] @ Bprev.conj().T
+        Qall = np.concatenate(blocks, axis=1)
+        for _ in range(2):
+            W = W - Qall @ (Qall.conj().T @ W)
+        wn = np.linalg.norm(W)
+        Qn, Bj = _qr_pos(W)
+        for k in range(b):
+            if abs(Bj[k, k]) < deflate * max(wn, 1e-300):
+                Bj[k, :] = 0.0
+                r = rng.standard_normal(n) + 0j
+                Qc = np.concatenate([Qall, Qn[:, :k]], axis=1)
+                for _ in range(2):
+                    r = r - Qc @ (Qc.conj().T @ r)
+                Qn[:, k] = r / np.linalg.norm(r)
+        As.append(Aj)
+        Bs.append(Bj)
+        if j + 1 < nblk:
+            blocks.append(Qn)
+            Qj = Qn
+        Bprev = Bj
+    return np.array(As), np.array(Bs), np.concatenate(blocks, axis=1).T
+
+
+def block_tridiag(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Dense block-tridiagonal T: diagonal blocks A_j, T[j+1, j] = B_j, T[j, j+1] = B_j^H."""
+    nb, b, _ = A.shape
+    T = np.zeros((nb * b, nb * b), dtype=np.complex128)
+    for j in range(nb):
+        T[j * b:(j + 1) * b, j * b:(j + 1) * b] = A[j]
+        if j + 1 < nb:
+            T[(j + 1) * b:(j + 2) * b, j * b:(j + 1) * b] = B[j]
+            T[j * b:(j + 1) * b, (j + 1) * b:(j + 2) * b] = B[j].conj().T
+    return T

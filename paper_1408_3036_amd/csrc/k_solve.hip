@@ -877,3 +877,29 @@ template void launch_proj_mfma<double>(const z64*, long, int, int, z64*, long, c
 template void launch_proj_mfma<float>(const z32*, long, int, int, z32*, long, const int*, int, z32*, hipStream_t);
 
 }  // namespace lgw
+
+namespace lgw {
+namespace {
+// W[c] -= sum_{i<m} X[i] Cm[c][i] for c < b (grid vectors of length n)
+__global__ void __launch_bounds__(256)
+k_block_sub(z64* __restrict__ W, long ldw, int b, const z64* __restrict__ X, long ldx, int m,
+            const z64* __restrict__ Cm, long n) {
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    for (int c = 0; c < b; ++c) {
+      z64 acc = W[(long)c * ldw + e];
+      const z64* cc = Cm + (long)c * m;
+      for (int i = 0; i < m; ++i) acc = acc - cc[i] * X[(long)i * ldx + e];
+      W[(long)c * ldw + e] = acc;
+    }
+  }
+}
+}  // namespace
+
+void launch_block_sub(z64* W, long ldw, int b, const z64* X, long ldx, int m, const z64* Cm, long n,
+                      hipStream_t s) {
+  if (b <= 0 || m <= 0) return;
+  long blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  k_block_sub<<<(int)blocks, 256, 0, s>>>(W, ldw, b, X, ldx, m, Cm, n);
+}
+}  // namespace lgw

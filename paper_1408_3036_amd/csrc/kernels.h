@@ -130,3 +130,9 @@ template <typename T>
 void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy, const int* act,
                       int nsys, cplx<T>* part, hipStream_t s);
 }  // namespace lgw
+
+namespace lgw {
+// W[c] -= sum_{i<m} X[i] Cm[c*m + i], c < b
+void launch_block_sub(z64* W, long ldw, int b, const z64* X, long ldx, int m, const z64* Cm, long n,
+                      hipStream_t s);
+}  // namespace lgw

@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -109,9 +110,12 @@ struct lgw_ctx {
     HIPCHK(hipEventCreate(&e));
     return e;
   }
-  // bracket one launch: call begin() before it and end() after it
-  hipEvent_t begin() {
-    if (!prof) return nullptr;
+  // bracket one launch: call begin() before it and end() after it.  Only
+  // batched launches (more than kTimedMin systems) are timed: small launch-
+  // bound batches run as replayed graphs.
+  static constexpr int kTimedMin = 64;
+  hipEvent_t begin(int nsys) {
+    if (!prof || nsys <= kTimedMin) return nullptr;
     hipEvent_t a = ev();
     HIPCHK(hipEventRecord(a, stream));
     return a;
@@ -180,13 +184,13 @@ void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const 
   const long ldt = (long)c->N * c->ncols;
   const double e = 2.0 * sizeof(T);   // bytes of one complex value
   const double cols = (double)nsys * c->N * c->ncols, sph = (double)nsys * c->npw;
-  hipEvent_t t0 = c->begin();
+  hipEvent_t t0 = c->begin(nsys);
   launch_zinv<T>(c->geom, tw_of<T>(c), X, ldx, Tb, ldt, T(1), act, nsys, c->stream);
   c->end(t0, LGW_K_ZINV, e * (sph + cols));
-  hipEvent_t t1 = c->begin();
+  hipEvent_t t1 = c->begin(nsys);
   launch_plane_hv<T>(c->geom, tw_of<T>(c), Tb, ldt, vt_of<T>(c), act, nsys, c->stream);
   c->end(t1, LGW_K_PLANE_HV, e * 2.0 * cols + sizeof(T) * (double)c->n3);
-  hipEvent_t t2 = c->begin();
+  hipEvent_t t2 = c->begin(nsys);
   launch_zfwd<T>(c->geom, tw_of<T>(c), Tb, ldt, T(1.0 / (double)c->n3), X, ldx, shift, E, lde, ecoef, Y, ldy,
                  act, nsys, c->stream);
   c->end(t2, LGW_K_ZFWD, e * (cols + (E ? 3.0 : 2.0) * sph));
@@ -197,7 +201,7 @@ template <class T>
 void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
   const int ks = proj_ksplit<T>(c->npw, nsys);
   cplx<T>* part = c->buf<cplx<T>>(sizeof(T) == 8 ? "proj.part64" : "proj.part32", (size_t)ks * nsys * c->nv);
-  hipEvent_t t0 = c->begin();
+  hipEvent_t t0 = c->begin(nsys);
   launch_proj_mfma<T>(phi_of<T>(c), c->npw, c->nv, c->npw, Y, ldy, act, nsys, part, c->stream);
   // Y read once and written once; the valence block is read once per launch
   c->end(t0, LGW_K_PROJ, 2.0 * sizeof(T) * ((2.0 * nsys + c->nv) * c->npw));
@@ -229,6 +233,21 @@ struct Batch {
   T* w2 = nullptr;
   int* act = nullptr;
   std::vector<int> h_iters, h_flags;
+  hipGraphExec_t gexec = nullptr;
+  int g_na = -1;
+  Batch() = default;
+  Batch(const Batch&) = delete;
+  Batch& operator=(const Batch&) = delete;
+  Batch(Batch&& o) noexcept { *this = std::move(o); }
+  Batch& operator=(Batch&& o) noexcept {
+    kind = o.kind; nsys = o.nsys; ld = o.ld; v = o.v; tmp = o.tmp; Tb = o.Tb; shift = o.shift; w2 = o.w2;
+    act = o.act; h_iters = std::move(o.h_iters); h_flags = std::move(o.h_flags);
+    gexec = o.gexec; g_na = o.g_na; o.gexec = nullptr;
+    return *this;
+  }
+  ~Batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+  }
 };
 
 template <class T>
@@ -257,6 +276,12 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   b.shift = c->buf<cplx<T>>(t + ".shift", nsys);
   b.w2 = c->buf<T>(t + ".w2", nsys);
   b.act = c->buf<int>(t + ".act", nsys);
+  {
+    size_t cap = 0;
+    for (int n = 1; n <= nsys; n += (n < 64 ? 1 : 16)) cap = std::max(cap, (size_t)proj_ksplit<T>(c->npw, n) * n);
+    cap = std::max(cap, (size_t)proj_ksplit<T>(c->npw, nsys) * nsys) + 64;
+    (void)c->buf<cplx<T>>(sizeof(T) == 8 ? "proj.part64" : "proj.part32", cap * c->nv);
+  }
   h2d(c, b.shift, shift.data(), nsys * sizeof(cplx<T>));
   std::vector<T> w(w2);
   w.resize(nsys, T(0));
@@ -296,21 +321,52 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     h2d(c, b.act, act.data(), act.size() * sizeof(int));
     const int chunk = std::min(check, maxit - it);
     const int na = (int)act.size();
-    for (int k = 0; k < chunk; ++k) {
-      apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na);
-      hipEvent_t t0 = c->begin();
-      if (b.kind == K_SQMR) {
-        launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
-        // reads q, t, r, d, x (q and r twice), writes r, d, x, q
-        c->end(t0, LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
-      } else {
-        launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
-        // reads p, Ap (twice), x, r (twice), p; writes x, r, p
-        c->end(t0, LGW_K_CG, 2.0 * sizeof(T) * 10.0 * na * npw);
+    auto iterate = [&](int n_it) {
+      for (int k = 0; k < n_it; ++k) {
+        apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na);
+        hipEvent_t t0 = c->begin(na);
+        if (b.kind == K_SQMR) {
+          launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
+          // reads q, t, r, d, x (q and r twice), writes r, d, x, q
+          c->end(t0, LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
+        } else {
+          launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
+          // reads p, Ap (twice), x, r (twice), p; writes x, r, p
+          c->end(t0, LGW_K_CG, 2.0 * sizeof(T) * 10.0 * na * npw);
+        }
       }
+    };
+    // Small, launch-bound batches replay their full chunks as a HIP graph
+    // (captured again whenever the active set changes); the first chunk runs
+    // eagerly so that every workspace buffer exists before capture.
+    const bool graph = c->opts.use_graph && it > 0 && chunk == check && na <= lgw_ctx::kTimedMin;
+    if (graph) {
+      if (!b.gexec || b.g_na != na) {
+        if (b.gexec) (void)hipGraphExecDestroy(b.gexec);
+        b.gexec = nullptr;
+        const long long h0 = c->tot_h;
+        hipGraph_t gr = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        iterate(chunk);
+        HIPCHK(hipStreamEndCapture(c->stream, &gr));
+        const hipError_t ie = hipGraphInstantiate(&b.gexec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        HIPCHK(ie);
+        b.g_na = na;
+        c->tot_h = h0;
+      }
+      HIPCHK(hipGraphLaunch(b.gexec, c->stream));
+      c->tot_h += (long long)chunk * na * (b.kind == K_CGSQ ? 2 : 1);
+    } else {
+      iterate(chunk);
     }
     c->check_launch();
     it += chunk;
+  }
+  if (b.gexec) {
+    (void)hipGraphExecDestroy(b.gexec);
+    b.gexec = nullptr;
+    b.g_na = -1;
   }
   HIPCHK(hipMemcpyAsync(flags.data(), b.v.flag, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipMemcpyAsync(iters.data(), b.v.iters, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -640,6 +696,7 @@ void lgw_default_opts(lgw_opts* o) {
   o->mem_budget_gb = 16.0;
   o->inner_tol = 1e-5;
   o->max_sweeps = 8;
+  o->use_graph = 1;
 }
 
 lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], double ecut, const double* V_loc,
@@ -913,6 +970,31 @@ lgw_status lgw_chi0_apply(lgw_ctx* c, int n_rhs, const lgw_c128* dV, int n_z, co
   }
 }
 
+lgw_status lgw_chi0_apply_many(int n_sys, lgw_ctx* const* ctx, const int* n_rhs, const lgw_c128* const* dV,
+                               int n_z, const lgw_c128* z, lgw_c128* const* dn) {
+  if (n_sys < 0 || (n_sys > 0 && (!ctx || !n_rhs || !dV || !dn))) return LGW_EINVAL;
+  for (int i = 0; i < n_sys; ++i) {
+    if (!ctx[i]) return LGW_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctx[j] == ctx[i]) return set_err(ctx[i], LGW_EINVAL, "a context appears twice");
+  }
+  // every system on its own stream, driven by its own host thread, so that
+  // small systems fill the GPU together
+  std::vector<lgw_status> st(n_sys, LGW_OK);
+  std::vector<std::thread> th;
+  th.reserve(n_sys);
+  for (int i = 0; i < n_sys; ++i)
+    th.emplace_back([&, i] { st[i] = lgw_chi0_apply(ctx[i], n_rhs[i], dV[i], n_z, z, dn[i]); });
+  for (auto& t : th) t.join();
+  lgw_status out = LGW_OK;
+  for (int i = 0; i < n_sys; ++i) {
+    if (st[i] == LGW_OK) continue;
+    if (st[i] != LGW_ENOCONV && st[i] != LGW_EBREAKDOWN) return st[i];
+    out = worst(out, st[i]);
+  }
+  return out;
+}
+
 lgw_status lgw_lanczos(lgw_ctx* c, const lgw_c128* q0, int k, double* alpha, double* beta, lgw_c128* Q,
                        int* k_done) {
   if (!c) return LGW_EINVAL;
@@ -1008,6 +1090,189 @@ lgw_status lgw_lanczos(lgw_ctx* c, const lgw_c128* q0, int k, double* alpha, dou
     }
     c->sync();
     *k_done = done;
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_block_lanczos(lgw_ctx* c, int b, const lgw_c128* Q0, int nblk, lgw_c128* A, lgw_c128* B,
+                             lgw_c128* Q, int* nblk_done) {
+  if (!c) return LGW_EINVAL;
+  if (b < 1 || b > 16 || nblk < 1 || !Q0 || !A || !B || !nblk_done)
+    return set_err(c, LGW_EINVAL, "invalid arguments (block size 1..16)");
+  try {
+    const long n3 = c->n3;
+    const int kmax = b * nblk;
+    const z64* d_q0 = static_cast<const z64*>(stage_in(c, Q0, (size_t)b * n3 * sizeof(z64), "io.bq0"));
+    int* d_flag = c->buf<int>("flag", 1);
+    HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), c->stream));
+    launch_finite_check(reinterpret_cast<const double*>(d_q0), 2 * (long)b * n3, d_flag, c->stream);
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    if (hflag) return set_err(c, LGW_ENAN, "non-finite value in Q0");
+    z64* Qd = c->buf<z64>("bl.Q", (size_t)(kmax + b) * n3);
+    z64* W = c->buf<z64>("bl.W", (size_t)b * n3);
+    z64* X1 = c->buf<z64>("bl.X1", (size_t)b * n3);
+    z64* Cm = c->buf<z64>("bl.Cm", (size_t)b * (kmax + b));
+    z64* part = c->buf<z64>("bl.part", (size_t)64 * (kmax + b) * b + 64 * (kmax + b));
+    double* nrm = c->buf<double>("bl.nrm", 1);
+    z64* Rcol = c->buf<z64>("bl.R", kmax + b);
+    std::vector<z64> hA((size_t)nblk * b * b), hB((size_t)nblk * b * b);
+    double wnorm_max = 0.0;
+    unsigned long long rng = 0x9E3779B97F4A7C15ull;
+    // orthonormalise the columns of blk (b grid vectors at rows `row0` of Qd)
+    // against Qd[0, row0) and each other, twice-classical Gram-Schmidt per
+    // column; returns R (upper triangular, row-major b x b)
+    auto qr_block = [&](z64* blk, int row0, std::vector<z64>& R, double wfro) {
+      R.assign((size_t)b * b, z64{0, 0});
+      for (int k = 0; k < b; ++k) {
+        z64* wk = blk + (size_t)k * n3;
+        std::vector<z64> rk(k, z64{0, 0});
+        for (int pass = 0; pass < 2; ++pass) {
+          if (k > 0) {
+            launch_dots(blk, n3, k, wk, n3, Rcol, part, c->stream);
+            launch_gemv_sub(blk, n3, k, Rcol, wk, n3, c->stream);
+            std::vector<z64> h(k);
+            HIPCHK(hipMemcpyAsync(h.data(), Rcol, k * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+            c->sync();
+            for (int i = 0; i < k; ++i) rk[i] = rk[i] + h[i];
+          }
+        }
+        launch_norm(wk, n3, nrm, part, c->stream);
+        double rkk = 0;
+        HIPCHK(hipMemcpyAsync(&rkk, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        if (!(rkk > 1e-10 * wfro)) {
+          // deflation: a fixed-seed random direction orthogonal to everything so far
+          std::vector<z64> r(n3);
+          for (long e = 0; e < n3; ++e) {
+            rng ^= rng << 13; rng ^= rng >> 7; rng ^= rng << 17;
+            r[e] = z64{(double)(rng >> 11) * 0x1.0p-53 - 0.5, 0.0};
+          }
+          h2d(c, wk, r.data(), n3 * sizeof(z64));
+          const int m = row0 + k;
+          for (int pass = 0; pass < 2; ++pass) {
+            launch_dots(Qd, n3, row0, wk, n3, Rcol, part, c->stream);
+            launch_gemv_sub(Qd, n3, row0, Rcol, wk, n3, c->stream);
+            if (k > 0) {
+              launch_dots(blk, n3, k, wk, n3, Rcol, part, c->stream);
+              launch_gemv_sub(blk, n3, k, Rcol, wk, n3, c->stream);
+            }
+          }
+          (void)m;
+          launch_norm(wk, n3, nrm, part, c->stream);
+          launch_scale_into(wk, nrm, wk, n3, c->stream);
+          for (int i = 0; i <= k; ++i) R[(size_t)i * b + k] = z64{0, 0};
+          for (int cc = k; cc < b; ++cc) R[(size_t)k * b + cc] = z64{0, 0};
+          continue;
+        }
+        launch_scale_into(wk, nrm, wk, n3, c->stream);
+        for (int i = 0; i < k; ++i) R[(size_t)i * b + k] = rk[i];
+        R[(size_t)k * b + k] = z64{rkk, 0.0};
+      }
+    };
+    // first block
+    launch_xyz_to_zxy(c->N, d_q0, n3, Qd, n3, b, false, c->stream);
+    {
+      std::vector<z64> R0;
+      qr_block(Qd, 0, R0, 1.0);
+    }
+    const lgw_c128 z0{0.0, 0.0};
+    lgw_status st = LGW_OK;
+    std::vector<int> all_it, all_fl, all_sw;
+    std::vector<double> all_res;
+    long long tot_it = 0, tot_h = 0;
+    int done = 0;
+    for (int j = 0; j < nblk; ++j) {
+      z64* Qj = Qd + (size_t)j * b * n3;
+      // W = -v^1/2 chi0(0) v^1/2 Q_j : the b columns in one batched solve
+      HIPCHK(hipMemcpyAsync(X1, Qj, (size_t)b * n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+      vhalf_inplace(c, X1, b, 1.0);
+      c->tot_iters = c->tot_h = 0;
+      st = worst(st, chi0_internal(c, b, X1, 1, &z0, W, n3));
+      all_it.insert(all_it.end(), c->st_iters.begin(), c->st_iters.end());
+      all_fl.insert(all_fl.end(), c->st_flags.begin(), c->st_flags.end());
+      all_sw.insert(all_sw.end(), c->st_sweeps.begin(), c->st_sweeps.end());
+      all_res.insert(all_res.end(), c->st_res.begin(), c->st_res.end());
+      tot_it += c->tot_iters;
+      tot_h += c->tot_h;
+      vhalf_inplace(c, W, b, -1.0);
+      // A_j = Q_j^H W (Hermitian part)
+      launch_gemm_hn(Qj, n3, b, W, n3, b, n3, Cm, part, c->stream);
+      std::vector<z64> G((size_t)b * b);
+      HIPCHK(hipMemcpyAsync(G.data(), Cm, G.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      z64* Aj = hA.data() + (size_t)j * b * b;
+      for (int r = 0; r < b; ++r)
+        for (int q = 0; q < b; ++q) {
+          // G[q][r] = <Q_j[r], W[q]> = A[r][q]
+          const z64 x = G[(size_t)q * b + r], y = G[(size_t)r * b + q];
+          Aj[(size_t)r * b + q] = z64{0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+        }
+      // W -= Q_j A_j + Q_{j-1} B_{j-1}^H
+      {
+        const int m = j > 0 ? 2 * b : b;
+        std::vector<z64> cm((size_t)b * m);
+        for (int q = 0; q < b; ++q) {
+          if (j > 0) {
+            const z64* Bp = hB.data() + (size_t)(j - 1) * b * b;
+            for (int i = 0; i < b; ++i) cm[(size_t)q * m + i] = conj(Bp[(size_t)q * b + i]);
+          }
+          for (int i = 0; i < b; ++i) cm[(size_t)q * m + (m - b) + i] = Aj[(size_t)i * b + q];
+        }
+        h2d(c, Cm, cm.data(), cm.size() * sizeof(z64));
+        launch_block_sub(W, n3, b, Qd + (size_t)(j > 0 ? j - 1 : 0) * b * n3, n3, m, Cm, n3, c->stream);
+      }
+      // full reorthogonalisation against every previous block, twice
+      const int m = (j + 1) * b;
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_gemm_hn(Qd, n3, m, W, n3, b, n3, Cm, part, c->stream);
+        launch_block_sub(W, n3, b, Qd, n3, m, Cm, n3, c->stream);
+      }
+      // B_j from the QR of W; the new block goes to rows (j+1) b of Qd
+      launch_gemm_hn(W, n3, b, W, n3, b, n3, Cm, part, c->stream);
+      std::vector<z64> gw((size_t)b * b);
+      HIPCHK(hipMemcpyAsync(gw.data(), Cm, gw.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      double wf = 0;
+      for (int q = 0; q < b; ++q) wf += gw[(size_t)q * b + q].x;
+      wf = std::sqrt(std::max(wf, 0.0));
+      wnorm_max = std::max(wnorm_max, wf);
+      z64* Qn = Qd + (size_t)(j + 1) * b * n3;
+      HIPCHK(hipMemcpyAsync(Qn, W, (size_t)b * n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+      std::vector<z64> R;
+      qr_block(Qn, (j + 1) * b, R, wf);
+      std::memcpy(hB.data() + (size_t)j * b * b, R.data(), R.size() * sizeof(z64));
+      done = j + 1;
+      if (!(wf > 1e-14 * std::max(1.0, wnorm_max)) && wf == 0.0) break;
+    }
+    c->st_iters = all_it;
+    c->st_flags = all_fl;
+    c->st_sweeps = all_sw;
+    c->st_res = all_res;
+    c->tot_iters = tot_it;
+    c->tot_h = tot_h;
+    const size_t ab = (size_t)done * b * b * sizeof(z64);
+    if (c->opts.mem == LGW_MEM_DEVICE) {
+      h2d(c, A, hA.data(), ab);
+      h2d(c, B, hB.data(), ab);
+    } else {
+      std::memcpy(A, hA.data(), ab);
+      std::memcpy(B, hB.data(), ab);
+    }
+    if (Q) {
+      const size_t qb = (size_t)done * b * n3 * sizeof(z64);
+      z64* dq = static_cast<z64*>(stage_out(c, Q, qb, "io.bQout"));
+      launch_zxy_to_xyz(c->N, Qd, n3, dq, n3, done * b, c->stream);
+      c->check_launch();
+      c->sync();
+      finish_out(c, Q, dq, qb);
+    }
+    c->sync();
+    *nblk_done = done;
     if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
     return st;
   } catch (const Fail& f) {

@@ -35,7 +35,7 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("check_every", C.c_int), ("precond", C.c_int), ("deterministic", C.c_int),
                 ("mem", C.c_int), ("stream", C.c_void_p), ("mem_budget_gb", C.c_double),
-                ("inner_tol", C.c_double), ("max_sweeps", C.c_int)]
+                ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("use_graph", C.c_int)]
 
 
 class Info(C.Structure):
@@ -78,6 +78,9 @@ def load_library():
     lib.lgw_chi0_apply.argtypes = [P, I, P, I, C.POINTER(c128), P]
     lib.lgw_lanczos.argtypes = [P, P, I, P, P, P, C.POINTER(I)]
     lib.lgw_project.argtypes = [P, I, P, I, C.POINTER(c128), P]
+    lib.lgw_block_lanczos.argtypes = [P, I, P, I, P, P, P, C.POINTER(I)]
+    lib.lgw_chi0_apply_many.argtypes = [I, C.POINTER(P), C.POINTER(I), C.POINTER(P), I,
+                                        C.POINTER(c128), C.POINTER(P)]
     lib.lgw_hpsi.argtypes = [P, I, c128, P, P]
     lib.lgw_vhalf.argtypes = [P, I, P, P]
     lib.lgw_get_info.argtypes = [P, C.POINTER(Info)]
@@ -89,7 +92,8 @@ def load_library():
     lib.lgw_last_error.restype = C.c_char_p
     lib.lgw_free.argtypes = [P]
     lib.lgw_free.restype = None
-    for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_hpsi",
+    for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_block_lanczos",
+                 "lgw_chi0_apply_many", "lgw_hpsi",
                  "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats", "lgw_profile",
                  "lgw_kernel_timing"]:
         getattr(lib, name).restype = I
@@ -113,7 +117,8 @@ class Lgw:
     def __init__(self, L, N: int, ecut: float, V, psi, eps, precision: str = "fp64",
                  tol: float | None = None, max_iter: int | None = None,
                  check_every: int | None = None, mem_budget_gb: float | None = None,
-                 inner_tol: float | None = None, max_sweeps: int | None = None):
+                 inner_tol: float | None = None, max_sweeps: int | None = None,
+                 use_graph: bool | None = None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -135,6 +140,8 @@ class Lgw:
             opts.inner_tol = inner_tol
         if max_sweeps is not None:
             opts.max_sweeps = max_sweeps
+        if use_graph is not None:
+            opts.use_graph = int(use_graph)
         self.opts = opts
         V = self._dev(V, torch.float64).reshape(-1)
         psi = self._dev(psi, torch.complex128).reshape(len(eps), -1)
@@ -202,6 +209,22 @@ class Lgw:
         n = kd.value
         return alpha[:n], beta[:n], (Q[:n] if Q is not None else None), n
 
+    def block_lanczos(self, Q0, nblk: int, want_Q: bool = True):
+        """Block Lanczos from the rows of Q0 [b, N^3]: returns A, B [nblk, b, b], Q, nblk_done."""
+        t = self.torch
+        Q0 = self._dev(Q0, t.complex128).reshape(-1, self.N ** 3)
+        b = Q0.shape[0]
+        A = t.zeros((nblk, b, b), dtype=t.complex128, device="cuda")
+        B = t.zeros((nblk, b, b), dtype=t.complex128, device="cuda")
+        Q = t.zeros((nblk * b, self.N ** 3), dtype=t.complex128, device="cuda") if want_Q else None
+        nd = C.c_int(0)
+        t.cuda.synchronize()
+        self.last_status = self._check(self.lib.lgw_block_lanczos(
+            self.ctx, b, Q0.data_ptr(), nblk, A.data_ptr(), B.data_ptr(),
+            Q.data_ptr() if Q is not None else None, C.byref(nd)))
+        n = nd.value
+        return A[:n], B[:n], (Q[:n * b] if Q is not None else None), n
+
     def project(self, Q, z):
         t = self.torch
         Q = self._dev(Q, t.complex128)
@@ -260,3 +283,28 @@ class Lgw:
                 "refine_sweeps": arr(s.refine_sweeps, np.int64),
                 "flags": arr(s.flags, np.int64), "total_iters": s.total_iters,
                 "total_happly": s.total_happly}
+
+
+def chi0_apply_many(systems, dVs, z, allow_partial: bool = False):
+    """chi0(z) on several independent systems in one call (uneven sizes allowed).
+
+    systems: list of Lgw; dVs: list of [n_rhs_i, N_i^3] complex128 tensors.
+    Returns a list of [n_z, n_rhs_i, N_i^3] tensors.
+    """
+    import torch
+    lib = load_library()
+    n = len(systems)
+    dVs = [s._dev(d, torch.complex128).reshape(-1, s.N ** 3) for s, d in zip(systems, dVs)]
+    zarr, nz = _z(z)
+    outs = [torch.empty((nz, d.shape[0], s.N ** 3), dtype=torch.complex128, device="cuda")
+            for s, d in zip(systems, dVs)]
+    ctxs = (C.c_void_p * n)(*[s.ctx.value for s in systems])
+    nr = (C.c_int * n)(*[d.shape[0] for d in dVs])
+    ins = (C.c_void_p * n)(*[d.data_ptr() for d in dVs])
+    ous = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    torch.cuda.synchronize()
+    st = lib.lgw_chi0_apply_many(n, ctxs, nr, ins, nz, zarr, ous)
+    if st != 0 and not (allow_partial and st in (5, 6)):
+        raise LgwError(st, "lgw_chi0_apply_many failed")
+    return outs
+

@@ -277,3 +277,43 @@ def test_projected_eps_at_zero_is_the_tridiagonal(small_M):
     assert np.abs(E[0] - lanczos.tridiag(a, be)).max() < 1e-12 * np.abs(a).max()
     # eps(iw) - 1 decreases along iw (Sec. VI): E(0.5i) <= E(0) in the Loewner order
     assert np.linalg.eigvalsh(E[0] - E[1]).min() > -1e-13
+
+
+# ---------------------------------------------------------------- block Lanczos
+def test_block_lanczos_with_one_vector_is_lanczos(small_M):
+    b, s, M = small_M
+    q0 = random_potentials(b.N, 1, 31)[0]
+    a, be, Q, _ = lanczos.lanczos(lambda v: M @ v, q0, 10)
+    A, B, QB = lanczos.block_lanczos(lambda v: M @ v, q0[None], 10)
+    assert np.allclose(A[:, 0, 0].real, a, atol=1e-12 * np.abs(a).max())
+    assert np.allclose(B[:, 0, 0].real, be, atol=1e-12 * np.abs(a).max())
+    # same vectors up to a unit phase per vector
+    ph = np.sum(Q.conj() * QB, axis=1)
+    assert np.allclose(np.abs(ph), 1.0, atol=1e-10)
+
+
+def test_block_lanczos_invariants(small_M):
+    b, s, M = small_M
+    Q0 = random_potentials(b.N, 4, 32)
+    A, B, Q = lanczos.block_lanczos(lambda v: M @ v, Q0, 6)
+    k = Q.shape[0]
+    assert k == 24
+    assert np.abs(Q.conj() @ Q.T - np.eye(k)).max() < 1e-13
+    T = lanczos.block_tridiag(A, B)
+    nrm = np.linalg.norm(M, 2)
+    assert np.abs(Q.conj() @ M @ Q.T - T).max() < 1e-12 * nrm
+    # R_0-free start: the first block spans the starting vectors
+    sv = np.linalg.svd(Q[:4].conj() @ (Q0 / np.linalg.norm(Q0, axis=1, keepdims=True)).T,
+                       compute_uv=False)
+    assert np.all(sv > 1e-8)
+    # block Krylov span: span(Q) = span{Q0, M Q0, M^2 Q0, ...} (first 3 blocks)
+    K = [Q0.T]
+    for _ in range(2):
+        K.append(M @ K[-1])
+    Kq, _ = np.linalg.qr(np.concatenate(K, axis=1))
+    sv = np.linalg.svd(Kq.conj().T @ Q[:12].T, compute_uv=False)
+    assert np.abs(sv - 1).max() < 1e-8
+    # B_j upper triangular with non-negative diagonal
+    for Bj in B:
+        assert np.abs(np.tril(Bj, -1)).max() == 0.0
+        assert np.all(np.diag(Bj).real >= 0)
