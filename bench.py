@@ -51,18 +51,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, mode: str):
-    """HBM bytes per launch from committed rocprofv3 --pmc counter summaries,
-    only if the kernel sources are unchanged since the counters were taken."""
+def measured_traffic(kernel: str, mode: str, model_bytes_per_launch: float):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE and WRITE_SIZE per system of the batched launches, each
+    scaled by the factor that makes a plain 1 GiB copy read as 1 GiB), scaled
+    to the systems of this run's launches; None if the transform sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_silane48.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    ent = rec.get(f"{mode}:{kernel}")
+    ent = rec.get("kernels", {}).get(f"{mode}:{kernel}")
     if not ent or rec.get("source_hash") != kernel_source_hash():
         return None
-    return ent["bytes_per_launch"]
+    systems = (model_bytes_per_launch - ent["model_bytes_fixed"]) / ent["model_bytes_per_system"]
+    return round(ent["hbm_bytes_per_system"] * systems + ent["model_bytes_fixed"])
 
 
 def cpu_baseline(w, zs_sample, x):
@@ -195,7 +199,7 @@ def main():
     dom = max(kt, key=lambda n: kt[n]["total_ms"])
     d = kt[dom]
     ach = d["model_bytes"] / (d["total_ms"] * 1e-3) / 1e9
-    trf = measured_traffic(dom, main_mode)
+    trf = measured_traffic(dom, main_mode, d["model_bytes"] / max(d["launches"], 1))
     out["roofline"] = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(ach, 1),
                        "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
                        "traffic": trf, "launches": d["launches"],

@@ -293,9 +293,13 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
 
 // Iterate the listed systems of a batch from (re)initialisation with rhs B[bidx]
 // until every one is converged, broken down or at max_iter.
+// stall > 0: a system whose residual estimate (CG |r|, SQMR tau) has not
+// halved within `stall` iterations ends (flag FLAG_MAXIT); used for the
+// single-precision inner solves, whose attainable accuracy can sit above the
+// inner tolerance for nearly resonant real-axis systems.
 template <class T>
 void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* bidx_dev, bool keep_x, double tol,
-               const std::vector<int>& start) {
+               const std::vector<int>& start, int stall = 0) {
   std::vector<int> act(start);
   if (act.empty()) return;
   const int npw = c->npw;
@@ -308,14 +312,37 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   const int check = std::max(1, c->opts.check_every);
   const int maxit = std::max(1, c->opts.max_iter);
   std::vector<int> flags(b.nsys), iters(b.nsys);
+  std::vector<T> est(b.nsys);
+  std::vector<double> best(b.nsys, 0.0);
+  std::vector<int> best_it(b.nsys, 0);
   int it = 0;
   while (!act.empty()) {
     // drop systems converged at initialisation or in the last chunk
     HIPCHK(hipMemcpyAsync(flags.data(), b.v.flag, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (stall > 0) HIPCHK(hipMemcpyAsync(est.data(), b.v.rr, b.nsys * sizeof(T), hipMemcpyDeviceToHost, c->stream));
     c->sync();
-    std::vector<int> next;
-    for (int s : act)
-      if (!flags[s]) next.push_back(s);
+    std::vector<int> next, stalled;
+    for (int s : act) {
+      if (flags[s]) continue;
+      if (stall > 0) {
+        const double e = b.kind == K_SQMR ? (double)est[s] : std::sqrt((double)est[s]);
+        if (it == 0 || e < 0.5 * best[s]) {
+          best[s] = e;
+          best_it[s] = it;
+        } else if (it - best_it[s] >= stall) {
+          stalled.push_back(s);
+          continue;
+        }
+      }
+      next.push_back(s);
+    }
+    for (int s : stalled) b.h_flags[s] = FLAG_MAXIT;
+    if (!stalled.empty()) {
+      std::vector<int> fl(stalled.size(), FLAG_MAXIT);
+      for (size_t i = 0; i < stalled.size(); ++i)
+        HIPCHK(hipMemcpyAsync(b.v.flag + stalled[i], &fl[i], sizeof(int), hipMemcpyHostToDevice, c->stream));
+      c->sync();
+    }
     act.swap(next);
     if (act.empty() || it >= maxit) break;
     h2d(c, b.act, act.data(), act.size() * sizeof(int));
@@ -501,7 +528,7 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       h2d(c, irs, h_irs.data(), nsys * sizeof(double));
       h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
       launch_scale_cvt(R, npw, R32, npw, irs, d_act, npw, (int)bad.size(), c->stream);
-      run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad);
+      run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad, 96);
       h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
       launch_cvt_32_64_axpy(b.v.x, X, rs, d_act, npw, npw, (int)bad.size(), c->stream);
       true_resid(bad);
