@@ -62,7 +62,7 @@ def measured_traffic(kernel: str, mode: str, model_bytes_per_launch: float):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    ent = rec.get("kernels", {}).get(f"{mode}:{kernel}")
+    ent = rec.get("kernels", {}).get(kernel)
     if not ent or rec.get("source_hash") != kernel_source_hash():
         return None
     systems = (model_bytes_per_launch - ent["model_bytes_fixed"]) / ent["model_bytes_per_system"]
@@ -171,11 +171,24 @@ def main():
         kt = lg.kernel_timing()
         lg.profile(False)
         dn_s = lg.chi0_apply(torch.from_numpy(x_s[None]), z_s).cpu().numpy()[:, 0]
+        plain = None
+        if mode == "fp64":
+            # the plain path: one chi0 apply (one column, one frequency) per call
+            xs = torch.from_numpy(random_potentials(w.N, 2, (14083036, 2, 0, 8))).cuda()
+            zp = [z_s[0], z_s[1], z_s[2], z_s[3]]
+            lg.chi0_apply(xs[:1], zp[:1])
+            torch.cuda.synchronize()
+            tp0 = time.perf_counter()
+            for j in range(2):
+                for zz in zp:
+                    lg.chi0_apply(xs[j:j + 1], [zz])
+            torch.cuda.synchronize()
+            plain = 8 / (time.perf_counter() - tp0)
         # accuracy: eps(z)-1 projected on the FP64 path's Lanczos basis
         E_ref_basis = None
         if mode != "fp64" and "fp64" in results:
             E_ref_basis = lg.project(results["fp64"]["Q"], zs).cpu().numpy()
-        results[mode] = dict(Q=Q, E_fp64_basis=E_ref_basis,elapsed=el, lanczos_s=tl, project_s=tp, alpha=a.cpu().numpy(),
+        results[mode] = dict(Q=Q, E_fp64_basis=E_ref_basis, plain=plain,elapsed=el, lanczos_s=tl, project_s=tp, alpha=a.cpu().numpy(),
                              beta=b.cpu().numpy(), E=E.cpu().numpy(), iters=it, happly=ha,
                              npw=lg.npw, ncols=lg.ncols, kt=kt, dn_s=dn_s, k_done=kd)
         lg.close()
@@ -207,21 +220,26 @@ def main():
                        "model_bytes_per_launch": round(d["model_bytes"] / max(d["launches"], 1))}
     for mode, rr in results.items():
         kt = rr["kt"]
-        hk = ["zinv", "plane_hv", "zfwd"]
+        suf = "f64" if mode == "fp64" else "f32"
+        hk = [n for n in (f"zinv_{suf}", f"plane_hv_{suf}", f"zfwd_{suf}") if n in kt]
         h_ms = sum(kt[n]["total_ms"] for n in hk)
-        elem = 16 if mode == "fp64" else 8
-        bh = hpsi_model_bytes(rr["npw"], rr["ncols"], w.N, elem)
+        h_gbps = sum(kt[n]["model_bytes"] for n in hk) / (h_ms * 1e-3) / 1e9 if h_ms else None
         out[mode] = {"chi0_applies_per_s": round(n_apply * args.steps / rr["elapsed"], 2),
                      "lanczos_s": round(rr["lanczos_s"] / args.steps, 3),
                      "project_s": round(rr["project_s"] / args.steps, 3),
                      "krylov_iters": int(rr["iters"] / args.steps),
                      "h_applies": int(rr["happly"] / args.steps),
-                     "hpsi_GBps": round(bh * rr["happly"] / (h_ms * 1e-3) / 1e9, 1) if h_ms else None,
-                     "hpsi_frac_hbm": round(bh * rr["happly"] / (h_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
-                     if h_ms else None,
+                     "hpsi_GBps": round(h_gbps, 1) if h_gbps else None,
+                     "hpsi_frac_hbm": round(h_gbps / HBM_PEAK_GBPS, 4) if h_gbps else None,
+                     "hpsi_model_bytes": hpsi_model_bytes(rr["npw"], rr["ncols"], w.N, 16 if suf == "f64" else 8),
                      "kernel_ms": {n: round(v["total_ms"] / args.steps, 2) for n, v in kt.items()},
                      "kernel_GBps": {n: round(v["model_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
                                      for n, v in kt.items() if v["total_ms"] > 0}}
+    if "fp64" in results:
+        out["plain_fp64"] = {"chi0_applies_per_s": round(results["fp64"]["plain"], 2),
+                             "sample": "one chi0 apply (1 column, 1 frequency) per call, FP64: "
+                                       "2 columns x z = 0, 0.13i, 2i, 0.5+0.1eV*i",
+                             "value_over_plain": round(value / results["fp64"]["plain"], 2)}
     if "fp64" in results and "mixed" in results:
         f, m = results["fp64"], results["mixed"]
         Em = m["E_fp64_basis"]

@@ -152,6 +152,21 @@ lgw_status lgw_block_lanczos(lgw_ctx* ctx, int b, const lgw_c128* Q0, int nblk, 
 lgw_status lgw_project(lgw_ctx* ctx, int k, const lgw_c128* Q, int n_z, const lgw_c128* z,
                        lgw_c128* E);
 
+/* Vector-Jacobian product of lgw_chi0_apply for the real scalar
+ *   L = Re sum_{z,j,r} conj(g_dn[z][j](r)) dn[z][j](r),  dn[z][j] = chi0(z) dV[j]:
+ *   g_dV  [n_rhs][N^3] (or NULL)  dL/d Re dV + i dL/d Im dV = sum_z chi0(conj z) g_dn[z]
+ *   g_Vloc [N^3]       (or NULL)  dL/dV_loc(r), total: the valence orbitals and
+ *                                  energies relax with V_loc (first-order
+ *                                  perturbation theory of H = T + V_loc).
+ * The V_loc part solves, per column, frequency and band, the forward and the
+ * adjoint shifted systems (SQMR at z and conj z; CG at z = 0) with the
+ * Sternheimer operator of Sec. III.A, then one static Sternheimer system per
+ * band for the orbital response.  Outputs are overwritten.  Valence levels
+ * degenerate to 1e-10 Ha contribute no rotation term (it cancels). */
+lgw_status lgw_chi0_apply_vjp(lgw_ctx* ctx, int n_rhs, const lgw_c128* dV, int n_z,
+                              const lgw_c128* z, const lgw_c128* g_dn, lgw_c128* g_dV,
+                              double* g_Vloc);
+
 /* y = (H - shift) x on sphere coefficients (the operator inside every
  * Sternheimer solve, Sec. III.A), in the context's precision.
  *   x, y [n][npw] in the library's sphere order (lgw_sphere). */
@@ -186,10 +201,12 @@ const char* lgw_last_error(const lgw_ctx* ctx);
  *                   potential read once per launch;
  *   LGW_K_ZINV      sphere read + column write;  LGW_K_ZFWD column read +
  *                   sphere input read + sphere output written;
- *   LGW_K_PROJ      vector read + written, valence block read once;
+ *   LGW_K_PROJ      vector read (dots), read + written (update), valence
+ *                   block read once;
  *   LGW_K_CG / LGW_K_SQMR  vectors touched by one update. */
 enum { LGW_K_PLANE_HV = 0, LGW_K_ZINV = 1, LGW_K_ZFWD = 2, LGW_K_PROJ = 3, LGW_K_CG = 4,
-       LGW_K_SQMR = 5, LGW_NKERNELS = 6 };
+       LGW_K_SQMR = 5, LGW_NKERNELS = 6,
+       LGW_K_FP32 = 8 /* add to an id for the single-precision launches */ };
 typedef struct { long long launches; double total_ms; double model_bytes; } lgw_timing;
 lgw_status lgw_profile(lgw_ctx* ctx, int enable);
 lgw_status lgw_kernel_timing(const lgw_ctx* ctx, int kernel, lgw_timing* out);

@@ -903,3 +903,31 @@ void launch_block_sub(z64* W, long ldw, int b, const z64* X, long ldx, int m, co
   k_block_sub<<<(int)blocks, 256, 0, s>>>(W, ldw, b, X, ldx, m, Cm, n);
 }
 }  // namespace lgw
+
+namespace lgw {
+namespace {
+// out[e] += Re(c * conj(a[e]) * b[e])  (grid accumulation of the adjoint terms)
+__global__ void __launch_bounds__(256)
+k_acc_re(double* __restrict__ out, const z64* __restrict__ a, const z64* __restrict__ b, z64 c, long n) {
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    const z64 p = c * cmulc(a[e], b[e]);
+    out[e] += p.x;
+  }
+}
+__global__ void __launch_bounds__(256)
+k_conj(const z64* __restrict__ in, z64* __restrict__ out, long n) {
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) out[e] = conj(in[e]);
+}
+}  // namespace
+
+void launch_acc_re(double* out, const z64* a, const z64* b, z64 c, long n, hipStream_t s) {
+  long blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  k_acc_re<<<(int)blocks, 256, 0, s>>>(out, a, b, c, n);
+}
+void launch_conj(const z64* in, z64* out, long n, hipStream_t s) {
+  long blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  k_conj<<<(int)blocks, 256, 0, s>>>(in, out, n);
+}
+}  // namespace lgw

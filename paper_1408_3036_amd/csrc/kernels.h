@@ -136,3 +136,9 @@ namespace lgw {
 void launch_block_sub(z64* W, long ldw, int b, const z64* X, long ldx, int m, const z64* Cm, long n,
                       hipStream_t s);
 }  // namespace lgw
+
+namespace lgw {
+// out[e] += Re(c * conj(a[e]) * b[e])
+void launch_acc_re(double* out, const z64* a, const z64* b, z64 c, long n, hipStream_t s);
+void launch_conj(const z64* in, z64* out, long n, hipStream_t s);
+}  // namespace lgw

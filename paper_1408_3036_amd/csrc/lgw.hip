@@ -76,6 +76,7 @@ struct lgw_ctx {
   std::vector<double> st_res;
   long long tot_iters = 0, tot_h = 0;
   std::string err;
+  bool ones_ready = false;
   // opt-in per-kernel timing with HIP events on the context stream
   bool prof = false;
   struct Timed {
@@ -85,9 +86,9 @@ struct lgw_ctx {
   };
   std::vector<Timed> pending;
   std::vector<hipEvent_t> pool;
-  double kt_ms[LGW_NKERNELS] = {0};
-  double kt_bytes[LGW_NKERNELS] = {0};
-  long long kt_launches[LGW_NKERNELS] = {0};
+  double kt_ms[2 * LGW_K_FP32] = {0};
+  double kt_bytes[2 * LGW_K_FP32] = {0};
+  long long kt_launches[2 * LGW_K_FP32] = {0};
 
   template <class T>
   T* buf(const std::string& name, size_t count) {
@@ -186,14 +187,15 @@ void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const 
   const double cols = (double)nsys * c->N * c->ncols, sph = (double)nsys * c->npw;
   hipEvent_t t0 = c->begin(nsys);
   launch_zinv<T>(c->geom, tw_of<T>(c), X, ldx, Tb, ldt, T(1), act, nsys, c->stream);
-  c->end(t0, LGW_K_ZINV, e * (sph + cols));
+  const int pk = sizeof(T) == 4 ? LGW_K_FP32 : 0;
+  c->end(t0, pk + LGW_K_ZINV, e * (sph + cols));
   hipEvent_t t1 = c->begin(nsys);
   launch_plane_hv<T>(c->geom, tw_of<T>(c), Tb, ldt, vt_of<T>(c), act, nsys, c->stream);
-  c->end(t1, LGW_K_PLANE_HV, e * 2.0 * cols + sizeof(T) * (double)c->n3);
+  c->end(t1, pk + LGW_K_PLANE_HV, e * 2.0 * cols + sizeof(T) * (double)c->n3);
   hipEvent_t t2 = c->begin(nsys);
   launch_zfwd<T>(c->geom, tw_of<T>(c), Tb, ldt, T(1.0 / (double)c->n3), X, ldx, shift, E, lde, ecoef, Y, ldy,
                  act, nsys, c->stream);
-  c->end(t2, LGW_K_ZFWD, e * (cols + (E ? 3.0 : 2.0) * sph));
+  c->end(t2, pk + LGW_K_ZFWD, e * (cols + (E ? 3.0 : 2.0) * sph));
   c->tot_h += nsys;
 }
 
@@ -204,7 +206,8 @@ void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
   hipEvent_t t0 = c->begin(nsys);
   launch_proj_mfma<T>(phi_of<T>(c), c->npw, c->nv, c->npw, Y, ldy, act, nsys, part, c->stream);
   // Y read once and written once; the valence block is read once per launch
-  c->end(t0, LGW_K_PROJ, 2.0 * sizeof(T) * ((2.0 * nsys + c->nv) * c->npw));
+  c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_PROJ,
+         2.0 * sizeof(T) * ((3.0 * nsys + c->nv) * c->npw));
 }
 
 // Y = A X for the projected operator of the given kind (X is in range(P_c)).
@@ -355,11 +358,11 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
         if (b.kind == K_SQMR) {
           launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
           // reads q, t, r, d, x (q and r twice), writes r, d, x, q
-          c->end(t0, LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
+          c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
         } else {
           launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
           // reads p, Ap (twice), x, r (twice), p; writes x, r, p
-          c->end(t0, LGW_K_CG, 2.0 * sizeof(T) * 10.0 * na * npw);
+          c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_CG, 2.0 * sizeof(T) * 10.0 * na * npw);
         }
       }
     };
@@ -670,6 +673,201 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
     launch_plane_acc<double>(c->geom, c->d_tw64.as<z64>(), Tb, ldt, c->d_psi.as<z64>(), nv, out + (size_t)k * ldz,
                              n3, -2.0 / std::sqrt(c->omega), nrhs, false, c->stream);
   }
+  c->check_launch();
+  return st;
+}
+
+// Sphere rows Y [n][npw] -> grid vectors out [n][N^3] (zxy), Scatter.
+void scatter_rows(lgw_ctx* c, const z64* Y, int n, z64* out) {
+  const long ldt = (long)c->N * c->ncols;
+  z64* Tb = c->buf<z64>("sc.Tb", (size_t)n * ldt);
+  z64* ones = c->buf<z64>("sc.ones", c->n3);
+  if (!c->ones_ready) {
+    std::vector<z64> h1(c->n3, z64{1.0, 0.0});
+    h2d(c, ones, h1.data(), c->n3 * sizeof(z64));
+    c->ones_ready = true;
+  }
+  launch_zinv<double>(c->geom, c->d_tw64.as<z64>(), Y, c->npw, Tb, ldt, 1.0, nullptr, n, c->stream);
+  launch_plane_acc<double>(c->geom, c->d_tw64.as<z64>(), Tb, ldt, ones, 1, out, c->n3, 1.0 / std::sqrt(c->omega), n,
+                           false, c->stream);
+}
+
+// out[x * nu + u] = scale * Gather(U[u] * X[x]) for grid vectors U [nu], X [nx]
+void gather_products(lgw_ctx* c, const z64* U, int nu, const z64* X, int nx, z64* out, double scale) {
+  const long ldt = (long)c->N * c->ncols;
+  z64* Tb = c->buf<z64>("gp.Tb", (size_t)nu * nx * ldt);
+  launch_plane_pair_fwd<double>(c->geom, c->d_tw64.as<z64>(), U, nu, X, c->n3, nx, Tb, ldt, c->stream);
+  launch_zfwd<double>(c->geom, c->d_tw64.as<z64>(), Tb, ldt, scale * std::sqrt(c->omega) / (double)c->n3, nullptr, 0,
+                      nullptr, nullptr, 0, nullptr, out, c->npw, nullptr, nu * nx, c->stream);
+}
+
+// Vector-Jacobian product of dn[z][j] = chi0(z) X[j] with respect to the local
+// potential, the valence orbitals and energies relaxing with it (first-order
+// perturbation theory), for L = Re sum_{z,j,r} conj(G[z][j](r)) dn[z][j](r).
+// With f_{v,s} = P (H - e_v - s z)^-1 P b_v, a_{v,s} = P (H - e_v - s conj z)^-1 P G_v,
+// G_v = Gather(g conj(psi_v)) and ~ denoting Scatter to the grid:
+//   dL/dV = 2 Re sum conj(~a) ~f                        (H inside the resolvents)
+//         - 2 Re(sum_s a^H f) |psi_v|^2                  (e_v in the shifts)
+//         - dV Re conj(~eta_w) conj(psi_w)               (conduction part of d psi_w)
+//         + dV Re sum_k t_wk psi_k conj(psi_w)           (valence rotations)
+// where eta_w = P (H - e_w)^-1 P S_w solves one static Sternheimer system per
+// band for the total sensitivity S_w of L to the sphere coefficients of
+// conj(psi_w) (through b_v, G_v and the projector), and t_wk = S_w^H Phi_k / (e_w - e_k).
+lgw_status vjp_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c128* zl, const z64* G, double* gV) {
+  const int nv = c->nv, npw = c->npw;
+  const long n3 = c->n3;
+  const int nb = nrhs * nv;
+  const double dvol = c->dV;
+  lgw_status st = LGW_OK;
+  HIPCHK(hipMemsetAsync(gV, 0, n3 * sizeof(double), c->stream));
+  z64* Xun = c->buf<z64>("vj.Xun", (size_t)nb * npw);   // Gather(conj psi_v x_j), rows j*nv+v
+  z64* B0 = c->buf<z64>("vj.B0", (size_t)nb * npw);
+  gather_products(c, c->d_u.as<z64>(), nv, X, nrhs, Xun, 1.0);
+  HIPCHK(hipMemcpyAsync(B0, Xun, (size_t)nb * npw * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+  proj<double>(c, B0, npw, nullptr, nb);
+  z64* S = c->buf<z64>("vj.S", (size_t)nv * npw);      // total orbital sensitivity
+  HIPCHK(hipMemsetAsync(S, 0, (size_t)nv * npw * sizeof(z64), c->stream));
+  z64* Gun = c->buf<z64>("vj.Gun", (size_t)nb * npw);
+  z64* PG = c->buf<z64>("vj.PG", (size_t)nb * npw);
+  z64* Fs = c->buf<z64>("vj.F", (size_t)2 * nb * npw);  // f_{s} rows s*nb + (j*nv+v)
+  z64* As = c->buf<z64>("vj.A", (size_t)2 * nb * npw);
+  z64* Fsum = c->buf<z64>("vj.Fsum", (size_t)nb * npw);
+  z64* Asum = c->buf<z64>("vj.Asum", (size_t)nb * npw);
+  z64* gf = c->buf<z64>("vj.gf", (size_t)2 * nb * n3);  // grids of f
+  z64* ga = c->buf<z64>("vj.ga", (size_t)2 * nb * n3);  // grids of a
+  z64* cg = c->buf<z64>("vj.cg", (size_t)nrhs * n3);    // conj(g_j)
+  z64* cx = c->buf<z64>("vj.cx", (size_t)nrhs * n3);    // conj(x_j)
+  z64* tmpS = c->buf<z64>("vj.tS", (size_t)nv * npw);
+  z64* Cm = c->buf<z64>("vj.Cm", (size_t)nv * nb);
+  z64* part = c->buf<z64>("vj.part", (size_t)64 * nv * nb + 64);
+  launch_conj(X, cx, (long)nrhs * n3, c->stream);
+  const z64 zero{0, 0};
+  for (int k = 0; k < nz; ++k) {
+    const z64 zz{zl[k].re, zl[k].im};
+    const bool zero_z = zz.x == 0.0 && zz.y == 0.0;
+    const z64* Gk = G + (size_t)k * nrhs * n3;
+    gather_products(c, c->d_u.as<z64>(), nv, Gk, nrhs, Gun, 1.0);
+    HIPCHK(hipMemcpyAsync(PG, Gun, (size_t)nb * npw * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    proj<double>(c, PG, npw, nullptr, nb);
+    launch_conj(Gk, cg, (long)nrhs * n3, c->stream);
+    // forward and adjoint solves
+    const int ns = zero_z ? 1 : 2;
+    for (int which = 0; which < 2; ++which) {   // 0: forward (z), 1: adjoint (conj z)
+      std::vector<int> bidx;
+      std::vector<z64> sh;
+      std::vector<double> w2;
+      for (int si = 0; si < ns; ++si) {
+        const double sg = si == 0 ? 1.0 : -1.0;
+        const z64 zs = which == 0 ? zz : conj(zz);
+        for (int p = 0; p < nb; ++p) {
+          bidx.push_back(p);
+          sh.push_back(z64{c->eps[p % nv] + sg * zs.x, sg * zs.y});
+          w2.push_back(0.0);
+        }
+      }
+      SolveOut so;
+      solve(c, zero_z ? K_CGLIN : K_SQMR, which == 0 ? B0 : PG, bidx, sh, w2, which == 0 ? Fs : As, so);
+      for (size_t i = 0; i < so.flags.size(); ++i) {
+        if (so.flags[i] == FLAG_BREAK) st = LGW_EBREAKDOWN;
+        else if (so.flags[i] != FLAG_CONV && st == LGW_OK) st = LGW_ENOCONV;
+      }
+    }
+    const double mult = zero_z ? 2.0 : 1.0;   // at z = 0 both shifts give the same system
+    // F_v = sum_s f_s, A_v = sum_s a_s
+    if (zero_z) {
+      launch_add(Fsum, Fs, Fs, (long)nb * npw, c->stream);
+      launch_add(Asum, As, As, (long)nb * npw, c->stream);
+    } else {
+      launch_add(Fsum, Fs, Fs + (size_t)nb * npw, (long)nb * npw, c->stream);
+      launch_add(Asum, As, As + (size_t)nb * npw, (long)nb * npw, c->stream);
+    }
+    scatter_rows(c, Fs, ns * nb, gf);
+    scatter_rows(c, As, ns * nb, ga);
+    // T1: 2 Re sum_s conj(~a_s) ~f_s
+    for (int q = 0; q < ns * nb; ++q)
+      launch_acc_re(gV, ga + (size_t)q * n3, gf + (size_t)q * n3, z64{2.0 * mult, 0.0}, n3, c->stream);
+    // T2: -2 Re(sum_s a_s^H f_s) |psi_v|^2
+    {
+      std::vector<z64> e(ns * nb);
+      z64* d_e = c->buf<z64>("vj.e", ns * nb);
+      for (int q = 0; q < ns * nb; ++q)
+        launch_dots(As + (size_t)q * npw, 0, 1, Fs + (size_t)q * npw, npw, d_e + q, part, c->stream);
+      HIPCHK(hipMemcpyAsync(e.data(), d_e, e.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      std::vector<double> ev(nv, 0.0);
+      for (int q = 0; q < ns * nb; ++q) ev[q % nv] += mult * e[q].x;
+      for (int v = 0; v < nv; ++v)
+        launch_acc_re(gV, c->d_psi.as<z64>() + (size_t)v * n3, c->d_psi.as<z64>() + (size_t)v * n3,
+                      z64{-2.0 * ev[v], 0.0}, n3, c->stream);
+    }
+    // sensitivities through b_v and G_v: S_v += -(2/dV) Gather(conj(g_j) ~F_v + ~A_v conj(x_j))
+    scatter_rows(c, Fsum, nb, gf);
+    scatter_rows(c, Asum, nb, ga);
+    for (int j = 0; j < nrhs; ++j) {
+      gather_products(c, cg + (size_t)j * n3, 1, gf + (size_t)j * nv * n3, nv, tmpS, -2.0 / dvol);
+      launch_add(S, S, tmpS, (long)nv * npw, c->stream);
+      gather_products(c, cx + (size_t)j * n3, 1, ga + (size_t)j * nv * n3, nv, tmpS, -2.0 / dvol);
+      launch_add(S, S, tmpS, (long)nv * npw, c->stream);
+    }
+    // sensitivities through the projector
+    {
+      std::vector<z64> cvw((size_t)nv * nb), dvw((size_t)nb * nv), cm((size_t)nv * nb);
+      launch_gemm_hn(Gun, npw, nb, c->d_Phi.as<z64>(), npw, nv, npw, Cm, part, c->stream);   // [w][i] = Gun_i^H Phi_w
+      HIPCHK(hipMemcpyAsync(cvw.data(), Cm, cvw.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+      launch_gemm_hn(c->d_Phi.as<z64>(), npw, nv, Xun, npw, nb, npw, Cm, part, c->stream);   // [i][w] = Phi_w^H Xun_i
+      HIPCHK(hipMemcpyAsync(dvw.data(), Cm, dvw.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      for (int w = 0; w < nv; ++w)
+        for (int i = 0; i < nb; ++i) cm[(size_t)w * nb + i] = (-2.0 / dvol) * cvw[(size_t)w * nb + i];
+      h2d(c, Cm, cm.data(), cm.size() * sizeof(z64));
+      launch_block_sub(S, npw, nv, Fsum, npw, nb, Cm, npw, c->stream);
+      for (int w = 0; w < nv; ++w)
+        for (int i = 0; i < nb; ++i) cm[(size_t)w * nb + i] = (-2.0 / dvol) * conj(dvw[(size_t)i * nv + w]);
+      h2d(c, Cm, cm.data(), cm.size() * sizeof(z64));
+      launch_block_sub(S, npw, nv, Asum, npw, nb, Cm, npw, c->stream);
+    }
+    c->check_launch();
+  }
+  // orbital response: eta_w = P (H - e_w)^-1 P S_w
+  {
+    z64* PS = c->buf<z64>("vj.PS", (size_t)nv * npw);
+    z64* eta = c->buf<z64>("vj.eta", (size_t)nv * npw);
+    HIPCHK(hipMemcpyAsync(PS, S, (size_t)nv * npw * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    proj<double>(c, PS, npw, nullptr, nv);
+    std::vector<int> bidx(nv);
+    std::vector<z64> sh(nv);
+    std::vector<double> w2(nv, 0.0);
+    for (int w = 0; w < nv; ++w) {
+      bidx[w] = w;
+      sh[w] = z64{c->eps[w], 0.0};
+    }
+    SolveOut so;
+    solve(c, K_CGLIN, PS, bidx, sh, w2, eta, so);
+    for (size_t i = 0; i < so.flags.size(); ++i) {
+      if (so.flags[i] == FLAG_BREAK) st = LGW_EBREAKDOWN;
+      else if (so.flags[i] != FLAG_CONV && st == LGW_OK) st = LGW_ENOCONV;
+    }
+    z64* geta = c->buf<z64>("vj.geta", (size_t)nv * n3);
+    scatter_rows(c, eta, nv, geta);
+    for (int w = 0; w < nv; ++w)
+      launch_acc_re(gV, geta + (size_t)w * n3, c->d_u.as<z64>() + (size_t)w * n3, z64{-dvol, 0.0}, n3, c->stream);
+    // valence rotations
+    z64* tw = c->buf<z64>("vj.t", (size_t)nv * nv);
+    launch_gemm_hn(S, npw, nv, c->d_Phi.as<z64>(), npw, nv, npw, tw, part, c->stream);   // [k][w] = S_w^H Phi_k
+    std::vector<z64> t((size_t)nv * nv);
+    HIPCHK(hipMemcpyAsync(t.data(), tw, t.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    for (int w = 0; w < nv; ++w)
+      for (int kk = 0; kk < nv; ++kk) {
+        if (kk == w) continue;
+        const double de = c->eps[w] - c->eps[kk];
+        if (std::abs(de) < 1e-10) continue;   // degenerate pair: the contribution cancels
+        const z64 twk = (1.0 / de) * t[(size_t)kk * nv + w];
+        launch_acc_re(gV, c->d_u.as<z64>() + (size_t)kk * n3, c->d_u.as<z64>() + (size_t)w * n3, dvol * twk, n3,
+                      c->stream);
+      }
+  }
+  (void)zero;
   c->check_launch();
   return st;
 }
@@ -1351,6 +1549,77 @@ lgw_status lgw_project(lgw_ctx* c, int k, const lgw_c128* Q, int n_z, const lgw_
   }
 }
 
+lgw_status lgw_chi0_apply_vjp(lgw_ctx* c, int n_rhs, const lgw_c128* dV, int n_z, const lgw_c128* z,
+                              const lgw_c128* g_dn, lgw_c128* g_dV, double* g_Vloc) {
+  if (!c) return LGW_EINVAL;
+  if (n_rhs < 1 || n_z < 1 || !dV || !z || !g_dn || (!g_dV && !g_Vloc))
+    return set_err(c, LGW_EINVAL, "invalid arguments");
+  for (int k = 0; k < n_z; ++k)
+    if (!std::isfinite(z[k].re) || !std::isfinite(z[k].im)) return set_err(c, LGW_ENAN, "non-finite frequency");
+  try {
+    const long n3 = c->n3;
+    const z64* d_in = static_cast<const z64*>(stage_in(c, dV, (size_t)n_rhs * n3 * sizeof(z64), "io.vin"));
+    const z64* d_g = static_cast<const z64*>(stage_in(c, g_dn, (size_t)n_z * n_rhs * n3 * sizeof(z64), "io.vg"));
+    int* d_flag = c->buf<int>("flag", 1);
+    HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), c->stream));
+    launch_finite_check(reinterpret_cast<const double*>(d_in), 2 * (long)n_rhs * n3, d_flag, c->stream);
+    launch_finite_check(reinterpret_cast<const double*>(d_g), 2 * (long)n_z * n_rhs * n3, d_flag, c->stream);
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    if (hflag) return set_err(c, LGW_ENAN, "non-finite value in dV or g_dn");
+    z64* X = c->buf<z64>("vi.X", (size_t)n_rhs * n3);
+    z64* G = c->buf<z64>("vi.G", (size_t)n_z * n_rhs * n3);
+    launch_xyz_to_zxy(c->N, d_in, n3, X, n3, n_rhs, false, c->stream);
+    launch_xyz_to_zxy(c->N, d_g, n3, G, n3, n_z * n_rhs, false, c->stream);
+    lgw_status st = LGW_OK;
+    c->tot_iters = c->tot_h = 0;
+    if (g_dV) {
+      // dL/d dV = sum_z chi0(z)^H g = sum_z chi0(conj z) g
+      z64* acc = c->buf<z64>("vi.acc", (size_t)n_rhs * n3);
+      z64* one = c->buf<z64>("vi.one", (size_t)n_rhs * n3);
+      HIPCHK(hipMemsetAsync(acc, 0, (size_t)n_rhs * n3 * sizeof(z64), c->stream));
+      for (int k = 0; k < n_z; ++k) {
+        const lgw_c128 zb{z[k].re, -z[k].im};
+        st = worst(st, chi0_internal(c, n_rhs, G + (size_t)k * n_rhs * n3, 1, &zb, one, (long)n_rhs * n3));
+        launch_add(acc, acc, one, (long)n_rhs * n3, c->stream);
+      }
+      const size_t ob = (size_t)n_rhs * n3 * sizeof(z64);
+      z64* d_out = static_cast<z64*>(stage_out(c, g_dV, ob, "io.vgx"));
+      launch_zxy_to_xyz(c->N, acc, n3, d_out, n3, n_rhs, c->stream);
+      c->sync();
+      finish_out(c, g_dV, d_out, ob);
+    }
+    if (g_Vloc) {
+      double* gV = c->buf<double>("vi.gV", n3);
+      st = worst(st, vjp_internal(c, n_rhs, X, n_z, z, G, gV));
+      // plane-major -> [x][y][z]
+      double* d_out = static_cast<double*>(stage_out(c, g_Vloc, n3 * sizeof(double), "io.vgv"));
+      z64* tmp = c->buf<z64>("vi.tmp", n3);
+      z64* tmp2 = c->buf<z64>("vi.tmp2", n3);
+      // reuse the complex transpose on (gV, 0) pairs
+      std::vector<double> h(n3);
+      HIPCHK(hipMemcpyAsync(h.data(), gV, n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      std::vector<z64> hz(n3);
+      for (long i = 0; i < n3; ++i) hz[i] = z64{h[i], 0.0};
+      h2d(c, tmp, hz.data(), n3 * sizeof(z64));
+      launch_zxy_to_xyz(c->N, tmp, n3, tmp2, n3, 1, c->stream);
+      HIPCHK(hipMemcpyAsync(hz.data(), tmp2, n3 * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      for (long i = 0; i < n3; ++i) h[i] = hz[i].x;
+      if (c->opts.mem == LGW_MEM_DEVICE) h2d(c, d_out, h.data(), n3 * sizeof(double));
+      else std::memcpy(g_Vloc, h.data(), n3 * sizeof(double));
+    }
+    c->check_launch();
+    c->sync();
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
 lgw_status lgw_hpsi(lgw_ctx* c, int n, lgw_c128 shift, const lgw_c128* x, lgw_c128* y) {
   if (!c) return LGW_EINVAL;
   if (n < 0 || (n > 0 && (!x || !y))) return set_err(c, LGW_EINVAL, "invalid arguments");
@@ -1449,7 +1718,7 @@ lgw_status lgw_profile(lgw_ctx* c, int enable) {
     return set_err(c, f.st, f.msg);
   }
   c->prof = enable != 0;
-  for (int k = 0; k < LGW_NKERNELS; ++k) {
+  for (int k = 0; k < 2 * LGW_K_FP32; ++k) {
     c->kt_ms[k] = 0;
     c->kt_bytes[k] = 0;
     c->kt_launches[k] = 0;
@@ -1458,7 +1727,8 @@ lgw_status lgw_profile(lgw_ctx* c, int enable) {
 }
 
 lgw_status lgw_kernel_timing(const lgw_ctx* c, int kernel, lgw_timing* out) {
-  if (!c || !out || kernel < 0 || kernel >= LGW_NKERNELS) return LGW_EINVAL;
+  if (!c || !out || kernel < 0 || kernel >= 2 * LGW_K_FP32 || kernel % LGW_K_FP32 >= LGW_NKERNELS)
+    return LGW_EINVAL;
   out->launches = c->kt_launches[kernel];
   out->total_ms = c->kt_ms[kernel];
   out->model_bytes = c->kt_bytes[kernel];

@@ -79,6 +79,7 @@ def load_library():
     lib.lgw_lanczos.argtypes = [P, P, I, P, P, P, C.POINTER(I)]
     lib.lgw_project.argtypes = [P, I, P, I, C.POINTER(c128), P]
     lib.lgw_block_lanczos.argtypes = [P, I, P, I, P, P, P, C.POINTER(I)]
+    lib.lgw_chi0_apply_vjp.argtypes = [P, I, P, I, C.POINTER(c128), P, P, P]
     lib.lgw_chi0_apply_many.argtypes = [I, C.POINTER(P), C.POINTER(I), C.POINTER(P), I,
                                         C.POINTER(c128), C.POINTER(P)]
     lib.lgw_hpsi.argtypes = [P, I, c128, P, P]
@@ -93,7 +94,7 @@ def load_library():
     lib.lgw_free.argtypes = [P]
     lib.lgw_free.restype = None
     for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_block_lanczos",
-                 "lgw_chi0_apply_many", "lgw_hpsi",
+                 "lgw_chi0_apply_many", "lgw_chi0_apply_vjp", "lgw_hpsi",
                  "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats", "lgw_profile",
                  "lgw_kernel_timing"]:
         getattr(lib, name).restype = I
@@ -195,6 +196,22 @@ class Lgw:
             allow_partial)
         return out
 
+    def chi0_apply_vjp(self, dV, z, g_dn, want_dV: bool = True, want_V: bool = True):
+        """Gradients of L = Re sum conj(g_dn) * chi0_apply(dV, z):
+        returns (dL/d dV as a complex tensor [n_rhs, N^3] or None,
+                 dL/dV_loc as a float64 tensor [N^3] or None)."""
+        t = self.torch
+        dV = self._dev(dV, t.complex128).reshape(-1, self.N ** 3)
+        zarr, nz = _z(z)
+        g = self._dev(g_dn, t.complex128).reshape(nz, dV.shape[0], self.N ** 3)
+        gdV = t.empty_like(dV) if want_dV else None
+        gV = t.empty(self.N ** 3, dtype=t.float64, device="cuda") if want_V else None
+        t.cuda.synchronize()
+        self.last_status = self._check(self.lib.lgw_chi0_apply_vjp(
+            self.ctx, dV.shape[0], dV.data_ptr(), nz, zarr, g.data_ptr(),
+            gdV.data_ptr() if gdV is not None else None, gV.data_ptr() if gV is not None else None))
+        return gdV, gV
+
     def lanczos(self, q0, k: int, want_Q: bool = True):
         t = self.torch
         q0 = self._dev(q0, t.complex128).reshape(-1)
@@ -263,12 +280,15 @@ class Lgw:
         self._check(self.lib.lgw_profile(self.ctx, int(enable)))
 
     def kernel_timing(self) -> dict:
+        """{'<kernel>_f64' / '<kernel>_f32': launches, total_ms, model_bytes}."""
         out = {}
         for name, k in KERNELS.items():
-            t = Timing()
-            self._check(self.lib.lgw_kernel_timing(self.ctx, k, C.byref(t)))
-            out[name] = {"launches": t.launches, "total_ms": t.total_ms,
-                         "model_bytes": t.model_bytes}
+            for suf, off in (("f64", 0), ("f32", 8)):
+                t = Timing()
+                self._check(self.lib.lgw_kernel_timing(self.ctx, k + off, C.byref(t)))
+                if t.launches:
+                    out[f"{name}_{suf}"] = {"launches": t.launches, "total_ms": t.total_ms,
+                                            "model_bytes": t.model_bytes}
         return out
 
     def stats(self) -> dict:

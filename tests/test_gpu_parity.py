@@ -211,3 +211,48 @@ def test_chi0_apply_many_uneven_systems(sysc1):
             assert colwise_rel(many[i].cpu().numpy()[k], s.chi0(z, xs[i])) < 1e-10
     for lg in lgs:
         lg.close()
+
+
+def _oracle_loss(b, V, n_v, x, zs, g):
+    s = SOS(b, V, n_v)
+    return sum(np.real(np.vdot(g[k], s.chi0(z, x))) for k, z in enumerate(zs))
+
+
+def test_chi0_vjp_matches_oracle_and_finite_differences(sysc1):
+    w, b, s, lg = sysc1
+    rng = np.random.default_rng(40)
+    x = random_potentials(w.N, 1, 41)
+    zs = [0.0, 0.3j, 0.4 + 0.0036749j]
+    g = rng.standard_normal((len(zs), 1, w.N ** 3)) + 1j * rng.standard_normal((len(zs), 1, w.N ** 3))
+    gdV, gV = lg.chi0_apply_vjp(torch.from_numpy(x), zs, torch.from_numpy(g))
+    gdV, gV = gdV.cpu().numpy(), gV.cpu().numpy()
+    # d/d dV: sum_z chi0(conj z) g
+    ref = sum(s.chi0(np.conj(z), g[k]) for k, z in enumerate(zs))
+    assert rel(gdV, ref) < 1e-10
+    # d/dV_loc against central differences of the sum-over-states loss
+    h = 1e-5
+    pts = rng.choice(w.N ** 3, 8, replace=False)
+    fd = []
+    for p in pts:
+        Vp = w.V.copy().reshape(-1); Vp[p] += h
+        Vm = w.V.copy().reshape(-1); Vm[p] -= h
+        fd.append((_oracle_loss(b, Vp.reshape(w.V.shape), w.n_v, x[0], zs, g[:, 0])
+                   - _oracle_loss(b, Vm.reshape(w.V.shape), w.n_v, x[0], zs, g[:, 0])) / (2 * h))
+    fd = np.array(fd)
+    err = np.abs(gV[pts] - fd).max() / np.abs(fd).max()
+    print(f"vjp: g_dV rel {rel(gdV, ref):.2e}; g_V vs FD max rel {err:.2e}; |g_V| {np.abs(fd).max():.3e}")
+    assert err < 1e-5
+
+
+def test_autograd_function_routes_through_vjp(sysc1):
+    from paper_1408_3036_amd.autograd import chi0_apply
+    w, b, s, lg = sysc1
+    V = torch.from_numpy(w.V).cuda().requires_grad_(True)
+    x = torch.from_numpy(random_potentials(w.N, 1, 42)).cuda().requires_grad_(True)
+    g = torch.randn(1, 1, w.N ** 3, dtype=torch.complex128, device="cuda")
+    dn = chi0_apply(lg, V, x, [0.2j])
+    loss = (g.conj() * dn).real.sum()
+    loss.backward()
+    gdV, gV = lg.chi0_apply_vjp(x.detach(), [0.2j], g)
+    assert torch.equal(V.grad.reshape(-1), gV)
+    assert torch.equal(x.grad, gdV)
