@@ -96,6 +96,7 @@ k_cg_init(SolveVecs<T> v, const cplx<T>* __restrict__ b, long ldb, const int* __
   block_sum<T, 1>(acc, sm);
   if (threadIdx.x == 0) {
     v.rr[sys] = acc[0];
+    v.theta[sys] = T(-1);
     if (!keep_x) { v.bb[sys] = acc[0]; v.iters[sys] = 0; }
     v.flag[sys] = acc[0] == T(0) ? FLAG_CONV : 0;
   }
@@ -118,7 +119,8 @@ k_cg_step(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act) {
   }
   block_sum<T, 1>(acc, sm);
   const T pAp = acc[0];
-  const T rr = v.rr[sys];
+  const T parked = v.theta[sys];
+  const T rr = parked >= T(0) ? parked : v.rr[sys];
   if (!(pAp > T(0))) {
     if (threadIdx.x == 0) v.flag[sys] = FLAG_BREAK;
     return;
@@ -138,6 +140,7 @@ k_cg_step(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act) {
   for (int i = threadIdx.x; i < npw; i += NT) p[i] = r[i] + beta * p[i];
   if (threadIdx.x == 0) {
     v.rr[sys] = rrn;
+    v.theta[sys] = T(-1);
     v.iters[sys] += 1;
     if (rrn <= tol2 * v.bb[sys]) v.flag[sys] = FLAG_CONV;
   }
@@ -847,7 +850,7 @@ template <typename T>
 int proj_ksplit(int npw, int nsys) {
   const int tiles = (nsys + 15) / 16;
   int ks = (2048 + tiles - 1) / tiles;
-  const int kmax = (npw + 511) / 512;       // keep slices >= 512 plane waves
+  const int kmax = (npw + 63) / 64;         // keep slices >= 64 plane waves
   if (ks > kmax) ks = kmax;
   return ks < 1 ? 1 : ks;
 }
@@ -930,4 +933,117 @@ void launch_conj(const z64* in, z64* out, long n, hipStream_t s) {
   if (blocks > 2048) blocks = 2048;
   k_conj<<<(int)blocks, 256, 0, s>>>(in, out, n);
 }
+}  // namespace lgw
+
+// ====================================================================
+// Split Krylov updates for small batches: a system's vectors are spread over
+// `nsplit` workgroups, with the block reductions exchanged through a small
+// partial-sum buffer between three kernels (dots; x/r update + new norm;
+// search-direction update).  Every workgroup rebuilds the same scalars from
+// the partials in a fixed order, so the result matches the one-workgroup
+// kernels up to the summation order.
+namespace lgw {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ void slice_of(int npw, int nsplit, int& i0, int& i1) {
+  const int chunk = (npw + nsplit - 1) / nsplit;
+  i0 = blockIdx.x * chunk;
+  i1 = min(npw, i0 + chunk);
+}
+
+// Partials are indexed by active slot (blockIdx.y), not by system.
+// phase 1: part[slot][blk] = Re p^H Ap.  Workgroup 0 first commits the norm
+// the previous phase 3 parked in theta (rr itself is never written while a
+// launch may still read it).
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_cg_split1(SolveVecs<T> v, int npw, const int* __restrict__ act, int nsplit, T* __restrict__ part) {
+  __shared__ T sm[NT / 64];
+  const int sys = sys_of(act, blockIdx.y);
+  if (v.flag[sys]) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && v.theta[sys] >= T(0)) {
+    v.rr[sys] = v.theta[sys];
+    v.theta[sys] = T(-1);
+  }
+  int i0, i1;
+  slice_of<T>(npw, nsplit, i0, i1);
+  const cplx<T>* p = v.p + (long)sys * v.ld;
+  const cplx<T>* Ap = v.Ap + (long)sys * v.ld;
+  T acc[1] = {T(0)};
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) acc[0] += p[i].x * Ap[i].x + p[i].y * Ap[i].y;
+  block_sum<T, 1>(acc, sm);
+  if (threadIdx.x == 0) part[(long)blockIdx.y * nsplit + blockIdx.x] = acc[0];
+}
+
+// phase 2: alpha from the partials; x += alpha p; r -= alpha Ap; |r|^2 partials
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_cg_split2(SolveVecs<T> v, int npw, const int* __restrict__ act, int nsplit, const T* __restrict__ part,
+            T* __restrict__ part2) {
+  __shared__ T sm[NT / 64];
+  const int sys = sys_of(act, blockIdx.y);
+  if (v.flag[sys]) return;
+  T pAp = T(0);
+  for (int k = 0; k < nsplit; ++k) pAp += part[(long)blockIdx.y * nsplit + k];
+  if (!(pAp > T(0))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) v.flag[sys] = FLAG_BREAK;
+    return;
+  }
+  const T alpha = v.rr[sys] / pAp;
+  int i0, i1;
+  slice_of<T>(npw, nsplit, i0, i1);
+  cplx<T>* x = v.x + (long)sys * v.ld;
+  cplx<T>* r = v.r + (long)sys * v.ld;
+  const cplx<T>* p = v.p + (long)sys * v.ld;
+  const cplx<T>* Ap = v.Ap + (long)sys * v.ld;
+  T acc[1] = {T(0)};
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) {
+    x[i] = x[i] + alpha * p[i];
+    const cplx<T> ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    acc[0] += norm2(ri);
+  }
+  block_sum<T, 1>(acc, sm);
+  if (threadIdx.x == 0) part2[(long)blockIdx.y * nsplit + blockIdx.x] = acc[0];
+}
+
+// phase 3: beta from the partials; p = r + beta p; workgroup 0 parks the new
+// norm in theta and updates the iteration count and the convergence flag
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int nsplit, const T* __restrict__ part2) {
+  const int sys = sys_of(act, blockIdx.y);
+  if (v.flag[sys]) return;
+  T rrn = T(0);
+  for (int k = 0; k < nsplit; ++k) rrn += part2[(long)blockIdx.y * nsplit + k];
+  const T beta = rrn / v.rr[sys];
+  int i0, i1;
+  slice_of<T>(npw, nsplit, i0, i1);
+  cplx<T>* p = v.p + (long)sys * v.ld;
+  const cplx<T>* r = v.r + (long)sys * v.ld;
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) p[i] = r[i] + beta * p[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    v.theta[sys] = rrn;
+    v.iters[sys] += 1;
+    if (rrn <= tol2 * v.bb[sys]) v.flag[sys] = FLAG_CONV;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
+                          hipStream_t s) {
+  if (nsys <= 0) return;
+  const dim3 grid(nsplit, nsys);
+  k_cg_split1<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part);
+  k_cg_split2<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part, part + (long)nsys * nsplit);
+  k_cg_split3<T><<<grid, NT, 0, s>>>(v, npw, tol2, act, nsplit, part + (long)nsys * nsplit);
+}
+
+template void launch_cg_step_split<double>(const SolveVecs<double>&, int, double, const int*, int, int, double*,
+                                           hipStream_t);
+template void launch_cg_step_split<float>(const SolveVecs<float>&, int, float, const int*, int, int, float*,
+                                          hipStream_t);
 }  // namespace lgw

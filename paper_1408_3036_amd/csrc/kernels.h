@@ -142,3 +142,11 @@ namespace lgw {
 void launch_acc_re(double* out, const z64* a, const z64* b, z64 c, long n, hipStream_t s);
 void launch_conj(const z64* in, z64* out, long n, hipStream_t s);
 }  // namespace lgw
+
+namespace lgw {
+// CG update spread over nsplit workgroups per system (small batches); part
+// needs 2 * nsys * nsplit entries
+template <typename T>
+void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
+                          hipStream_t s);
+}  // namespace lgw

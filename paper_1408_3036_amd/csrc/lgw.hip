@@ -235,6 +235,8 @@ struct Batch {
   cplx<T>* shift = nullptr;
   T* w2 = nullptr;
   int* act = nullptr;
+  int nsplit = 1;
+  T* split_part = nullptr;
   std::vector<int> h_iters, h_flags;
   hipGraphExec_t gexec = nullptr;
   int g_na = -1;
@@ -244,7 +246,8 @@ struct Batch {
   Batch(Batch&& o) noexcept { *this = std::move(o); }
   Batch& operator=(Batch&& o) noexcept {
     kind = o.kind; nsys = o.nsys; ld = o.ld; v = o.v; tmp = o.tmp; Tb = o.Tb; shift = o.shift; w2 = o.w2;
-    act = o.act; h_iters = std::move(o.h_iters); h_flags = std::move(o.h_flags);
+    act = o.act; nsplit = o.nsplit; split_part = o.split_part;
+    h_iters = std::move(o.h_iters); h_flags = std::move(o.h_flags);
     gexec = o.gexec; g_na = o.g_na; o.gexec = nullptr;
     return *this;
   }
@@ -279,6 +282,8 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   b.shift = c->buf<cplx<T>>(t + ".shift", nsys);
   b.w2 = c->buf<T>(t + ".w2", nsys);
   b.act = c->buf<int>(t + ".act", nsys);
+  b.nsplit = std::max(1, std::min(64, c->npw / 1024));
+  b.split_part = c->buf<T>(t + ".split", (size_t)2 * std::min(nsys, lgw_ctx::kTimedMin) * b.nsplit);
   {
     size_t cap = 0;
     for (int n = 1; n <= nsys; n += (n < 64 ? 1 : 16)) cap = std::max(cap, (size_t)proj_ksplit<T>(c->npw, n) * n);
@@ -359,6 +364,9 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
           launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
           // reads q, t, r, d, x (q and r twice), writes r, d, x, q
           c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
+        } else if (na <= lgw_ctx::kTimedMin) {
+          // small batch: spread each system over several workgroups
+          launch_cg_step_split<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, c->stream);
         } else {
           launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
           // reads p, Ap (twice), x, r (twice), p; writes x, r, p
