@@ -167,6 +167,23 @@ lgw_status lgw_chi0_apply_vjp(lgw_ctx* ctx, int n_rhs, const lgw_c128* dV, int n
                               const lgw_c128* z, const lgw_c128* g_dn, lgw_c128* g_dV,
                               double* g_Vloc);
 
+/* Loss of the Lanczos-projected dielectric matrix and its gradient:
+ *   L = sum_z log det(I + E(z)),  E(z) = Q^H (eps(z) - 1) Q,
+ * with Q the k Lanczos vectors of eps(0) - 1 from q0 (as lgw_lanczos: the
+ * static basis of Sec. V reused for every frequency as in Sec. VI), so that
+ * sum_k log(1 + theta_k(z)) over the eigenvalues of E(z).  Every z must be
+ * i*w with w >= 0 (E Hermitian, I + E positive definite); otherwise EINVAL.
+ *   loss   [1]   (follows opts.mem)
+ *   g_Vloc [N^3] (or NULL for the loss alone) dL/dV_loc(r), overwritten; the
+ *          total derivative: Q follows eps(0) through the recursion
+ *          (reverse pass over the k steps with their reorthogonalisation,
+ *          k - 1 further applications of eps(0) - 1), and chi0 carries the
+ *          orbital response as in lgw_chi0_apply_vjp.
+ *   k_done (or NULL) number of Lanczos vectors used (< k after breakdown).
+ * EBREAKDOWN if some I + E(z) is not numerically positive definite. */
+lgw_status lgw_lanczos_loss_vjp(lgw_ctx* ctx, const lgw_c128* q0, int k, int n_z,
+                                const lgw_c128* z, double* loss, double* g_Vloc, int* k_done);
+
 /* y = (H - shift) x on sphere coefficients (the operator inside every
  * Sternheimer solve, Sec. III.A), in the context's precision.
  *   x, y [n][npw] in the library's sphere order (lgw_sphere). */

@@ -69,6 +69,24 @@ def project(apply_Mz, Q: np.ndarray, z_list) -> np.ndarray:
     return np.array(out)
 
 
+def logdet_loss(apply_Mz, q0: np.ndarray, k: int, z_list) -> float:
+    """Scalar summary of the frequency-dependent dielectric matrix in the static
+    basis: L = sum_z log det(I + E(z)) = sum_z sum_i log(1 + theta_i(z)), with
+    E(z) = Q^H (eps(z) - 1) Q over the k Lanczos vectors of eps(0) - 1 from q0
+    (Sec. V basis, reused at every imaginary frequency as in Sec. VI).  E(z)
+    is Hermitian on the imaginary axis and eps - 1 is positive semidefinite
+    there, so I + E(z) is positive definite."""
+    _, _, Q, _ = lanczos(lambda x: apply_Mz(0.0, x), q0, k)
+    total = 0.0
+    for Ez in project(apply_Mz, Q, z_list):
+        S = np.eye(len(Q)) + 0.5 * (Ez + Ez.conj().T)
+        sign, ld = np.linalg.slogdet(S)
+        if not np.real(sign) > 0:
+            raise ValueError("I + E(z) is not positive definite")
+        total += float(ld)
+    return total
+
+
 def _qr_pos(W: np.ndarray):
     """Thin QR of the columns of W (n x b) with a non-negative diagonal of R."""
     Qf, R = np.linalg.qr(W)

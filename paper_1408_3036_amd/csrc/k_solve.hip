@@ -564,6 +564,12 @@ void launch_real_xyz_to_zxy(int N, const double* in, double* out, hipStream_t s)
   k_transpose_real<<<grid, NT, 0, s>>>(in, out, A, B);
 }
 
+void launch_real_zxy_to_xyz(int N, const double* in, double* out, hipStream_t s) {
+  const int A = N, B = N * N;
+  dim3 grid((A + 31) / 32, (B + 31) / 32);
+  k_transpose_real<<<grid, NT, 0, s>>>(in, out, A, B);
+}
+
 #define LGW_INST_S(T)                                                                                  \
   template void launch_proj<T>(const cplx<T>*, long, int, int, cplx<T>*, long, const int*, int,         \
                                hipStream_t);                                                           \

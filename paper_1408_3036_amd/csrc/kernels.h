@@ -52,6 +52,7 @@ void launch_xyz_to_zxy(int N, const z64* in, long ldi, z64* out, long ldo, int n
 void launch_zxy_to_xyz(int N, const z64* in, long ldi, z64* out, long ldo, int nvec,
                        hipStream_t s);
 void launch_real_xyz_to_zxy(int N, const double* in, double* out, hipStream_t s);
+void launch_real_zxy_to_xyz(int N, const double* in, double* out, hipStream_t s);
 
 // ---- projector and solvers ----------------------------------------------
 // Y <- Y - Phi (Phi^H Y) for every listed system

@@ -721,13 +721,14 @@ void gather_products(lgw_ctx* c, const z64* U, int nu, const z64* X, int nx, z64
 // where eta_w = P (H - e_w)^-1 P S_w solves one static Sternheimer system per
 // band for the total sensitivity S_w of L to the sphere coefficients of
 // conj(psi_w) (through b_v, G_v and the projector), and t_wk = S_w^H Phi_k / (e_w - e_k).
-lgw_status vjp_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c128* zl, const z64* G, double* gV) {
+lgw_status vjp_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c128* zl, const z64* G, double* gV,
+                        bool accumulate = false) {
   const int nv = c->nv, npw = c->npw;
   const long n3 = c->n3;
   const int nb = nrhs * nv;
   const double dvol = c->dV;
   lgw_status st = LGW_OK;
-  HIPCHK(hipMemsetAsync(gV, 0, n3 * sizeof(double), c->stream));
+  if (!accumulate) HIPCHK(hipMemsetAsync(gV, 0, n3 * sizeof(double), c->stream));
   z64* Xun = c->buf<z64>("vj.Xun", (size_t)nb * npw);   // Gather(conj psi_v x_j), rows j*nv+v
   z64* B0 = c->buf<z64>("vj.B0", (size_t)nb * npw);
   gather_products(c, c->d_u.as<z64>(), nv, X, nrhs, Xun, 1.0);
@@ -909,6 +910,259 @@ lgw_status set_err(lgw_ctx* c, lgw_status st, const std::string& m) {
 }
 
 thread_local std::string g_setup_err;
+
+// Solve statistics gathered over several internal chi0 calls.
+struct SolveTally {
+  std::vector<int> it, fl, sw;
+  std::vector<double> res;
+  long long tot_it = 0, tot_h = 0;
+  void add(const lgw_ctx* c) {
+    it.insert(it.end(), c->st_iters.begin(), c->st_iters.end());
+    fl.insert(fl.end(), c->st_flags.begin(), c->st_flags.end());
+    sw.insert(sw.end(), c->st_sweeps.begin(), c->st_sweeps.end());
+    res.insert(res.end(), c->st_res.begin(), c->st_res.end());
+    tot_it += c->tot_iters;
+    tot_h += c->tot_h;
+  }
+  void store(lgw_ctx* c) const {
+    c->st_iters = it;
+    c->st_flags = fl;
+    c->st_sweeps = sw;
+    c->st_res = res;
+    c->tot_iters = tot_it;
+    c->tot_h = tot_h;
+  }
+};
+
+// w = (eps(0) - 1) q = -v^1/2 chi0(0) v^1/2 q on plane-major grids
+lgw_status apply_M0(lgw_ctx* c, const z64* q, z64* w, SolveTally& tally) {
+  const long n3 = c->n3;
+  z64* x1 = c->buf<z64>("lz.x1", n3);
+  HIPCHK(hipMemcpyAsync(x1, q, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+  vhalf_inplace(c, x1, 1, 1.0);
+  const lgw_c128 z0{0.0, 0.0};
+  c->tot_iters = c->tot_h = 0;
+  const lgw_status st = chi0_internal(c, 1, x1, 1, &z0, w, n3);
+  tally.add(c);
+  vhalf_inplace(c, w, 1, -1.0);
+  return st;
+}
+
+// Checks the starting vector (user layout, opts.mem) and writes q_0 = q0/|q0|
+// plane-major into Q.
+lgw_status lanczos_start(lgw_ctx* c, const lgw_c128* q0, z64* Q) {
+  const long n3 = c->n3;
+  const z64* d_q0 = static_cast<const z64*>(stage_in(c, q0, n3 * sizeof(z64), "io.q0"));
+  int* d_flag = c->buf<int>("flag", 1);
+  HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), c->stream));
+  launch_finite_check(reinterpret_cast<const double*>(d_q0), 2 * n3, d_flag, c->stream);
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  if (hflag) return set_err(c, LGW_ENAN, "non-finite value in q0");
+  z64* w = c->buf<z64>("lz.w", n3);
+  z64* part = c->buf<z64>("lz.part0", 64);
+  double* d_nrm = c->buf<double>("lz.nrm", 1);
+  launch_xyz_to_zxy(c->N, d_q0, n3, w, n3, 1, false, c->stream);
+  launch_norm(w, n3, d_nrm, part, c->stream);
+  double h_nrm = 0;
+  HIPCHK(hipMemcpyAsync(&h_nrm, d_nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  if (!(h_nrm > 0)) return set_err(c, LGW_EINVAL, "q0 is zero");
+  launch_scale_into(w, d_nrm, Q, n3, c->stream);
+  return LGW_OK;
+}
+
+// Lanczos with full reorthogonalisation on eps(0) - 1 (Sec. V): from q_0 in
+// Q[0], for j < k: w = M q_j, alpha_j = Re <q_j, w>, w -= alpha_j q_j +
+// beta_{j-1} q_{j-1}, then classical Gram-Schmidt against q_0..q_j twice,
+// beta_j = |w|, q_{j+1} = w / beta_j.  Stops early when beta_j < 1e-14
+// max|alpha|.  W0 (or null) keeps every product M q_j.
+lgw_status lanczos_core(lgw_ctx* c, int k, z64* Qd, z64* W0, double* d_alpha, double* d_beta, int* done_out) {
+  const long n3 = c->n3;
+  z64* wbuf = c->buf<z64>("lz.w", n3);
+  z64* h = c->buf<z64>("lz.h", k);
+  z64* part = c->buf<z64>("lz.part", (size_t)64 * (k + 1));
+  lgw_status st = LGW_OK;
+  SolveTally tally;
+  double amax = 0.0;
+  int done = 0;
+  for (int j = 0; j < k; ++j) {
+    z64* qj = Qd + (size_t)j * n3;
+    st = worst(st, apply_M0(c, qj, wbuf, tally));
+    if (W0) HIPCHK(hipMemcpyAsync(W0 + (size_t)j * n3, wbuf, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    launch_lanczos_alpha(qj, wbuf, n3, d_alpha + j, part, c->stream);
+    launch_lanczos_sub(wbuf, qj, j > 0 ? qj - n3 : nullptr, d_alpha + j, j > 0 ? d_beta + j - 1 : nullptr, n3,
+                       c->stream);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_dots(Qd, n3, j + 1, wbuf, n3, h, part, c->stream);
+      launch_gemv_sub(Qd, n3, j + 1, h, wbuf, n3, c->stream);
+    }
+    launch_norm(wbuf, n3, d_beta + j, part, c->stream);
+    double hb[2];
+    HIPCHK(hipMemcpyAsync(&hb[0], d_alpha + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&hb[1], d_beta + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    amax = std::max(amax, std::abs(hb[0]));
+    done = j + 1;
+    if (hb[1] < 1e-14 * amax) break;
+    if (j + 1 < k) launch_scale_into(wbuf, d_beta + j, Qd + (size_t)(j + 1) * n3, n3, c->stream);
+  }
+  tally.store(c);
+  *done_out = done;
+  return st;
+}
+
+// Cholesky of the Hermitian m x m matrix C (row-major): log det C and C^{-1}.
+// False when C is not numerically positive definite.
+bool hpd_logdet_inverse(const std::vector<z64>& C, int m, double& logdet, std::vector<z64>& inv) {
+  std::vector<z64> Lf((size_t)m * m, z64{0, 0});
+  auto at = [&](int i, int j) -> z64& { return Lf[(size_t)i * m + j]; };
+  logdet = 0.0;
+  for (int j = 0; j < m; ++j) {
+    double d = C[(size_t)j * m + j].x;
+    for (int p = 0; p < j; ++p) d -= at(j, p).x * at(j, p).x + at(j, p).y * at(j, p).y;
+    if (!(d > 0.0)) return false;
+    const double ljj = std::sqrt(d);
+    at(j, j) = z64{ljj, 0.0};
+    logdet += 2.0 * std::log(ljj);
+    for (int i = j + 1; i < m; ++i) {
+      z64 s = C[(size_t)i * m + j];
+      for (int p = 0; p < j; ++p) s = s - cmulc(at(j, p), at(i, p));   // L[i][p] conj(L[j][p])
+      at(i, j) = z64{s.x / ljj, s.y / ljj};
+    }
+  }
+  // inverse column by column: L y = e_c, L^H x = y
+  inv.assign((size_t)m * m, z64{0, 0});
+  std::vector<z64> y(m), x(m);
+  for (int cc = 0; cc < m; ++cc) {
+    for (int i = 0; i < m; ++i) {
+      z64 s = z64{i == cc ? 1.0 : 0.0, 0.0};
+      for (int p = 0; p < i; ++p) s = s - at(i, p) * y[p];
+      y[i] = z64{s.x / at(i, i).x, s.y / at(i, i).x};
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      z64 s = y[i];
+      for (int p = i + 1; p < m; ++p) s = s - cmulc(at(p, i), x[p]);   // conj(L[p][i]) x[p]
+      x[i] = z64{s.x / at(i, i).x, s.y / at(i, i).x};
+    }
+    for (int i = 0; i < m; ++i) inv[(size_t)i * m + cc] = x[i];
+  }
+  return true;
+}
+
+double re_dot(lgw_ctx* c, const z64* a, const z64* b) {
+  double* d = c->buf<double>("ll.red", 1);
+  z64* part = c->buf<z64>("ll.redp", 64);
+  launch_lanczos_alpha(a, b, c->n3, d, part, c->stream);
+  double v = 0.0;
+  HIPCHK(hipMemcpyAsync(&v, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  return v;
+}
+
+// Reverse pass through the Lanczos recursion of lanczos_core (steps j = m-2
+// .. 0 that produced q_1 .. q_{m-1}).  Qb holds dL/dQ (convention dL = Re
+// sum_j <Qb_j, dq_j>) and is consumed; the products M q_j are read from W0.
+// Every step's sensitivity to M is a pair (q_j, wb_j) with dL += Re <wb_j,
+// dM q_j>; these are handed to the chi0 VJP at z = 0 at the end, and
+// M wb_j feeds back into Qb_j (M(0) is Hermitian).
+lgw_status lanczos_reverse(lgw_ctx* c, int m, const z64* Qd, const z64* W0, const double* d_alpha,
+                           const double* d_beta, z64* Qb, double* gV, SolveTally& tally) {
+  const long n3 = c->n3;
+  std::vector<double> al(m), be(m);
+  HIPCHK(hipMemcpyAsync(al.data(), d_alpha, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(be.data(), d_beta, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  std::vector<double> bb(m, 0.0);                     // dL/d beta_j
+  z64* w1 = c->buf<z64>("lr.w1", n3);
+  z64* w2 = c->buf<z64>("lr.w2", n3);
+  z64* pr = c->buf<z64>("lr.pair", 2 * (size_t)n3);   // rows: adjoint vector, forward vector
+  z64* mw = c->buf<z64>("lr.mw", n3);
+  z64* Xp = c->buf<z64>("lr.X", (size_t)(m - 1) * n3);
+  z64* Gp = c->buf<z64>("lr.G", (size_t)(m - 1) * n3);
+  z64* cd = c->buf<z64>("lr.c", 4 * (size_t)m);       // c1, c2, d (device)
+  z64* part = c->buf<z64>("lr.part", (size_t)64 * (m + 1));
+  z64* Cm = c->buf<z64>("lr.Cm", 2 * (size_t)m);
+  std::vector<z64> hc(3 * (size_t)m), cm(2 * (size_t)m);
+  lgw_status st = LGW_OK;
+  const z64 one{1.0, 0.0};
+  auto fetch = [&](const z64* d, int n, z64* hdst) {
+    HIPCHK(hipMemcpyAsync(hdst, d, n * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+  };
+  // Qb[i] -= conj(a[i]) pr[0] + conj(b[i]) pr[1] for i <= j
+  auto rank2 = [&](int j, const z64* a, const z64* b) {
+    for (int i = 0; i <= j; ++i) {
+      cm[2 * i] = z64{a[i].x, -a[i].y};
+      cm[2 * i + 1] = z64{b[i].x, -b[i].y};
+    }
+    h2d(c, Cm, cm.data(), 2 * (j + 1) * sizeof(z64));
+    launch_block_sub(Qb, n3, j + 1, pr, n3, 2, Cm, n3, c->stream);
+  };
+  for (int j = m - 2; j >= 0; --j) {
+    const z64* qj = Qd + (size_t)j * n3;
+    const z64* qn = Qd + (size_t)(j + 1) * n3;
+    z64* qbn = Qb + (size_t)(j + 1) * n3;
+    const int nj = j + 1;
+    z64* c1 = cd;
+    z64* c2 = cd + m;
+    z64* dv = cd + 2 * m;
+    // forward intermediates of step j: w1 = M q_j - alpha_j q_j - beta_{j-1} q_{j-1},
+    // c1 = Q^H w1, w2 = w1 - Q c1, c2 = Q^H w2
+    HIPCHK(hipMemcpyAsync(w1, W0 + (size_t)j * n3, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    launch_axpby(w1, qj, z64{-al[j], 0.0}, one, n3, c->stream);
+    if (j > 0) launch_axpby(w1, qj - n3, z64{-be[j - 1], 0.0}, one, n3, c->stream);
+    launch_dots(Qd, n3, nj, w1, n3, c1, part, c->stream);
+    HIPCHK(hipMemcpyAsync(w2, w1, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    launch_gemv_sub(Qd, n3, nj, c1, w2, n3, c->stream);
+    launch_dots(Qd, n3, nj, w2, n3, c2, part, c->stream);
+    // q_{j+1} = w3 / beta_j:  wb3 = (Qb_{j+1} - q_{j+1} Re<q_{j+1}, Qb_{j+1}>) / beta_j + bb_j q_{j+1}
+    const double r = re_dot(c, qn, qbn);
+    z64* wb = pr;
+    HIPCHK(hipMemcpyAsync(wb, qbn, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    launch_axpby(wb, qn, z64{-r / be[j] + bb[j], 0.0}, z64{1.0 / be[j], 0.0}, n3, c->stream);
+    // second CGS pass w3 = w2 - Q (Q^H w2)
+    HIPCHK(hipMemcpyAsync(pr + n3, w2, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    launch_dots(Qd, n3, nj, wb, n3, dv, part, c->stream);
+    fetch(c2, nj, hc.data() + m);
+    fetch(dv, nj, hc.data() + 2 * m);
+    rank2(j, hc.data() + m, hc.data() + 2 * m);
+    launch_gemv_sub(Qd, n3, nj, dv, wb, n3, c->stream);
+    // first CGS pass w2 = w1 - Q (Q^H w1)
+    HIPCHK(hipMemcpyAsync(pr + n3, w1, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    launch_dots(Qd, n3, nj, wb, n3, dv, part, c->stream);
+    fetch(c1, nj, hc.data());
+    fetch(dv, nj, hc.data() + 2 * m);
+    rank2(j, hc.data(), hc.data() + 2 * m);
+    launch_gemv_sub(Qd, n3, nj, dv, wb, n3, c->stream);
+    // three-term step: wb is now dL/d w1
+    z64* qbj = Qb + (size_t)j * n3;
+    const double abar = -re_dot(c, qj, wb);
+    launch_axpby(qbj, wb, z64{-al[j], 0.0}, one, n3, c->stream);
+    if (j > 0) {
+      bb[j - 1] += -re_dot(c, qj - n3, wb);
+      launch_axpby(qbj - n3, wb, z64{-be[j - 1], 0.0}, one, n3, c->stream);
+    }
+    // alpha_j = Re <q_j, M q_j>: wb += abar q_j (now dL/d(M q_j)), Qb_j += abar M q_j
+    launch_axpby(wb, qj, z64{abar, 0.0}, one, n3, c->stream);
+    launch_axpby(qbj, W0 + (size_t)j * n3, z64{abar, 0.0}, one, n3, c->stream);
+    // w = M q_j: Qb_j += M wb
+    st = worst(st, apply_M0(c, wb, mw, tally));
+    launch_add(qbj, qbj, mw, n3, c->stream);
+    HIPCHK(hipMemcpyAsync(Xp + (size_t)j * n3, qj, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(Gp + (size_t)j * n3, wb, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+  }
+  // sum_j Re <wb_j, dM q_j>, M = -v^1/2 chi0(0) v^1/2: chi0 VJP with x = v^1/2 q_j, g = -v^1/2 wb_j
+  vhalf_inplace(c, Xp, m - 1, 1.0);
+  vhalf_inplace(c, Gp, m - 1, -1.0);
+  const lgw_c128 z0{0.0, 0.0};
+  c->tot_iters = c->tot_h = 0;
+  st = worst(st, vjp_internal(c, m - 1, Xp, 1, &z0, Gp, gV, true));
+  tally.add(c);
+  c->check_launch();
+  return st;
+}
 
 }  // namespace
 
@@ -1234,77 +1488,14 @@ lgw_status lgw_lanczos(lgw_ctx* c, const lgw_c128* q0, int k, double* alpha, dou
   if (k < 1 || !q0 || !alpha || !beta || !k_done) return set_err(c, LGW_EINVAL, "invalid arguments");
   try {
     const long n3 = c->n3;
-    const z64* d_q0 = static_cast<const z64*>(stage_in(c, q0, n3 * sizeof(z64), "io.q0"));
-    int* d_flag = c->buf<int>("flag", 1);
-    HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), c->stream));
-    launch_finite_check(reinterpret_cast<const double*>(d_q0), 2 * n3, d_flag, c->stream);
-    int hflag = 0;
-    HIPCHK(hipMemcpyAsync(&hflag, d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
-    if (hflag) return set_err(c, LGW_ENAN, "non-finite value in q0");
     z64* Qd = c->buf<z64>("lz.Q", (size_t)k * n3);
-    z64* w = c->buf<z64>("lz.w", n3);
-    z64* x1 = c->buf<z64>("lz.x1", n3);
-    z64* h = c->buf<z64>("lz.h", k);
-    z64* part = c->buf<z64>("lz.part", (size_t)64 * (k + 1));
-    double* ab = c->buf<double>("lz.ab", 2 * (size_t)k + 1);   // alpha[0..k), beta[0..k), norm
+    double* ab = c->buf<double>("lz.ab", 2 * (size_t)k);   // alpha[0..k), beta[0..k)
     double* d_alpha = ab;
     double* d_beta = ab + k;
-    double* d_nrm = ab + 2 * k;
-    launch_xyz_to_zxy(c->N, d_q0, n3, w, n3, 1, false, c->stream);
-    launch_norm(w, n3, d_nrm, part, c->stream);
-    double h_nrm = 0;
-    HIPCHK(hipMemcpyAsync(&h_nrm, d_nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
-    if (!(h_nrm > 0)) return set_err(c, LGW_EINVAL, "q0 is zero");
-    launch_scale_into(w, d_nrm, Qd, n3, c->stream);
-    const lgw_c128 z0{0.0, 0.0};
-    lgw_status st = LGW_OK;
-    std::vector<int> all_it, all_fl, all_sw;
-    std::vector<double> all_res;
-    long long tot_it = 0, tot_h = 0;
-    double amax = 0.0;
+    const lgw_status pre = lanczos_start(c, q0, Qd);
+    if (pre != LGW_OK) return pre;
     int done = 0;
-    for (int j = 0; j < k; ++j) {
-      z64* qj = Qd + (size_t)j * n3;
-      // w = -v^1/2 chi0(0) v^1/2 q_j
-      HIPCHK(hipMemcpyAsync(x1, qj, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
-      vhalf_inplace(c, x1, 1, 1.0);
-      c->tot_iters = c->tot_h = 0;
-      lgw_status s1 = chi0_internal(c, 1, x1, 1, &z0, w, n3);
-      st = worst(st, s1);
-      all_it.insert(all_it.end(), c->st_iters.begin(), c->st_iters.end());
-      all_fl.insert(all_fl.end(), c->st_flags.begin(), c->st_flags.end());
-      all_sw.insert(all_sw.end(), c->st_sweeps.begin(), c->st_sweeps.end());
-      all_res.insert(all_res.end(), c->st_res.begin(), c->st_res.end());
-      tot_it += c->tot_iters;
-      tot_h += c->tot_h;
-      vhalf_inplace(c, w, 1, -1.0);
-      // alpha_j = Re <q_j, w>; w -= alpha_j q_j + beta_{j-1} q_{j-1}
-      launch_lanczos_alpha(qj, w, n3, d_alpha + j, part, c->stream);
-      launch_lanczos_sub(w, qj, j > 0 ? qj - n3 : nullptr, d_alpha + j, j > 0 ? d_beta + j - 1 : nullptr, n3,
-                         c->stream);
-      // full reorthogonalisation: classical Gram-Schmidt, twice
-      for (int pass = 0; pass < 2; ++pass) {
-        launch_dots(Qd, n3, j + 1, w, n3, h, part, c->stream);
-        launch_gemv_sub(Qd, n3, j + 1, h, w, n3, c->stream);
-      }
-      launch_norm(w, n3, d_beta + j, part, c->stream);
-      double hb[2];
-      HIPCHK(hipMemcpyAsync(&hb[0], d_alpha + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipMemcpyAsync(&hb[1], d_beta + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      c->sync();
-      amax = std::max(amax, std::abs(hb[0]));
-      done = j + 1;
-      if (hb[1] < 1e-14 * amax) break;
-      if (j + 1 < k) launch_scale_into(w, d_beta + j, Qd + (size_t)(j + 1) * n3, n3, c->stream);
-    }
-    c->st_iters = all_it;
-    c->st_flags = all_fl;
-    c->st_sweeps = all_sw;
-    c->st_res = all_res;
-    c->tot_iters = tot_it;
-    c->tot_h = tot_h;
+    const lgw_status st = lanczos_core(c, k, Qd, nullptr, d_alpha, d_beta, &done);
     // outputs
     if (c->opts.mem == LGW_MEM_DEVICE) {
       HIPCHK(hipMemcpyAsync(alpha, d_alpha, done * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1323,6 +1514,109 @@ lgw_status lgw_lanczos(lgw_ctx* c, const lgw_c128* q0, int k, double* alpha, dou
     }
     c->sync();
     *k_done = done;
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_lanczos_loss_vjp(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, const lgw_c128* z, double* loss,
+                                double* g_Vloc, int* k_done) {
+  if (!c) return LGW_EINVAL;
+  if (k < 1 || n_z < 1 || !q0 || !z || !loss) return set_err(c, LGW_EINVAL, "invalid arguments");
+  for (int i = 0; i < n_z; ++i) {
+    if (!std::isfinite(z[i].re) || !std::isfinite(z[i].im)) return set_err(c, LGW_ENAN, "non-finite frequency");
+    if (z[i].re != 0.0 || z[i].im < 0.0)
+      return set_err(c, LGW_EINVAL, "loss frequencies must be i*w with w >= 0 (imaginary axis)");
+  }
+  try {
+    const long n3 = c->n3;
+    z64* Qd = c->buf<z64>("lz.Q", (size_t)k * n3);
+    z64* W0 = c->buf<z64>("ll.W0", (size_t)k * n3);
+    double* ab = c->buf<double>("lz.ab", 2 * (size_t)k);
+    const lgw_status pre = lanczos_start(c, q0, Qd);
+    if (pre != LGW_OK) return pre;
+    SolveTally tally;
+    int m = 0;
+    lgw_status st = lanczos_core(c, k, Qd, W0, ab, ab + k, &m);
+    tally.add(c);
+    const bool grad = g_Vloc != nullptr;
+    z64* X = c->buf<z64>("ll.X", (size_t)m * n3);
+    z64* Wz = c->buf<z64>("ll.Wz", (size_t)m * n3);
+    z64* Gb = grad ? c->buf<z64>("ll.Gb", (size_t)m * n3) : nullptr;   // adjoint of Q
+    double* gV = grad ? c->buf<double>("ll.gV", n3) : nullptr;
+    z64* Et = c->buf<z64>("ll.E", (size_t)m * m);
+    z64* part = c->buf<z64>("ll.part", (size_t)m * m * 64);
+    z64* Cm = c->buf<z64>("ll.Cm", (size_t)m * m);
+    if (grad) {
+      HIPCHK(hipMemsetAsync(Gb, 0, (size_t)m * n3 * sizeof(z64), c->stream));
+      HIPCHK(hipMemsetAsync(gV, 0, n3 * sizeof(double), c->stream));
+    }
+    double L = 0.0;
+    std::vector<z64> h((size_t)m * m), A((size_t)m * m), cm((size_t)m * m), cm2((size_t)m * m);
+    for (int iz = 0; iz < n_z; ++iz) {
+      // W = (eps(z) - 1) Q; the z = 0 products are the Lanczos recursion's own
+      const z64* W = W0;
+      if (z[iz].im != 0.0) {
+        HIPCHK(hipMemcpyAsync(X, Qd, (size_t)m * n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+        vhalf_inplace(c, X, m, 1.0);
+        c->tot_iters = c->tot_h = 0;
+        st = worst(st, chi0_internal(c, m, X, 1, &z[iz], Wz, (long)m * n3));
+        tally.add(c);
+        vhalf_inplace(c, Wz, m, -1.0);
+        W = Wz;
+      }
+      launch_gemm_hn(Qd, n3, m, W, n3, m, n3, Et, part, c->stream);   // Et[b][a] = <q_a, W_b>
+      HIPCHK(hipMemcpyAsync(h.data(), Et, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      // I + E, made exactly Hermitian; log det and inverse through Cholesky
+      std::vector<z64> C((size_t)m * m);
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+          const z64 eab = h[(size_t)b * m + a], eba = h[(size_t)a * m + b];
+          C[(size_t)a * m + b] = z64{0.5 * (eab.x + eba.x) + (a == b ? 1.0 : 0.0), 0.5 * (eab.y - eba.y)};
+        }
+      double ld = 0.0;
+      if (!hpd_logdet_inverse(C, m, ld, A))
+        throw Fail{LGW_EBREAKDOWN, "I + E(z) is not positive definite"};
+      L += ld;
+      if (!grad) continue;
+      // Cm[c][i] = -A[i][c]: block_sub then adds sum_i X_i A[i][c] to column c
+      for (int cc = 0; cc < m; ++cc)
+        for (int i = 0; i < m; ++i) {
+          const z64 v = A[(size_t)i * m + cc];
+          cm[(size_t)cc * m + i] = z64{-v.x, -v.y};
+        }
+      // adjoint of Q: dL/dQ = 2 sum_z (eps(z)-1) Q A_z  (A_z and eps(z)-1 Hermitian)
+      for (size_t e = 0; e < cm.size(); ++e) cm2[e] = 2.0 * cm[e];
+      h2d(c, Cm, cm2.data(), cm2.size() * sizeof(z64));
+      launch_block_sub(Gb, n3, m, W, n3, m, Cm, n3, c->stream);
+      h2d(c, Cm, cm.data(), cm.size() * sizeof(z64));   // stream-ordered after the launch above
+      // explicit term tr[A_z Q^H d(eps(z)-1) Q]: chi0 VJP with x = v^1/2 Q A_z, g = -v^1/2 Q
+      HIPCHK(hipMemsetAsync(X, 0, (size_t)m * n3 * sizeof(z64), c->stream));
+      launch_block_sub(X, n3, m, Qd, n3, m, Cm, n3, c->stream);
+      vhalf_inplace(c, X, m, 1.0);
+      HIPCHK(hipMemcpyAsync(Wz, Qd, (size_t)m * n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+      vhalf_inplace(c, Wz, m, -1.0);
+      c->tot_iters = c->tot_h = 0;
+      st = worst(st, vjp_internal(c, m, X, 1, &z[iz], Wz, gV, true));
+      tally.add(c);
+    }
+    if (grad && m > 1) {
+      st = worst(st, lanczos_reverse(c, m, Qd, W0, ab, ab + k, Gb, gV, tally));
+    }
+    tally.store(c);
+    if (c->opts.mem == LGW_MEM_DEVICE) h2d(c, loss, &L, sizeof(double));
+    else *loss = L;
+    if (grad) {
+      double* d_out = static_cast<double*>(stage_out(c, g_Vloc, n3 * sizeof(double), "io.llg"));
+      launch_real_zxy_to_xyz(c->N, gV, d_out, c->stream);
+      c->check_launch();
+      finish_out(c, g_Vloc, d_out, n3 * sizeof(double));
+    }
+    c->sync();
+    if (k_done) *k_done = m;
     if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
     return st;
   } catch (const Fail& f) {
@@ -1603,21 +1897,9 @@ lgw_status lgw_chi0_apply_vjp(lgw_ctx* c, int n_rhs, const lgw_c128* dV, int n_z
       st = worst(st, vjp_internal(c, n_rhs, X, n_z, z, G, gV));
       // plane-major -> [x][y][z]
       double* d_out = static_cast<double*>(stage_out(c, g_Vloc, n3 * sizeof(double), "io.vgv"));
-      z64* tmp = c->buf<z64>("vi.tmp", n3);
-      z64* tmp2 = c->buf<z64>("vi.tmp2", n3);
-      // reuse the complex transpose on (gV, 0) pairs
-      std::vector<double> h(n3);
-      HIPCHK(hipMemcpyAsync(h.data(), gV, n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      c->sync();
-      std::vector<z64> hz(n3);
-      for (long i = 0; i < n3; ++i) hz[i] = z64{h[i], 0.0};
-      h2d(c, tmp, hz.data(), n3 * sizeof(z64));
-      launch_zxy_to_xyz(c->N, tmp, n3, tmp2, n3, 1, c->stream);
-      HIPCHK(hipMemcpyAsync(hz.data(), tmp2, n3 * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
-      c->sync();
-      for (long i = 0; i < n3; ++i) h[i] = hz[i].x;
-      if (c->opts.mem == LGW_MEM_DEVICE) h2d(c, d_out, h.data(), n3 * sizeof(double));
-      else std::memcpy(g_Vloc, h.data(), n3 * sizeof(double));
+      launch_real_zxy_to_xyz(c->N, gV, d_out, c->stream);
+      c->check_launch();
+      finish_out(c, g_Vloc, d_out, n3 * sizeof(double));
     }
     c->check_launch();
     c->sync();

@@ -80,6 +80,7 @@ def load_library():
     lib.lgw_project.argtypes = [P, I, P, I, C.POINTER(c128), P]
     lib.lgw_block_lanczos.argtypes = [P, I, P, I, P, P, P, C.POINTER(I)]
     lib.lgw_chi0_apply_vjp.argtypes = [P, I, P, I, C.POINTER(c128), P, P, P]
+    lib.lgw_lanczos_loss_vjp.argtypes = [P, P, I, I, C.POINTER(c128), P, P, C.POINTER(I)]
     lib.lgw_chi0_apply_many.argtypes = [I, C.POINTER(P), C.POINTER(I), C.POINTER(P), I,
                                         C.POINTER(c128), C.POINTER(P)]
     lib.lgw_hpsi.argtypes = [P, I, c128, P, P]
@@ -225,6 +226,22 @@ class Lgw:
             Q.data_ptr() if Q is not None else None, C.byref(kd)))
         n = kd.value
         return alpha[:n], beta[:n], (Q[:n] if Q is not None else None), n
+
+    def lanczos_loss_vjp(self, q0, k: int, z, want_V: bool = True):
+        """L = sum_z log det(I + Q^H (eps(z)-1) Q) with Q the k-step Lanczos
+        basis of eps(0)-1 from q0, and dL/dV_loc (float64 [N^3], or None).
+        Returns (L, gradient, number of Lanczos vectors used)."""
+        t = self.torch
+        q0 = self._dev(q0, t.complex128).reshape(-1)
+        zarr, nz = _z(z)
+        loss = t.zeros(1, dtype=t.float64, device="cuda")
+        gV = t.empty(self.N ** 3, dtype=t.float64, device="cuda") if want_V else None
+        kd = C.c_int(0)
+        t.cuda.synchronize()
+        self.last_status = self._check(self.lib.lgw_lanczos_loss_vjp(
+            self.ctx, q0.data_ptr(), k, nz, zarr, loss.data_ptr(),
+            gV.data_ptr() if gV is not None else None, C.byref(kd)))
+        return float(loss.item()), gV, kd.value
 
     def block_lanczos(self, Q0, nblk: int, want_Q: bool = True):
         """Block Lanczos from the rows of Q0 [b, N^3]: returns A, B [nblk, b, b], Q, nblk_done."""

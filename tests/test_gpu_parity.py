@@ -259,3 +259,77 @@ def test_autograd_function_routes_through_vjp(sysc1):
     gdV, gV = lg.chi0_apply_vjp(x.detach(), [0.2j], g)
     assert torch.equal(V.grad.reshape(-1), gV)
     assert torch.equal(x.grad, gdV)
+
+
+C5_Z = [0.0] + list(1j * np.geomspace(0.1, 2.0, 4))
+
+
+def _oracle_lanczos_loss(b, V, n_v, q0, k, zs):
+    s = SOS(b, V, n_v)
+    return olz.logdet_loss(lambda z, v: s.M(z, v), q0, k, zs)
+
+
+def test_lanczos_loss_and_gradient(sysc1):
+    w, b, s, lg = sysc1
+    q0 = random_potentials(w.N, 1, 50)[0]
+    k = 5
+    L, gV, kd = lg.lanczos_loss_vjp(torch.from_numpy(q0), k, C5_Z)
+    gV = gV.cpu().numpy()
+    assert kd == k
+    ref = olz.logdet_loss(lambda z, v: s.M(z, v), q0, k, C5_Z)
+    assert abs(L - ref) < 1e-10 * abs(ref)
+    # the same loss from the library's own Lanczos vectors and projection
+    _, _, Q, _ = lg.lanczos(torch.from_numpy(q0), k)
+    E = lg.project(Q, C5_Z).cpu().numpy()
+    L2 = sum(np.linalg.slogdet(np.eye(k) + 0.5 * (e + e.conj().T))[1] for e in E)
+    assert abs(L - L2) < 1e-12 * abs(L)
+    # total derivative against Richardson-extrapolated central differences of the
+    # oracle's loss (steps h and 2h, error O(h^4)) along two smooth random
+    # directions (h = 1e-3) and at one grid point.  A single grid value moves L
+    # by ~1e-6 per Ha, so rounding in L (~1e-15 of 8.6) would swamp a 1e-3 step
+    # there: that entry takes h = 3e-2, where the response is still linear to
+    # well below the bar.
+    rng = np.random.default_rng(51)
+    r = w.L * np.stack(np.meshgrid(*[np.arange(w.N)] * 3, indexing="ij"), -1) / w.N
+    dirs = []
+    for _ in range(2):
+        d = np.zeros((w.N,) * 3)
+        for _ in range(3):
+            c = rng.uniform(0, w.L, 3)
+            dd = (r - c + w.L / 2) % w.L - w.L / 2
+            d += rng.standard_normal() * np.exp(-np.sum(dd ** 2, -1) / (2 * 1.2 ** 2))
+        dirs.append(d)
+    e = np.zeros(w.N ** 3)
+    e[rng.integers(w.N ** 3)] = 1.0
+    dirs.append(e.reshape((w.N,) * 3))
+
+    def fd(d, h):
+        return (_oracle_lanczos_loss(b, w.V + h * d, w.n_v, q0, k, C5_Z)
+                - _oracle_lanczos_loss(b, w.V - h * d, w.n_v, q0, k, C5_Z)) / (2 * h)
+    for i, (d, h) in enumerate(zip(dirs, (1e-3, 1e-3, 3e-2))):
+        ref_d = (4 * fd(d, h) - fd(d, 2 * h)) / 3
+        got = float(np.dot(gV, d.reshape(-1)))
+        err = abs(got - ref_d) / abs(ref_d)
+        print(f"lanczos loss: direction {i}: grad.d {got:.10e} FD {ref_d:.10e} rel {err:.2e}")
+        assert err < 1e-6
+
+
+def test_lanczos_loss_autograd(sysc1):
+    from paper_1408_3036_amd.autograd import lanczos_loss
+    w, b, s, lg = sysc1
+    q0 = torch.from_numpy(random_potentials(w.N, 1, 52)[0])
+    V = torch.from_numpy(w.V).cuda().requires_grad_(True)
+    L = lanczos_loss(lg, V, q0, 3, C5_Z[:2])
+    (2.0 * L).backward()
+    L_ref, gV, _ = lg.lanczos_loss_vjp(q0, 3, C5_Z[:2])
+    assert abs(float(L.detach()) - L_ref) < 1e-12 * abs(L_ref)
+    assert torch.allclose(V.grad.reshape(-1), 2.0 * gV, rtol=0, atol=1e-12 * float(gV.abs().max()))
+
+
+def test_lanczos_loss_rejects_real_axis_frequency(sysc1):
+    w, b, s, lg = sysc1
+    q0 = torch.from_numpy(random_potentials(w.N, 1, 53)[0])
+    from paper_1408_3036_amd.lgw import LgwError
+    with pytest.raises(LgwError) as ei:
+        lg.lanczos_loss_vjp(q0, 3, [0.0, 0.3 + 0.01j])
+    assert ei.value.status == 1

@@ -279,6 +279,31 @@ def test_projected_eps_at_zero_is_the_tridiagonal(small_M):
     assert np.linalg.eigvalsh(E[0] - E[1]).min() > -1e-13
 
 
+def test_logdet_loss_depends_only_on_the_krylov_space(small_M):
+    # The loss is invariant under any unitary change of basis of span(Q), so an
+    # orthonormal basis of the monomial Krylov space {q, Mq, ..., M^{k-1} q}
+    # from a QR factorisation, with dense eps(z) - 1 matrices, must give it too.
+    b, s, M = small_M
+    q0 = random_potentials(b.N, 1, 24)[0]
+    k, zs = 4, [0.0, 0.3j, 1.5j]
+    L = lanczos.logdet_loss(lambda z, v: s.M(z, v), q0, k, zs)
+    K = [q0 / np.linalg.norm(q0)]
+    for _ in range(k - 1):
+        K.append(M @ K[-1])
+    U, _ = np.linalg.qr(np.array(K).T)
+    ref = 0.0
+    for z in zs:
+        Mz = s.M_matrix(z)
+        E = U.conj().T @ (0.5 * (Mz + Mz.conj().T)) @ U
+        ref += np.sum(np.log1p(np.linalg.eigvalsh(E)))
+    assert abs(L - ref) < 1e-9 * abs(ref)
+    # at z = 0 alone the projected matrix is the Lanczos tridiagonal
+    a, be, _, _ = lanczos.lanczos(lambda v: s.M(0.0, v), q0, k)
+    T = lanczos.tridiag(a, be)
+    L0 = lanczos.logdet_loss(lambda z, v: s.M(z, v), q0, k, [0.0])
+    assert abs(L0 - np.linalg.slogdet(np.eye(k) + T)[1]) < 1e-12 * abs(L0)
+
+
 # ---------------------------------------------------------------- block Lanczos
 def test_block_lanczos_with_one_vector_is_lanczos(small_M):
     b, s, M = small_M
