@@ -4,12 +4,14 @@ One step = the whole hot path on the silane-sized molecule-in-a-box workload
 (L = 20 bohr, 48^3 grid, ecut 10 Ha, 12,053 plane waves, 5 Gaussian wells,
 4 valence bands): a 64-step Lanczos basis of eps(0) - 1 built with full
 reorthogonalisation (64 static chi0 applies), then eps(z) - 1 projected on that
-basis at 32 frequencies (16 imaginary, 0..2 Ha, by CG on the squared
-equation; 16 real, 0..1 Ha with 0.1 eV broadening, by SQMR): 64 + 32 * 64 =
-2,112 chi0 applies.  `value` is chi0 applies per second of the mixed-precision
-path (FP32 transforms and projector inside FP64 refinement); the plain FP64
-path is timed beside it.  Inputs are synthetic and resident in HBM before the
-timed region starts.
+basis at 32 frequencies (16 imaginary, 0..2 Ha; 16 real, 0..1 Ha with
+0.1 eV broadening): 64 + 32 * 64 = 2,112 chi0 applies.  `value` is chi0
+applies per second of the mixed-precision path (FP32 transforms and projector
+inside FP64 refinement) with the kinetic preconditioner and the imaginary axis
+solved as two shifted SQMR systems; the FP64 path and both precisions in the
+unpreconditioned form (squared-equation CG on the imaginary axis, plain SQMR
+on the real axis) are timed beside it.  Inputs are synthetic and resident in
+HBM before the timed region starts.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -100,6 +102,9 @@ def main():
     ap.add_argument("--lanczos", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["both", "fp64", "mixed"], default="both")
+    ap.add_argument("--solver", choices=["both", "fast", "paper"], default="both",
+                    help="fast: kinetic preconditioner + shifted pair on the imaginary axis; "
+                         "paper: unpreconditioned, squared form on the imaginary axis")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -135,9 +140,13 @@ def main():
     z_s = np.array([0.0, 0.13j, 2.0j, 0.5 + 1j * zs[-1].imag])
 
     results = {}
-    modes = ["fp64", "mixed"] if args.only == "both" else [args.only]
-    for mode in modes:
-        kw = dict(tol=1e-13) if mode == "fp64" else dict(precision="mixed", tol=1e-10)
+    precs = ["fp64", "mixed"] if args.only == "both" else [args.only]
+    forms = ["fast", "paper"] if args.solver == "both" else [args.solver]
+    runs = [(p if f == "fast" else f"{p}_paper", p, f) for f in forms for p in precs]
+    for mode, prec, form in runs:
+        kw = dict(tol=1e-13) if prec == "fp64" else dict(precision="mixed", tol=1e-10)
+        if form == "fast":
+            kw.update(precond=True, imag_form="shifted")
         lg = Lgw(w.L, w.N, w.ecut, V, psi, w.eps, **kw)
         for i in range(args.warmup):
             t = time.time()
@@ -172,7 +181,7 @@ def main():
         lg.profile(False)
         dn_s = lg.chi0_apply(torch.from_numpy(x_s[None]), z_s).cpu().numpy()[:, 0]
         plain = None
-        if mode == "fp64":
+        if mode == "fp64" or (mode == "fp64_paper" and "fp64" not in [r[0] for r in runs]):
             # the plain path: one chi0 apply (one column, one frequency) per call
             xs = torch.from_numpy(random_potentials(w.N, 2, (14083036, 2, 0, 8))).cuda()
             zp = [z_s[0], z_s[1], z_s[2], z_s[3]]
@@ -186,7 +195,7 @@ def main():
             plain = 8 / (time.perf_counter() - tp0)
         # accuracy: eps(z)-1 projected on the FP64 path's Lanczos basis
         E_ref_basis = None
-        if mode != "fp64" and "fp64" in results:
+        if prec == "mixed" and "fp64" in results:
             E_ref_basis = lg.project(results["fp64"]["Q"], zs).cpu().numpy()
         results[mode] = dict(Q=Q, E_fp64_basis=E_ref_basis, plain=plain,elapsed=el, lanczos_s=tl, project_s=tp, alpha=a.cpu().numpy(),
                              beta=b.cpu().numpy(), E=E.cpu().numpy(), iters=it, happly=ha,
@@ -194,25 +203,29 @@ def main():
         lg.close()
 
     n_apply = k + len(zs) * k
-    main_mode = "mixed" if "mixed" in results else "fp64"
+    main_mode = [m for m in ("mixed", "fp64", "mixed_paper", "fp64_paper") if m in results][0]
+    main_prec = "mixed" if main_mode.startswith("mixed") else "fp64"
     r = results[main_mode]
     ms = 1e3 * r["elapsed"] / args.steps
     value = n_apply * args.steps / r["elapsed"]
     out = {"metric": METRIC, "value": round(value, 2), "unit": "chi0-applies/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 1),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32+f64-refine" if main_mode == "mixed" else "f64", "data": "synthetic",
+           "dtype": "f32+f64-refine" if main_prec == "mixed" else "f64", "data": "synthetic",
            "config": {"workload": f"{w.name}: L={w.L} bohr, {w.N}^3 grid, ecut {w.ecut} Ha, "
                                   f"{r['npw']} PW, {w.n_wells} Gaussian wells, n_v={w.n_v}; "
                                   f"{k}-step Lanczos + eps(z)-1 at {len(zs)} z "
                                   f"(16 imaginary 0..2 Ha, 16 real 0..1 Ha + 0.1 eV)",
-                      "chi0_applies_per_step": n_apply}}
+                      "chi0_applies_per_step": n_apply,
+                      "solver": ("kinetic preconditioner (symmetric diagonal scaling), imaginary "
+                                 "axis as two shifted SQMR systems" if not main_mode.endswith("_paper")
+                                 else "unpreconditioned; squared-form CG on the imaginary axis")}}
     # roofline of the dominant kernel of the main path (HIP events, live)
     kt = r["kt"]
     dom = max(kt, key=lambda n: kt[n]["total_ms"])
     d = kt[dom]
     ach = d["model_bytes"] / (d["total_ms"] * 1e-3) / 1e9
-    trf = measured_traffic(dom, main_mode, d["model_bytes"] / max(d["launches"], 1))
+    trf = measured_traffic(dom, main_prec, d["model_bytes"] / max(d["launches"], 1))
     out["roofline"] = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(ach, 1),
                        "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
                        "traffic": trf, "launches": d["launches"],
@@ -220,11 +233,12 @@ def main():
                        "model_bytes_per_launch": round(d["model_bytes"] / max(d["launches"], 1))}
     for mode, rr in results.items():
         kt = rr["kt"]
-        suf = "f64" if mode == "fp64" else "f32"
+        suf = "f64" if mode.startswith("fp64") else "f32"
         hk = [n for n in (f"zinv_{suf}", f"plane_hv_{suf}", f"zfwd_{suf}") if n in kt]
         h_ms = sum(kt[n]["total_ms"] for n in hk)
         h_gbps = sum(kt[n]["model_bytes"] for n in hk) / (h_ms * 1e-3) / 1e9 if h_ms else None
-        out[mode] = {"chi0_applies_per_s": round(n_apply * args.steps / rr["elapsed"], 2),
+        dst = out.setdefault("paper_form", {}) if mode.endswith("_paper") else out
+        dst[mode.replace("_paper", "")] = {"chi0_applies_per_s": round(n_apply * args.steps / rr["elapsed"], 2),
                      "lanczos_s": round(rr["lanczos_s"] / args.steps, 3),
                      "project_s": round(rr["project_s"] / args.steps, 3),
                      "krylov_iters": int(rr["iters"] / args.steps),
@@ -235,11 +249,22 @@ def main():
                      "kernel_ms": {n: round(v["total_ms"] / args.steps, 2) for n, v in kt.items()},
                      "kernel_GBps": {n: round(v["model_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
                                      for n, v in kt.items() if v["total_ms"] > 0}}
-    if "fp64" in results:
-        out["plain_fp64"] = {"chi0_applies_per_s": round(results["fp64"]["plain"], 2),
-                             "sample": "one chi0 apply (1 column, 1 frequency) per call, FP64: "
-                                       "2 columns x z = 0, 0.13i, 2i, 0.5+0.1eV*i",
-                             "value_over_plain": round(value / results["fp64"]["plain"], 2)}
+    pm = "fp64" if "fp64" in results else ("fp64_paper" if "fp64_paper" in results else None)
+    if pm:
+        out["plain_fp64"] = {"chi0_applies_per_s": round(results[pm]["plain"], 2),
+                             "sample": "one chi0 apply (1 column, 1 frequency) per call, FP64 "
+                                       + ("(same solver form as the headline)" if pm == "fp64"
+                                          else "(unpreconditioned form)")
+                                       + ": 2 columns x z = 0, 0.13i, 2i, 0.5+0.1eV*i",
+                             "value_over_plain": round(value / results[pm]["plain"], 2)}
+    if "fp64" in results and "fp64_paper" in results:
+        f, p_ = results["fp64"], results["fp64_paper"]
+        out["fast_vs_paper_fp64"] = {
+            "alpha_rel": float(np.abs(f["alpha"] - p_["alpha"]).max() / np.abs(p_["alpha"]).max()),
+            "beta_rel": float(np.abs(f["beta"] - p_["beta"]).max() / np.abs(p_["alpha"]).max()),
+            "E_rel": float(max(np.linalg.norm(f["E"][i] - p_["E"][i]) / np.linalg.norm(p_["E"][i])
+                               for i in range(len(zs)))),
+            "speedup": round(p_["elapsed"] / f["elapsed"], 3)}
     if "fp64" in results and "mixed" in results:
         f, m = results["fp64"], results["mixed"]
         Em = m["E_fp64_basis"]
@@ -251,11 +276,18 @@ def main():
             "speedup": round(f["elapsed"] / m["elapsed"], 3)}
     if not args.no_cpu:
         ref, el = cpu_baseline(w, z_s, x_s)
-        out["cpu_baseline"] = {"value": round(len(z_s) / el, 4), "unit": "chi0-applies/s",
+        # more columns for the timing sample (about 10 s of one core)
+        xs_extra = random_potentials(w.N, 2, (14083036, 2, 0, 9))
+        _, el2 = cpu_baseline(w, z_s, xs_extra[0])
+        _, el3 = cpu_baseline(w, z_s, xs_extra[1])
+        n_cpu = 3 * len(z_s)
+        el_all = el + el2 + el3
+        out["cpu_baseline"] = {"value": round(n_cpu / el_all, 4), "unit": "chi0-applies/s",
                                "cores": 1, "kind": "oracle",
                                "sample": f"matrix-free FP64 Sternheimer oracle (numpy FFT, SciPy "
-                                         f"CG/GMRES) on 1 column at z = 0, 0.13i, 2i, "
-                                         f"0.5+0.1eV*i of the same workload, {el:.1f}s"}
+                                         f"CG/GMRES) on 3 columns x z = 0, 0.13i, 2i, "
+                                         f"0.5+0.1eV*i of the same workload ({n_cpu} chi0 applies), "
+                                         f"{el_all:.1f}s"}
         out["oracle_check"] = {mode: float(max(np.linalg.norm(rr["dn_s"][i] - ref[i]) /
                                                np.linalg.norm(ref[i]) for i in range(len(z_s))))
                                for mode, rr in results.items()}

@@ -59,8 +59,11 @@ typedef struct {
                           |b - A x| / |b|; default 1e-13                      */
   int    max_iter;     /* iterations per solve (per refinement sweep); 5000  */
   int    check_every;  /* iterations between host convergence polls; 8       */
-  int    precond;      /* reserved, must be 0 (no preconditioner, as in the
-                          paper's unpreconditioned CG/SQMR)                   */
+  int    precond;      /* 0 (default): none, the unpreconditioned CG/SQMR of
+                          Sec. III.  1: diagonal kinetic preconditioner,
+                          applied as the symmetric scaling S = (|K|^2/2 +
+                          precond_shift)^(-1/2) (squared form: S^2), so each
+                          Krylov solve runs on S P A P S and x = P S y       */
   int    deterministic;/* reductions are always in a fixed order; kept for
                           interface stability                                 */
   int    mem;          /* LGW_MEM_DEVICE (default) or LGW_MEM_HOST            */
@@ -73,6 +76,12 @@ typedef struct {
   int    use_graph;    /* 1 (default): batches of at most 64 systems replay the
                           Krylov iterations between two convergence polls as
                           a captured HIP graph                                */
+  double precond_shift;/* Ha, > 0: the shift of the kinetic preconditioner; 3 */
+  int    imag_form;    /* z = i*w, w > 0.  0 (default): CG on the squared form
+                          ((H-e_v)^2 + w^2) y = 2 (H-e_v) b, Eq. (P2+).  1: the
+                          two shifted systems (H - e_v -+ i w) g = b solved by
+                          SQMR as on the real axis (Eq. (P1)); fewer H
+                          applications, same chi0                             */
 } lgw_opts;
 
 /* Fill *opts with the defaults listed above. */

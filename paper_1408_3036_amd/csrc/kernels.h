@@ -121,6 +121,10 @@ void launch_scale_cvt(const z64* in, long ldi, z32* out, long ldo, const double*
                       int nsys, hipStream_t s);
 void launch_gemm_hn(const z64* A, long lda, int m, const z64* B, long ldb, int p, long n, z64* C, z64* partial,
                     hipStream_t s);
+// Y[yrow] = d .* X[xrow] for nrows rows (xrow = xi ? xi[i] : i, same for yrow)
+template <typename T>
+void launch_scale_diag(const cplx<T>* X, long ldx, const int* xi, cplx<T>* Y, long ldy, const int* yi, const T* d,
+                       int n, int nrows, hipStream_t s);
 }  // namespace lgw
 
 namespace lgw {

@@ -70,6 +70,11 @@ struct lgw_ctx {
   std::vector<double> kin, eps;
   DevBuf d_col_start, d_col_h, d_col_pos, d_kin, d_Vt, d_Vt32, d_sqrtv, d_tw64, d_tw32, d_psi, d_u, d_Phi,
       d_Phi32;
+  // kinetic preconditioner (opts.precond = 1): diagonal scalings of the
+  // linear / SQMR systems (|K|^2/2 + shift)^(-1/2) and of the squared form
+  // (|K|^2/2 + shift)^(-1), in both precisions, and min/max of each
+  DevBuf d_pre64[2], d_pre32[2];
+  double pre_ratio[2] = {1.0, 1.0};
   Geom geom{};
   std::map<std::string, DevBuf> ws;
   std::vector<int> st_iters, st_flags, st_sweeps;
@@ -165,6 +170,18 @@ template <class T>
 const cplx<T>* phi_of(lgw_ctx* c);
 template <> const z64* phi_of<double>(lgw_ctx* c) { return c->d_Phi.as<z64>(); }
 template <> const z32* phi_of<float>(lgw_ctx* c) { return c->d_Phi32.as<z32>(); }
+// preconditioner scaling for a system kind (null without preconditioning)
+template <class T>
+const T* pre_of(lgw_ctx* c, int kind);
+template <> const double* pre_of<double>(lgw_ctx* c, int kind) {
+  return c->opts.precond == 1 ? c->d_pre64[kind == K_CGSQ ? 1 : 0].as<double>() : nullptr;
+}
+template <> const float* pre_of<float>(lgw_ctx* c, int kind) {
+  return c->opts.precond == 1 ? c->d_pre32[kind == K_CGSQ ? 1 : 0].as<float>() : nullptr;
+}
+double pre_ratio(const lgw_ctx* c, int kind) {
+  return c->opts.precond == 1 ? c->pre_ratio[kind == K_CGSQ ? 1 : 0] : 1.0;
+}
 
 // host -> device copy that has finished reading the host buffer on return
 void h2d(lgw_ctx* c, void* dst, const void* src, size_t bytes) {
@@ -211,9 +228,17 @@ void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
 }
 
 // Y = A X for the projected operator of the given kind (X is in range(P_c)).
+// With a preconditioner scaling S (pre != null): Y = S P A P S X, the product
+// S X staged in ptmp.
 template <class T>
 void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, cplx<T>* Tb, long ld,
-              const cplx<T>* shift, const T* w2, const int* act, int nsys) {
+              const cplx<T>* shift, const T* w2, const int* act, int nsys, const T* pre = nullptr,
+              cplx<T>* ptmp = nullptr) {
+  if (pre) {
+    launch_scale_diag<T>(X, ld, act, ptmp, ld, act, pre, c->npw, nsys, c->stream);
+    proj<T>(c, ptmp, ld, act, nsys);
+    X = ptmp;
+  }
   if (kind == K_CGSQ) {
     happly<T>(c, X, ld, tmp, ld, shift, nullptr, 0, nullptr, Tb, act, nsys);
     proj<T>(c, tmp, ld, act, nsys);
@@ -222,6 +247,7 @@ void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, 
     happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys);
   }
   proj<T>(c, Y, ld, act, nsys);
+  if (pre) launch_scale_diag<T>(Y, ld, act, Y, ld, act, pre, c->npw, nsys, c->stream);
 }
 
 // Batched Krylov state for one precision.
@@ -237,6 +263,8 @@ struct Batch {
   int* act = nullptr;
   int nsplit = 1;
   T* split_part = nullptr;
+  const T* pre = nullptr;      // preconditioner scaling or null
+  cplx<T>* ptmp = nullptr;
   std::vector<int> h_iters, h_flags;
   hipGraphExec_t gexec = nullptr;
   int g_na = -1;
@@ -246,7 +274,7 @@ struct Batch {
   Batch(Batch&& o) noexcept { *this = std::move(o); }
   Batch& operator=(Batch&& o) noexcept {
     kind = o.kind; nsys = o.nsys; ld = o.ld; v = o.v; tmp = o.tmp; Tb = o.Tb; shift = o.shift; w2 = o.w2;
-    act = o.act; nsplit = o.nsplit; split_part = o.split_part;
+    act = o.act; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp;
     h_iters = std::move(o.h_iters); h_flags = std::move(o.h_flags);
     gexec = o.gexec; g_na = o.g_na; o.gexec = nullptr;
     return *this;
@@ -271,6 +299,8 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   b.v.Ap = c->buf<cplx<T>>(t + ".Ap", nv);
   b.v.d = kind == K_SQMR ? c->buf<cplx<T>>(t + ".d", nv) : nullptr;
   b.tmp = kind == K_CGSQ ? c->buf<cplx<T>>(t + ".tmp", nv) : nullptr;
+  b.pre = pre_of<T>(c, kind);
+  b.ptmp = b.pre ? c->buf<cplx<T>>(t + ".ptmp", nv) : nullptr;
   b.Tb = c->buf<cplx<T>>(t + ".Tb", (size_t)nsys * c->N * c->ncols);
   b.v.ld = b.ld;
   b.v.rr = c->buf<T>(t + ".rr", nsys);
@@ -358,7 +388,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     const int na = (int)act.size();
     auto iterate = [&](int n_it) {
       for (int k = 0; k < n_it; ++k) {
-        apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na);
+        apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na, b.pre, b.ptmp);
         hipEvent_t t0 = c->begin(na);
         if (b.kind == K_SQMR) {
           launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
@@ -479,9 +509,37 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
     sh.resize(nsys);
     std::vector<double> w(w2v);
     Batch<double> b = make_batch<double>(c, "b64", kind, nsys, sh, w);
+    // With the preconditioner the Krylov solve runs on S P A P S y = S b and
+    // x = P S y (the projection happens in true_resid).  CG's tolerance is
+    // tightened by min S / max S (a bound on how much the scaled relative
+    // residual can understate the true one); SQMR keeps the requested one,
+    // since asking it for more than its attainable accuracy costs the iterate
+    // (below), and the true residual decides in both cases.
+    const double* pre = b.pre;
+    const double itol = kind == K_SQMR ? tol : tol * pre_ratio(c, kind);
+    const z64* B0 = B;
+    const int* bidx0 = d_bidx;
+    if (pre) {
+      z64* Bs = c->buf<z64>("sv.Bs", (size_t)nsys * npw);
+      launch_scale_diag<double>(B, npw, d_bidx, Bs, npw, nullptr, pre, npw, nsys, c->stream);
+      B0 = Bs;
+      bidx0 = nullptr;
+    }
+    // X rows from the batch's iterates: all rows, or the rows listed in d_act
+    auto x_out = [&](const int* rows, int n) {
+      if (pre) launch_scale_diag<double>(b.v.x, npw, rows, X, npw, rows, pre, npw, n, c->stream);
+      else if (!rows) HIPCHK(hipMemcpyAsync(X, b.v.x, (size_t)nsys * npw * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+      else launch_rows_out(b.v.x, npw, X, npw, rows, rows, nullptr, npw, n, c->stream);
+    };
+    // SQMR's recurrences lose accuracy when iterated past the attainable
+    // residual (the quasi-residual stagnates and the iterate degrades within a
+    // few tens of steps), so a system whose quasi-residual has not halved in
+    // 32 iterations stops and is judged by its true residual (restarted from
+    // it when above the tolerance).
+    const int stall = kind == K_SQMR ? 32 : 0;
     // solve into the batch's x, then refine by restarts on the true residual
-    run_batch<double>(c, b, B, npw, d_bidx, false, tol, all);
-    HIPCHK(hipMemcpyAsync(X, b.v.x, (size_t)nsys * npw * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    run_batch<double>(c, b, B0, npw, bidx0, false, itol, all, stall);
+    x_out(nullptr, nsys);
     std::vector<int> lst = all;
     for (int restart = 0; restart < 3; ++restart) {
       true_resid(lst);
@@ -489,17 +547,21 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       for (int s : lst)
         if (out.rel[s] > tol && b.h_flags[s] != FLAG_BREAK) bad.push_back(s);
       if (bad.empty()) break;
-      // restart from x with the true residual: b.v.x already holds X
+      // restart from x with the true residual: b.v.x already holds X (or y)
       h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
-      run_batch<double>(c, b, R, npw, nullptr, true, tol, bad);
-      HIPCHK(hipMemcpyAsync(X, b.v.x, (size_t)nsys * npw * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+      if (pre) launch_scale_diag<double>(R, npw, d_act, R, npw, d_act, pre, npw, (int)bad.size(), c->stream);
+      run_batch<double>(c, b, R, npw, nullptr, true, itol, bad, stall);
+      h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
+      x_out(d_act, (int)bad.size());
       lst = bad;
     }
+    // rows restarted last were not projected by a true-residual pass
+    proj<double>(c, X, npw, nullptr, nsys);
     for (int s = 0; s < nsys; ++s) {
       out.iters[s] = b.h_iters[s];
-      int f = b.h_flags[s];
-      if (out.rel[s] > 10 * tol && f == FLAG_CONV) f = FLAG_MAXIT;
-      out.flags[s] = f;
+      // the true residual decides; a Krylov breakdown is reported as such
+      const int f = b.h_flags[s];
+      out.flags[s] = out.rel[s] <= 10 * tol ? FLAG_CONV : (f == FLAG_BREAK ? FLAG_BREAK : FLAG_MAXIT);
       out.sweeps[s] = 1;
     }
   } else {
@@ -539,8 +601,13 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       h2d(c, irs, h_irs.data(), nsys * sizeof(double));
       h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
       launch_scale_cvt(R, npw, R32, npw, irs, d_act, npw, (int)bad.size(), c->stream);
-      run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad, 96);
+      if (b.pre) launch_scale_diag<float>(R32, npw, d_act, R32, npw, d_act, b.pre, npw, (int)bad.size(), c->stream);
+      // FP32 SQMR stops on a 32-iteration stagnation window like the FP64 one
+      // (an iterate pushed past its attainable accuracy spoils the correction);
+      // CG keeps a longer window for slowly converging imaginary-axis systems
+      run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad, kind == K_SQMR ? 32 : 96);
       h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
+      if (b.pre) launch_scale_diag<float>(b.v.x, npw, d_act, b.v.x, npw, d_act, b.pre, npw, (int)bad.size(), c->stream);
       launch_cvt_32_64_axpy(b.v.x, X, rs, d_act, npw, npw, (int)bad.size(), c->stream);
       true_resid(bad);
       for (int s : bad) {
@@ -585,9 +652,11 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
                       nullptr, 0, nullptr, B0, npw, nullptr, nb, c->stream);
   proj<double>(c, B0, npw, nullptr, nb);
   launch_add(B2, B0, B0, (long)nb * npw, c->stream);
+  // imaginary frequencies in the squared form need 2 P (H - e_v) b
+  const bool squared = c->opts.imag_form == 0;
   bool any_imag = false;
   for (int k = 0; k < nz; ++k)
-    if (zl[k].re == 0.0 && zl[k].im != 0.0) any_imag = true;
+    if (squared && zl[k].re == 0.0 && zl[k].im != 0.0) any_imag = true;
   z64* B1 = nullptr;   // 2 P (H - e_v) b
   std::vector<z64> eps_shift(nb);
   for (int p = 0; p < nb; ++p) eps_shift[p] = z64{c->eps[p % nv], 0.0};
@@ -607,7 +676,7 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
   for (int k = 0; k < nz; ++k) {
     for (int p = 0; p < nb; ++p) {
       if (zl[k].re == 0.0 && zl[k].im == 0.0) lin.push_back({k, p, 0});
-      else if (zl[k].re == 0.0) sq.push_back({k, p, 0});
+      else if (zl[k].re == 0.0 && squared) sq.push_back({k, p, 0});
       else {
         qm.push_back({k, p, -1});
         qm.push_back({k, p, +1});
@@ -1184,6 +1253,8 @@ void lgw_default_opts(lgw_opts* o) {
   o->inner_tol = 1e-5;
   o->max_sweeps = 8;
   o->use_graph = 1;
+  o->precond_shift = 3.0;
+  o->imag_form = 0;
 }
 
 lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], double ecut, const double* V_loc,
@@ -1213,7 +1284,10 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
   }
   if (!(o.tol > 0.0) || o.max_iter < 1 || o.check_every < 1) return bad("invalid solver options");
   if (o.precision != LGW_FP64 && o.precision != LGW_MIXED) return bad("invalid precision");
-  if (o.precond != 0) return bad("precond must be 0");
+  if (o.precond != 0 && o.precond != 1) return bad("precond must be 0 or 1");
+  if (o.precond == 1 && !(o.precond_shift > 0.0 && std::isfinite(o.precond_shift)))
+    return bad("precond_shift must be positive");
+  if (o.imag_form != 0 && o.imag_form != 1) return bad("imag_form must be 0 or 1");
   if (o.mem != LGW_MEM_DEVICE && o.mem != LGW_MEM_HOST) return bad("invalid mem mode");
   const int N = grid[0];
   const long n3 = (long)N * N * N;
@@ -1283,6 +1357,23 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
     upload(c.get(), c->d_col_h, col_h);
     upload(c.get(), c->d_col_pos, col_pos);
     upload(c.get(), c->d_kin, kin);
+    if (o.precond == 1) {
+      double kmax = 0.0;
+      for (double k : kin) kmax = std::max(kmax, k);
+      for (int f = 0; f < 2; ++f) {
+        std::vector<double> d(kin.size());
+        std::vector<float> d32(kin.size());
+        for (size_t i = 0; i < kin.size(); ++i) {
+          const double g = kin[i] + o.precond_shift;
+          d[i] = f == 0 ? 1.0 / std::sqrt(g) : 1.0 / g;
+          d32[i] = (float)d[i];
+        }
+        upload(c.get(), c->d_pre64[f], d);
+        upload(c.get(), c->d_pre32[f], d32);
+        const double q = o.precond_shift / (kmax + o.precond_shift);
+        c->pre_ratio[f] = f == 0 ? std::sqrt(q) : q;
+      }
+    }
     c->geom = Geom{N, c->npw, c->ncols, hx, hy, c->d_col_start.as<int>(), c->d_col_h.as<int>(),
                    c->d_col_pos.as<int>(), c->d_kin.as<double>()};
     // twiddles exp(-2 pi i j / N)

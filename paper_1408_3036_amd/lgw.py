@@ -35,7 +35,8 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("check_every", C.c_int), ("precond", C.c_int), ("deterministic", C.c_int),
                 ("mem", C.c_int), ("stream", C.c_void_p), ("mem_budget_gb", C.c_double),
-                ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("use_graph", C.c_int)]
+                ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("use_graph", C.c_int),
+                ("precond_shift", C.c_double), ("imag_form", C.c_int)]
 
 
 class Info(C.Structure):
@@ -113,14 +114,18 @@ class Lgw:
     """One system (H, valence set) on the current HIP device.
 
     V: real [N, N, N] float64 CUDA tensor; psi: [n_v, N^3] complex128 CUDA
-    tensor; eps: n_v floats; cell: box edges (Lx, Ly, Lz) in bohr.
+    tensor; eps: n_v floats; cell: box edges (Lx, Ly, Lz) in bohr.  Solver
+    options left as None keep the library defaults; precond=True turns on the
+    diagonal kinetic preconditioner and imag_form="shifted" solves the
+    imaginary axis as two shifted SQMR systems instead of the squared form.
     """
 
     def __init__(self, L, N: int, ecut: float, V, psi, eps, precision: str = "fp64",
                  tol: float | None = None, max_iter: int | None = None,
                  check_every: int | None = None, mem_budget_gb: float | None = None,
                  inner_tol: float | None = None, max_sweeps: int | None = None,
-                 use_graph: bool | None = None):
+                 use_graph: bool | None = None, precond: bool | None = None,
+                 precond_shift: float | None = None, imag_form: str | None = None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -144,6 +149,12 @@ class Lgw:
             opts.max_sweeps = max_sweeps
         if use_graph is not None:
             opts.use_graph = int(use_graph)
+        if precond is not None:
+            opts.precond = int(precond)
+        if precond_shift is not None:
+            opts.precond_shift = precond_shift
+        if imag_form is not None:
+            opts.imag_form = {"squared": 0, "shifted": 1}[imag_form]
         self.opts = opts
         V = self._dev(V, torch.float64).reshape(-1)
         psi = self._dev(psi, torch.complex128).reshape(len(eps), -1)

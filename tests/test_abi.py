@@ -57,7 +57,9 @@ def _setup(lib, **kw):
     (dict(n_v=40), "n_v"),
     (dict(eps=[-0.5, -1.0]), "ascending"),
     (dict(opts={"tol": 0.0}), "solver options"),
-    (dict(opts={"precond": 1}), "precond"),
+    (dict(opts={"precond": 2}), "precond"),
+    (dict(opts={"precond": 1, "precond_shift": 0.0}), "precond_shift"),
+    (dict(opts={"imag_form": 3}), "imag_form"),
 ])
 def test_setup_rejects_invalid_arguments_on_the_host(kw, msg):
     lib = _lib()
