@@ -840,15 +840,43 @@ __global__ void __launch_bounds__(256)
 k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, cplx<T>* __restrict__ Y, long ldy,
               const int* __restrict__ act, int nsys, int ks, const cplx<T>* __restrict__ part) {
   __shared__ cplx<T> C[16][kMaxBands];
+  __shared__ cplx<T> red[256];
   const int tile = blockIdx.y * 16;
   const int nt = min(16, nsys - tile);
-  for (int q = threadIdx.x; q < nt * nv; q += 256) {
-    const int s = q / nv, v = q - s * nv;
-    cplx<T> acc{0, 0};
-    for (int k = 0; k < ks; ++k) acc = acc + part[((long)k * nsys + tile + s) * nv + v];
-    C[s][v] = acc;
+  // C = sum of the ks partial tiles: tpe threads per entry (a power of two,
+  // at least 16 so a long K-split is summed in parallel), rounds of 256/tpe
+  // entries, fixed order (strided partial sums, then a tree in LDS)
+  const int E = nt * nv;
+  constexpr int tpe = 16;
+  constexpr int per_round = 256 / tpe;
+  const int sub = threadIdx.x % tpe;
+  for (int e0 = 0; e0 < E; e0 += per_round) {
+    const int e = e0 + threadIdx.x / tpe;
+    cplx<T> a0{0, 0}, a1{0, 0};
+    if (e < E) {
+      const int s = e / nv, v = e - s * nv;
+      const cplx<T>* pp = part + (long)(tile + s) * nv + v;
+      const long step = (long)nsys * nv;
+      int k = sub;
+      for (; k + tpe < ks; k += 2 * tpe) {
+        a0 = a0 + pp[(long)k * step];
+        a1 = a1 + pp[(long)(k + tpe) * step];
+      }
+      if (k < ks) a0 = a0 + pp[(long)k * step];
+    }
+    red[threadIdx.x] = a0 + a1;
+    __syncthreads();
+#pragma unroll
+    for (int off = tpe / 2; off > 0; off >>= 1) {
+      if (sub < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (sub == 0 && e < E) {
+      const int s = e / nv, v = e - s * nv;
+      C[s][v] = red[threadIdx.x];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= npw) return;
   for (int v0 = 0; v0 < nv; v0 += 8) {
