@@ -764,11 +764,12 @@ template <> struct Mfma<float> {
 constexpr int kProjGroups = kMaxBands / 8;
 
 // grid (ks, ceil(nsys/16)), one wave: partial[ks][sys][v] = sum over the
-// slice of conj(Phi_v) Y_sys
+// slice of conj(Phi_v) (d .* Y_sys), d = dpre or 1
 template <typename T, int NG>
 __global__ void __launch_bounds__(64)
 k_proj_dots(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, const cplx<T>* __restrict__ Y,
-            long ldy, const int* __restrict__ act, int nsys, int kchunk, cplx<T>* __restrict__ part) {
+            long ldy, const int* __restrict__ act, int nsys, int kchunk, cplx<T>* __restrict__ part,
+            const T* __restrict__ dpre) {
   using M = Mfma<T>;
   const int lane = threadIdx.x;
   const int tile = blockIdx.y * 16;
@@ -798,6 +799,7 @@ k_proj_dots(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, const 
       const int kk = k0 + 4 * u + kl;
       const bool kv = kk < k_end;
       y[u] = (kv && svalid) ? Ys[kk] : cplx<T>{0, 0};
+      if (dpre && kv) y[u] = dpre[kk] * y[u];
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         a[u][g] = T(0);
@@ -834,11 +836,13 @@ k_proj_dots(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, const 
   }
 }
 
-// grid (ceil(npw/256), ceil(nsys/16)): Y_sys -= sum_v Phi_v C[v][sys]
+// grid (ceil(npw/256), ceil(nsys/16)):
+//   Y_sys = dpost .* (dpre .* X_sys - sum_v Phi_v C[v][sys])   (X may be Y)
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, cplx<T>* __restrict__ Y, long ldy,
-              const int* __restrict__ act, int nsys, int ks, const cplx<T>* __restrict__ part) {
+k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, const cplx<T>* X, cplx<T>* Y,
+              long ldy, const int* __restrict__ act, int nsys, int ks, const cplx<T>* __restrict__ part,
+              const T* __restrict__ dpre, const T* __restrict__ dpost) {
   __shared__ cplx<T> C[16][kMaxBands];
   __shared__ cplx<T> red[256];
   const int tile = blockIdx.y * 16;
@@ -885,19 +889,21 @@ k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, cplx
     for (int u = 0; u < 8; ++u) ph[u] = v0 + u < nv ? Phi[(long)(v0 + u) * ldphi + i] : cplx<T>{0, 0};
     for (int s0 = 0; s0 < nt; s0 += 4) {
       cplx<T> y[4];
-      cplx<T>* Ys[4];
+      long row[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        Ys[q] = s0 + q < nt ? Y + (long)sys_of(act, tile + s0 + q) * ldy : nullptr;
-        y[q] = Ys[q] ? Ys[q][i] : cplx<T>{0, 0};
+        row[q] = s0 + q < nt ? (long)sys_of(act, tile + s0 + q) * ldy : -1;
+        y[q] = row[q] >= 0 ? (v0 == 0 ? X[row[q] + i] : Y[row[q] + i]) : cplx<T>{0, 0};
+        if (v0 == 0 && dpre) y[q] = dpre[i] * y[q];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (!Ys[q]) continue;
+        if (row[q] < 0) continue;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
           if (v0 + u < nv) y[q] = y[q] - C[s0 + q][v0 + u] * ph[u];
-        Ys[q][i] = y[q];
+        if (dpost && v0 + 8 >= nv) y[q] = dpost[i] * y[q];
+        Y[row[q] + i] = y[q];
       }
     }
   }
@@ -915,8 +921,8 @@ int proj_ksplit(int npw, int nsys) {
 }
 
 template <typename T>
-void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy, const int* act,
-                      int nsys, cplx<T>* part, hipStream_t s) {
+void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, const cplx<T>* X, cplx<T>* Y, long ldy,
+                      const int* act, int nsys, cplx<T>* part, const T* dpre, const T* dpost, hipStream_t s) {
   if (nsys <= 0 || nv <= 0) return;
   const int ks = proj_ksplit<T>(npw, nsys);
   int kchunk = (npw + ks - 1) / ks;
@@ -924,19 +930,29 @@ void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* 
   const int tiles = (nsys + 15) / 16;
   const dim3 grid(ks, tiles);
   switch ((nv + 7) / 8) {
-    case 1: k_proj_dots<T, 1><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, kchunk, part); break;
-    case 2: k_proj_dots<T, 2><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, kchunk, part); break;
-    case 3: k_proj_dots<T, 3><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, kchunk, part); break;
-    default: k_proj_dots<T, 4><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, kchunk, part); break;
+    case 1: k_proj_dots<T, 1><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, X, ldy, act, nsys, kchunk, part, dpre); break;
+    case 2: k_proj_dots<T, 2><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, X, ldy, act, nsys, kchunk, part, dpre); break;
+    case 3: k_proj_dots<T, 3><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, X, ldy, act, nsys, kchunk, part, dpre); break;
+    default: k_proj_dots<T, 4><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, X, ldy, act, nsys, kchunk, part, dpre); break;
   }
-  k_proj_update<T><<<dim3((npw + 255) / 256, tiles), 256, 0, s>>>(Phi, ldphi, nv, npw, Y, ldy, act, nsys, ks,
-                                                                   part);
+  k_proj_update<T><<<dim3((npw + 255) / 256, tiles), 256, 0, s>>>(Phi, ldphi, nv, npw, X, Y, ldy, act, nsys, ks,
+                                                                   part, dpre, dpost);
+}
+
+template <typename T>
+void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy, const int* act,
+                      int nsys, cplx<T>* part, hipStream_t s) {
+  launch_proj_mfma<T>(Phi, ldphi, nv, npw, Y, Y, ldy, act, nsys, part, nullptr, nullptr, s);
 }
 
 template int proj_ksplit<double>(int, int);
 template int proj_ksplit<float>(int, int);
 template void launch_proj_mfma<double>(const z64*, long, int, int, z64*, long, const int*, int, z64*, hipStream_t);
 template void launch_proj_mfma<float>(const z32*, long, int, int, z32*, long, const int*, int, z32*, hipStream_t);
+template void launch_proj_mfma<double>(const z64*, long, int, int, const z64*, z64*, long, const int*, int, z64*,
+                                       const double*, const double*, hipStream_t);
+template void launch_proj_mfma<float>(const z32*, long, int, int, const z32*, z32*, long, const int*, int, z32*,
+                                      const float*, const float*, hipStream_t);
 
 }  // namespace lgw
 

@@ -134,6 +134,10 @@ template <typename T> int proj_ksplit(int npw, int nsys);
 template <typename T>
 void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy, const int* act,
                       int nsys, cplx<T>* part, hipStream_t s);
+// Y = dpost .* P (dpre .* X) (X may be Y; null scalings are 1)
+template <typename T>
+void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, const cplx<T>* X, cplx<T>* Y, long ldy,
+                      const int* act, int nsys, cplx<T>* part, const T* dpre, const T* dpost, hipStream_t s);
 }  // namespace lgw
 
 namespace lgw {

@@ -216,15 +216,21 @@ void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const 
   c->tot_h += nsys;
 }
 
+// Y = dpost .* P (dpre .* X) for the listed systems (X may be Y)
 template <class T>
-void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
+void proj(lgw_ctx* c, const cplx<T>* X, cplx<T>* Y, long ldy, const int* act, int nsys, const T* dpre = nullptr,
+          const T* dpost = nullptr) {
   const int ks = proj_ksplit<T>(c->npw, nsys);
   cplx<T>* part = c->buf<cplx<T>>(sizeof(T) == 8 ? "proj.part64" : "proj.part32", (size_t)ks * nsys * c->nv);
   hipEvent_t t0 = c->begin(nsys);
-  launch_proj_mfma<T>(phi_of<T>(c), c->npw, c->nv, c->npw, Y, ldy, act, nsys, part, c->stream);
+  launch_proj_mfma<T>(phi_of<T>(c), c->npw, c->nv, c->npw, X, Y, ldy, act, nsys, part, dpre, dpost, c->stream);
   // Y read once and written once; the valence block is read once per launch
   c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_PROJ,
          2.0 * sizeof(T) * ((3.0 * nsys + c->nv) * c->npw));
+}
+template <class T>
+void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
+  proj<T>(c, Y, Y, ldy, act, nsys);
 }
 
 // Y = A X for the projected operator of the given kind (X is in range(P_c)).
@@ -235,8 +241,7 @@ void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, 
               const cplx<T>* shift, const T* w2, const int* act, int nsys, const T* pre = nullptr,
               cplx<T>* ptmp = nullptr) {
   if (pre) {
-    launch_scale_diag<T>(X, ld, act, ptmp, ld, act, pre, c->npw, nsys, c->stream);
-    proj<T>(c, ptmp, ld, act, nsys);
+    proj<T>(c, X, ptmp, ld, act, nsys, pre, nullptr);   // ptmp = P S X
     X = ptmp;
   }
   if (kind == K_CGSQ) {
@@ -246,8 +251,7 @@ void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, 
   } else {
     happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys);
   }
-  proj<T>(c, Y, ld, act, nsys);
-  if (pre) launch_scale_diag<T>(Y, ld, act, Y, ld, act, pre, c->npw, nsys, c->stream);
+  proj<T>(c, Y, Y, ld, act, nsys, nullptr, pre);          // Y = S P Y (S = 1 without preconditioner)
 }
 
 // Batched Krylov state for one precision.
