@@ -1124,6 +1124,32 @@ bool hpd_logdet_inverse(const std::vector<z64>& C, int m, double& logdet, std::v
   return true;
 }
 
+// Lower Cholesky factor L of the Hermitian positive definite m x m matrix G
+// (row-major, G = L L^H) and its inverse; false if G is not positive definite.
+bool chol_lower_inverse(const std::vector<z64>& G, int m, std::vector<z64>& Linv) {
+  std::vector<z64> Lf((size_t)m * m, z64{0, 0});
+  auto at = [&](int i, int j) -> z64& { return Lf[(size_t)i * m + j]; };
+  for (int j = 0; j < m; ++j) {
+    double d = G[(size_t)j * m + j].x;
+    for (int p = 0; p < j; ++p) d -= norm2(at(j, p));
+    if (!(d > 0.0)) return false;
+    at(j, j) = z64{std::sqrt(d), 0.0};
+    for (int i = j + 1; i < m; ++i) {
+      z64 s = G[(size_t)i * m + j];
+      for (int p = 0; p < j; ++p) s = s - cmulc(at(j, p), at(i, p));
+      at(i, j) = (1.0 / at(j, j).x) * s;
+    }
+  }
+  Linv.assign((size_t)m * m, z64{0, 0});
+  for (int c = 0; c < m; ++c)           // column c of L^{-1}: L y = e_c
+    for (int i = c; i < m; ++i) {
+      z64 s = z64{i == c ? 1.0 : 0.0, 0.0};
+      for (int p = c; p < i; ++p) s = s - at(i, p) * Linv[(size_t)p * m + c];
+      Linv[(size_t)i * m + c] = (1.0 / at(i, i).x) * s;
+    }
+  return true;
+}
+
 double re_dot(lgw_ctx* c, const z64* a, const z64* b) {
   double* d = c->buf<double>("ll.red", 1);
   z64* part = c->buf<z64>("ll.redp", 64);
@@ -1497,6 +1523,36 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
           std::snprintf(msg, sizeof msg, "eigen-residual of band %d is %.3e Ha", a, std::sqrt(h_rn[a]));
           return bad(msg);
         }
+      }
+      // Orthonormalise the valence block within its span (G = L L^H, Phi <-
+      // conj(L^-1) Phi): the projector 1 - Phi^H Phi is then exact to rounding.
+      // It matters once the Krylov vectors leave range(P), as with the
+      // preconditioner: a defect d of the supplied orbitals (1e-14 from an
+      // iterative eigensolver) leaves valence directions with eigenvalues of
+      // either sign of order d in the projected operator.
+      {
+        std::vector<z64> G((size_t)n_v * n_v), Linv;
+        for (int a = 0; a < n_v; ++a)
+          for (int b = 0; b < n_v; ++b) G[(size_t)a * n_v + b] = h_ov[(size_t)b * n_v + a];
+        for (int a = 0; a < n_v; ++a)          // exactly Hermitian
+          for (int b = 0; b < a; ++b) {
+            const z64 u = G[(size_t)a * n_v + b], l = G[(size_t)b * n_v + a];
+            const z64 avg{0.5 * (u.x + l.x), 0.5 * (u.y - l.y)};
+            G[(size_t)a * n_v + b] = avg;
+            G[(size_t)b * n_v + a] = z64{avg.x, -avg.y};
+          }
+        if (!chol_lower_inverse(G, n_v, Linv)) return bad("valence overlap matrix not positive definite");
+        // block_sub: W[c] -= sum_i X[i] Cm[c][i]; W = 0, Cm = -conj(Linv)
+        std::vector<z64> cm((size_t)n_v * n_v);
+        for (size_t e = 0; e < cm.size(); ++e) cm[e] = z64{-Linv[e].x, Linv[e].y};
+        z64* dcm = cp->buf<z64>("tmp.cm", cm.size());
+        h2d(cp, dcm, cm.data(), cm.size() * sizeof(z64));
+        z64* W = cp->buf<z64>("tmp.W", (size_t)n_v * npw);
+        HIPCHK(hipMemsetAsync(W, 0, (size_t)n_v * npw * sizeof(z64), cp->stream));
+        launch_block_sub(W, npw, n_v, c->d_Phi.as<z64>(), npw, n_v, dcm, npw, cp->stream);
+        HIPCHK(hipMemcpyAsync(c->d_Phi.p, W, (size_t)n_v * npw * sizeof(z64), hipMemcpyDeviceToDevice,
+                              cp->stream));
+        cp->check_launch();
       }
       c->d_Phi32.ensure((size_t)n_v * npw * sizeof(z32));
       launch_cvt_64_32(c->d_Phi.as<z64>(), c->d_Phi32.as<z32>(), (long)n_v * npw, cp->stream);

@@ -98,13 +98,16 @@ def config_freqs(kind: str) -> np.ndarray:
         return np.concatenate([imag_freqs(16), real_freqs(16)])
     if kind == "c3":
         return imag_freqs(32)
+    if kind == "uneven":
+        return imag_freqs(8)
     raise ValueError(kind)
 
 
 def make_workload(cfg: int, sys: int = 0, with_ground_state: bool = True,
                   max_attempts: int = 20, **override) -> Workload:
-    """Build config `cfg` (1..3) deterministically; reseed until the gap is >= 1e-3 Ha."""
-    p = dict(CONFIGS[cfg])
+    """Build config `cfg` deterministically (1..3; 4 = box `sys` of the uneven
+    batch, see uneven_box_params); reseed until the gap is >= 1e-3 Ha."""
+    p = dict(CONFIGS[cfg]) if cfg != 4 else uneven_box_params(sys)
     p.update(override)
     for attempt in range(max_attempts):
         seed = (SEED_BASE, cfg, sys, attempt)
@@ -121,3 +124,18 @@ def make_workload(cfg: int, sys: int = 0, with_ground_state: bool = True,
                         n_wells=p["n_wells"], V=V, psi=psi, eps=eps, gap=gap,
                         lanczos_steps=p["lanczos"], z=config_freqs(p["z"]), seed=seed)
     raise RuntimeError("no seed with a valence/conduction gap >= 1e-3 Ha")
+
+
+def uneven_box_params(sys: int) -> dict:
+    """Recipe of one box of the batched uneven-systems workload: grid N drawn
+    from {24, 32, 40, 48, 64}, edge L = N * 20/48 bohr (the silane-48 ratio of
+    grid to box), ecut 10 Ha, N_v from 2..32, 1..12 wells; 8 imaginary
+    frequencies; 32 Lanczos steps.  Draws come from default_rng([14083036, 4,
+    sys]) in the order N, N_v, wells (the potential itself is drawn by
+    make_workload from its own seed)."""
+    rng = np.random.default_rng([SEED_BASE, 4, sys])
+    N = int(rng.choice([24, 32, 40, 48, 64]))
+    n_v = int(rng.integers(2, 33))
+    n_wells = int(rng.integers(1, 13))
+    return dict(name=f"uneven-{sys}", L=N * 20.0 / 48.0, N=N, ecut=10.0, n_wells=n_wells,
+                n_v=n_v, lanczos=32, z="uneven")

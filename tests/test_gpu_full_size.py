@@ -1,0 +1,204 @@
+"""GPU parity at the full sizes of the workloads.
+
+Where the oracle is too slow for whole outputs, sampled outputs are compared
+with it one by one (the matrix-free FP64 Sternheimer oracle, or the dense sum
+over states on small boxes), and properties that hold at any size are checked
+on the rest: Hermiticity and sign of chi0 on the imaginary axis, agreement of
+the solver forms and precisions, Lanczos invariants, and the gradient against
+central differences of the loss.
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.pw import Basis
+from oracle.sternheimer import MatrixFree
+from oracle import lanczos as olz
+from synthetic import make_workload, random_potentials
+from synthetic.ground_state import ground_state
+from tests.gpu_common import lib_order, rel, colwise_rel
+
+FAST = dict(precond=True, imag_form="shifted")
+
+
+def _lgw(w, V=None, psi=None, eps=None, **kw):
+    from paper_1408_3036_amd import Lgw
+    V = w.V if V is None else V
+    psi = w.psi if psi is None else psi
+    eps = w.eps if eps is None else eps
+    return Lgw(w.L, w.N, w.ecut, torch.from_numpy(V), torch.from_numpy(psi), eps, **kw)
+
+
+@pytest.mark.parametrize("N", [16, 24, 32, 40, 48, 64, 72])
+def test_hpsi_and_vhalf_on_every_grid(N):
+    """Every FFT length the library plans (two-stage radices 4*4 ... 8*9); a
+    small cut-off keeps the ground state cheap."""
+    w = make_workload(1, N=N, L=N * 20.0 / 48.0, ecut=1.5, n_v=2, n_wells=3)
+    b = Basis(w.L, w.N, w.ecut)
+    lg = _lgw(w)
+    try:
+        order = lib_order(lg, b)
+        rng = np.random.default_rng(N)
+        X = rng.standard_normal((3, b.npw)) + 1j * rng.standard_normal((3, b.npw))
+        shift = 0.2 - 0.1j
+        Y = lg.hpsi(torch.from_numpy(X[:, order]), shift).cpu().numpy()
+        ref = np.array([b.apply_H(w.V, x) - shift * x for x in X])[:, order]
+        assert rel(Y, ref) < 1e-13
+        g = random_potentials(N, 2, N + 1, real=False)
+        assert rel(lg.vhalf(torch.from_numpy(g)).cpu().numpy(), b.apply_vhalf(g)) < 1e-13
+    finally:
+        lg.close()
+
+
+@pytest.mark.parametrize("case", ["bands32_grid24", "grid64_bands2"])
+def test_uneven_box_extremes_against_oracle(case):
+    """The extremes of the uneven batch: 32 valence bands (four 8-band projector
+    groups on the matrix cores) on a 24^3 box, and its largest grid (64^3)."""
+    if case == "bands32_grid24":
+        w = make_workload(4, sys=7, n_v=32)
+        zs = [0.0, 0.3j]
+    else:
+        w = make_workload(4, sys=11)
+        zs = [0.0, 0.3 + 0.0036749j]
+    assert (w.N, w.n_v) == ((24, 32) if case == "bands32_grid24" else (64, 2))
+    x = random_potentials(w.N, 2, 70)
+    mf = MatrixFree(Basis(w.L, w.N, w.ecut), w.V, w.psi, w.eps)
+    t = time.time()
+    ref = [mf.chi0(z, x[0]) for z in zs]
+    print(f"{case}: oracle {time.time() - t:.1f}s")
+    for prec, tol, bar, kw in (("fp64", 1e-13, 1e-10, {}), ("fp64", 1e-13, 1e-10, FAST),
+                               ("mixed", 1e-10, 1e-6, FAST)):
+        lg = _lgw(w, precision=prec, tol=tol, **kw)
+        try:
+            dn = lg.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+        finally:
+            lg.close()
+        for k, z in enumerate(zs):
+            err = rel(dn[k, 0], ref[k])
+            print(f"{case} {prec} {'fast' if kw else 'plain'} z={z}: {err:.2e}")
+            assert err < bar
+
+
+def test_silane48_batched_sampled_against_oracle():
+    """The benchmark's configuration: 16 columns x all 32 frequencies in one
+    call (about 3,800 systems), mixed precision with both solver options;
+    one column sampled at four frequencies against the oracle."""
+    w = make_workload(2)
+    b = Basis(w.L, w.N, w.ecut)
+    lg = _lgw(w, precision="mixed", tol=1e-10, **FAST)
+    l64 = _lgw(w, tol=1e-13, **FAST)
+    try:
+        X = lg.vhalf(torch.from_numpy(random_potentials(w.N, 16, 71)))
+        zs = list(w.z)
+        dn = lg.chi0_apply(X, zs).cpu().numpy()
+        st = lg.stats()
+        assert np.all(st["flags"] == 1)
+        pick = [0, 6, 15, 24]
+        d64 = l64.chi0_apply(X[3:4], [zs[i] for i in pick]).cpu().numpy()[:, 0]
+    finally:
+        lg.close()
+        l64.close()
+    mf = MatrixFree(b, w.V, w.psi, w.eps)
+    x3 = X[3].cpu().numpy()
+    for j, i in enumerate(pick):
+        ref = mf.chi0(zs[i], x3)
+        e_m, e_64 = rel(dn[i, 3], ref), rel(d64[j], ref)
+        print(f"silane-48 z={zs[i]:.4f}: mixed {e_m:.2e} fp64 {e_64:.2e}")
+        assert e_m < 1e-6
+        assert e_64 < 1e-10
+
+
+def test_large72_full_size():
+    """72^3 box, 38,401 plane waves, 16 valence bands: one static column against
+    the oracle; Hermiticity and sign at an imaginary frequency; solver forms
+    and precisions against each other; two 8-vector block-Lanczos steps."""
+    w = make_workload(3)
+    b = Basis(w.L, w.N, w.ecut)
+    assert (b.npw, w.n_v) == (38401, 16)
+    plain = _lgw(w, tol=1e-13)
+    fast = _lgw(w, tol=1e-13, **FAST)
+    mixed = _lgw(w, precision="mixed", tol=1e-10, **FAST)
+    try:
+        X = plain.vhalf(torch.from_numpy(random_potentials(w.N, 8, 72)))
+        # static column against the oracle
+        d0 = {n: l.chi0_apply(X[:1], [0.0]).cpu().numpy()[0, 0] for n, l in
+              (("plain", plain), ("fast", fast), ("mixed", mixed))}
+        t = time.time()
+        ref = MatrixFree(b, w.V, w.psi, w.eps).chi0(0.0, X[0].cpu().numpy())
+        print(f"large-72 oracle {time.time() - t:.1f}s; " +
+              ", ".join(f"{n} {rel(v, ref):.2e}" for n, v in d0.items()))
+        assert rel(d0["plain"], ref) < 1e-10
+        assert rel(d0["fast"], ref) < 1e-10
+        assert rel(d0["mixed"], ref) < 1e-6
+        # imaginary axis: squared form (plain) vs shifted pair + preconditioner
+        z = [0.5j]
+        dp = plain.chi0_apply(X[:2], z).cpu().numpy()[0]
+        df = fast.chi0_apply(X[:2], z).cpu().numpy()[0]
+        dm = mixed.chi0_apply(X[:2], z).cpu().numpy()[0]
+        assert colwise_rel(df, dp) < 1e-10
+        assert colwise_rel(dm, dp) < 1e-6
+        a, c = X[0].cpu().numpy(), X[1].cpu().numpy()
+        ab, ba = np.vdot(a, dp[1]), np.vdot(c, dp[0])
+        assert abs(ab - np.conj(ba)) < 1e-10 * abs(ab)
+        assert np.vdot(a, dp[0]).real < 0 and abs(np.vdot(a, dp[0]).imag) < 1e-10 * abs(np.vdot(a, dp[0]))
+        # block Lanczos: orthonormal basis, projected eps(0)-1 is the block tridiagonal
+        A, B, Q, nd = fast.block_lanczos(X, 2)
+        assert nd == 2
+        Qh = Q.cpu().numpy()
+        assert np.abs(Qh.conj() @ Qh.T - np.eye(16)).max() < 1e-12
+        T = olz.block_tridiag(A.cpu().numpy(), B.cpu().numpy())
+        E0 = fast.project(Q, [0.0]).cpu().numpy()[0]
+        assert np.abs(E0 - T).max() < 1e-9 * np.abs(T).max()
+    finally:
+        plain.close()
+        fast.close()
+        mixed.close()
+
+
+def test_lanczos_loss_gradient_silane48():
+    """The differentiation workload: silane-48, 64 Lanczos steps, z = 0 and four
+    imaginary frequencies.  The gradient is compared with Richardson-extrapolated
+    central differences of the library's own loss along two smooth directions,
+    the ground state recomputed at every displaced potential (total derivative)."""
+    w = make_workload(2)
+    zs = [0.0] + list(1j * np.geomspace(0.1, 2.0, 4))
+    q0 = torch.from_numpy(random_potentials(w.N, 1, 73)[0])
+    k = 64
+    lg = _lgw(w, tol=1e-13, **FAST)
+    try:
+        t = time.time()
+        L, gV, kd = lg.lanczos_loss_vjp(q0, k, zs)
+        print(f"silane-48 loss {L:.10f} k={kd} in {time.time() - t:.1f}s")
+    finally:
+        lg.close()
+    assert kd == k
+    gV = gV.cpu().numpy()
+    rng = np.random.default_rng(74)
+    r = w.L * np.stack(np.meshgrid(*[np.arange(w.N)] * 3, indexing="ij"), -1) / w.N
+
+    def loss_at(V):
+        psi, eps, _ = ground_state(V, w.L, w.ecut, w.n_v)
+        l2 = _lgw(w, V=V, psi=psi, eps=eps, tol=1e-13, **FAST)
+        try:
+            return l2.lanczos_loss_vjp(q0, k, zs, want_V=False)[0]
+        finally:
+            l2.close()
+    for i in range(2):
+        d = np.zeros((w.N,) * 3)
+        for _ in range(3):
+            c = rng.uniform(0, w.L, 3)
+            dd = (r - c + w.L / 2) % w.L - w.L / 2
+            d += rng.standard_normal() * np.exp(-np.sum(dd ** 2, -1) / (2 * 1.5 ** 2))
+        h = 1e-2
+        f1 = (loss_at(w.V + h * d) - loss_at(w.V - h * d)) / (2 * h)
+        f2 = (loss_at(w.V + 2 * h * d) - loss_at(w.V - 2 * h * d)) / (4 * h)
+        fd = (4 * f1 - f2) / 3
+        got = float(np.dot(gV, d.reshape(-1)))
+        err = abs(got - fd) / abs(fd)
+        print(f"silane-48 loss gradient, direction {i}: grad.d {got:.10e} FD {fd:.10e} rel {err:.2e}")
+        assert err < 1e-5
