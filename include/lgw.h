@@ -176,6 +176,18 @@ lgw_status lgw_chi0_apply_vjp(lgw_ctx* ctx, int n_rhs, const lgw_c128* dV, int n
                               const lgw_c128* z, const lgw_c128* g_dn, lgw_c128* g_dV,
                               double* g_Vloc);
 
+/* lgw_lanczos followed by lgw_project on its vectors, with the projection
+ * overlapped: every 8 finished Lanczos vectors are projected at all
+ * frequencies on a second stream (a twin of the context, created on the first
+ * call and kept with it) while the recursion continues.  The products
+ * (eps(0) - 1) q_j of the recursion serve z = 0.  Outputs as lgw_lanczos
+ * (alpha, beta [k], Q [k][N^3] or NULL, k_done) and lgw_project (E
+ * [n_z][k][k]; with k_done < k only the leading k_done x k_done block of each
+ * E[z] is written, the rest set to zero).  Needs n_z * k * N^3 complex values
+ * of device workspace. */
+lgw_status lgw_lanczos_project(lgw_ctx* ctx, const lgw_c128* q0, int k, int n_z, const lgw_c128* z,
+                               double* alpha, double* beta, lgw_c128* Q, lgw_c128* E, int* k_done);
+
 /* Loss of the Lanczos-projected dielectric matrix and its gradient:
  *   L = sum_z log det(I + E(z)),  E(z) = Q^H (eps(z) - 1) Q,
  * with Q the k Lanczos vectors of eps(0) - 1 from q0 (as lgw_lanczos: the

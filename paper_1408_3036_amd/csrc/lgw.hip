@@ -10,6 +10,10 @@
 #include <memory>
 #include <string>
 #include <thread>
+#include <functional>
+#include <mutex>
+#include <condition_variable>
+#include <deque>
 #include <vector>
 
 #include "kernels.h"
@@ -94,6 +98,10 @@ struct lgw_ctx {
   double kt_ms[2 * LGW_K_FP32] = {0};
   double kt_bytes[2 * LGW_K_FP32] = {0};
   long long kt_launches[2 * LGW_K_FP32] = {0};
+  // a second context on the same system with its own stream and copies of
+  // the read-only data, created on first use by calls that overlap two
+  // independent streams of work (lgw_lanczos_project)
+  std::unique_ptr<lgw_ctx> twin;
 
   template <class T>
   T* buf(const std::string& name, size_t count) {
@@ -146,6 +154,11 @@ struct lgw_ctx {
     pending.clear();
   }
   ~lgw_ctx() {
+    if (twin) {
+      hipStream_t ts = twin->own_stream ? twin->stream : nullptr;
+      twin.reset();
+      if (ts) (void)hipStreamDestroy(ts);
+    }
     if (stream) (void)hipStreamSynchronize(stream);
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     for (const Timed& t : pending) {
@@ -1051,7 +1064,8 @@ lgw_status lanczos_start(lgw_ctx* c, const lgw_c128* q0, z64* Q) {
 // beta_{j-1} q_{j-1}, then classical Gram-Schmidt against q_0..q_j twice,
 // beta_j = |w|, q_{j+1} = w / beta_j.  Stops early when beta_j < 1e-14
 // max|alpha|.  W0 (or null) keeps every product M q_j.
-lgw_status lanczos_core(lgw_ctx* c, int k, z64* Qd, z64* W0, double* d_alpha, double* d_beta, int* done_out) {
+lgw_status lanczos_core(lgw_ctx* c, int k, z64* Qd, z64* W0, double* d_alpha, double* d_beta, int* done_out,
+                        const std::function<void(int)>& ready = nullptr) {
   const long n3 = c->n3;
   z64* wbuf = c->buf<z64>("lz.w", n3);
   z64* h = c->buf<z64>("lz.h", k);
@@ -1079,7 +1093,10 @@ lgw_status lanczos_core(lgw_ctx* c, int k, z64* Qd, z64* W0, double* d_alpha, do
     amax = std::max(amax, std::abs(hb[0]));
     done = j + 1;
     if (hb[1] < 1e-14 * amax) break;
-    if (j + 1 < k) launch_scale_into(wbuf, d_beta + j, Qd + (size_t)(j + 1) * n3, n3, c->stream);
+    if (j + 1 < k) {
+      launch_scale_into(wbuf, d_beta + j, Qd + (size_t)(j + 1) * n3, n3, c->stream);
+      if (ready) ready(j + 2);   // q_0 .. q_{j+1} are (being) written on the stream
+    }
   }
   tally.store(c);
   *done_out = done;
@@ -1122,6 +1139,65 @@ bool hpd_logdet_inverse(const std::vector<z64>& C, int m, double& logdet, std::v
     for (int i = 0; i < m; ++i) inv[(size_t)i * m + cc] = x[i];
   }
   return true;
+}
+
+void dup_buf(lgw_ctx* c, DevBuf& dst, const DevBuf& src) {
+  if (!src.p) return;
+  dst.ensure(src.n);
+  HIPCHK(hipMemcpyAsync(dst.p, src.p, src.n, hipMemcpyDeviceToDevice, c->stream));
+}
+
+// The context's twin (see lgw_ctx::twin): same system and options, own
+// stream, device copies of the read-only data.
+lgw_ctx* twin_of(lgw_ctx* c) {
+  if (c->twin) return c->twin.get();
+  std::unique_ptr<lgw_ctx> t(new lgw_ctx);
+  t->device = c->device;
+  HIPCHK(hipStreamCreateWithFlags(&t->stream, hipStreamNonBlocking));
+  t->own_stream = true;
+  t->opts = c->opts;
+  t->opts.stream = t->stream;
+  for (int i = 0; i < 3; ++i) t->L[i] = c->L[i];
+  t->N = c->N;
+  t->n3 = c->n3;
+  t->ecut = c->ecut;
+  t->omega = c->omega;
+  t->dV = c->dV;
+  t->nv = c->nv;
+  t->npw = c->npw;
+  t->ncols = c->ncols;
+  t->hx = c->hx;
+  t->hy = c->hy;
+  t->m = c->m;
+  t->col_start = c->col_start;
+  t->col_h = c->col_h;
+  t->col_pos = c->col_pos;
+  t->kin = c->kin;
+  t->eps = c->eps;
+  t->pre_ratio[0] = c->pre_ratio[0];
+  t->pre_ratio[1] = c->pre_ratio[1];
+  dup_buf(c, t->d_col_start, c->d_col_start);
+  dup_buf(c, t->d_col_h, c->d_col_h);
+  dup_buf(c, t->d_col_pos, c->d_col_pos);
+  dup_buf(c, t->d_kin, c->d_kin);
+  dup_buf(c, t->d_Vt, c->d_Vt);
+  dup_buf(c, t->d_Vt32, c->d_Vt32);
+  dup_buf(c, t->d_sqrtv, c->d_sqrtv);
+  dup_buf(c, t->d_tw64, c->d_tw64);
+  dup_buf(c, t->d_tw32, c->d_tw32);
+  dup_buf(c, t->d_psi, c->d_psi);
+  dup_buf(c, t->d_u, c->d_u);
+  dup_buf(c, t->d_Phi, c->d_Phi);
+  dup_buf(c, t->d_Phi32, c->d_Phi32);
+  for (int f = 0; f < 2; ++f) {
+    dup_buf(c, t->d_pre64[f], c->d_pre64[f]);
+    dup_buf(c, t->d_pre32[f], c->d_pre32[f]);
+  }
+  c->sync();
+  t->geom = Geom{t->N, t->npw, t->ncols, t->hx, t->hy, t->d_col_start.as<int>(), t->d_col_h.as<int>(),
+                 t->d_col_pos.as<int>(), t->d_kin.as<double>()};
+  c->twin = std::move(t);
+  return c->twin.get();
 }
 
 // Lower Cholesky factor L of the Hermitian positive definite m x m matrix G
@@ -1622,7 +1698,13 @@ lgw_status lgw_chi0_apply_many(int n_sys, lgw_ctx* const* ctx, const int* n_rhs,
   std::vector<std::thread> th;
   th.reserve(n_sys);
   for (int i = 0; i < n_sys; ++i)
-    th.emplace_back([&, i] { st[i] = lgw_chi0_apply(ctx[i], n_rhs[i], dV[i], n_z, z, dn[i]); });
+    th.emplace_back([&, i] {
+      if (hipSetDevice(ctx[i]->device) != hipSuccess) {
+        st[i] = LGW_EDEVICE;
+        return;
+      }
+      st[i] = lgw_chi0_apply(ctx[i], n_rhs[i], dV[i], n_z, z, dn[i]);
+    });
   for (auto& t : th) t.join();
   lgw_status out = LGW_OK;
   for (int i = 0; i < n_sys; ++i) {
@@ -1768,6 +1850,182 @@ lgw_status lgw_lanczos_loss_vjp(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, 
     }
     c->sync();
     if (k_done) *k_done = m;
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_lanczos_project(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, const lgw_c128* z, double* alpha,
+                               double* beta, lgw_c128* Q, lgw_c128* E, int* k_done) {
+  if (!c) return LGW_EINVAL;
+  if (k < 1 || n_z < 1 || !q0 || !z || !alpha || !beta || !E || !k_done)
+    return set_err(c, LGW_EINVAL, "invalid arguments");
+  for (int i = 0; i < n_z; ++i) {
+    if (!std::isfinite(z[i].re) || !std::isfinite(z[i].im)) return set_err(c, LGW_ENAN, "non-finite frequency");
+    if (z[i].re != 0.0 && z[i].im < 0.0) return set_err(c, LGW_EINVAL, "real-axis broadening must be >= 0");
+  }
+  try {
+    const long n3 = c->n3;
+    z64* Qd = c->buf<z64>("lz.Q", (size_t)k * n3);
+    double* ab = c->buf<double>("lz.ab", 2 * (size_t)k);
+    // W[iz][b] = (eps(z_iz) - 1) q_b, plane-major; z = 0 comes from the recursion
+    z64* W = c->buf<z64>("lp.W", (size_t)n_z * k * n3);
+    const lgw_status pre = lanczos_start(c, q0, Qd);
+    if (pre != LGW_OK) return pre;
+    int iz0 = -1;
+    std::vector<lgw_c128> zw;
+    std::vector<int> zw_idx;
+    for (int i = 0; i < n_z; ++i) {
+      if (z[i].re == 0.0 && z[i].im == 0.0 && iz0 < 0) iz0 = i;
+      else {
+        zw.push_back(z[i]);
+        zw_idx.push_back(i);
+      }
+    }
+    lgw_ctx* tw = twin_of(c);
+    tw->prof = c->prof;
+    // worker: projects chunks of finished Lanczos vectors on the twin's stream
+    constexpr int kChunk = 8;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::pair<int, hipEvent_t>> queue;   // (end of chunk, event on c->stream)
+    bool finished = false;
+    lgw_status wst = LGW_OK;
+    std::string werr;
+    SolveTally wt;
+    std::vector<hipEvent_t> events;
+    std::thread worker([&] {
+      int from = 0;
+      try {
+        HIPCHK(hipSetDevice(c->device));
+        for (;;) {
+          std::pair<int, hipEvent_t> job;
+          {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return !queue.empty() || finished; });
+            if (queue.empty()) break;
+            job = queue.front();
+            queue.pop_front();
+          }
+          const int nb = job.first - from;
+          if (nb <= 0 || zw.empty()) {
+            from = job.first;
+            continue;
+          }
+          HIPCHK(hipStreamWaitEvent(tw->stream, job.second, 0));
+          z64* X = tw->buf<z64>("lp.X", (size_t)nb * n3);
+          z64* D = tw->buf<z64>("lp.D", (size_t)zw.size() * nb * n3);
+          HIPCHK(hipMemcpyAsync(X, Qd + (size_t)from * n3, (size_t)nb * n3 * sizeof(z64),
+                                hipMemcpyDeviceToDevice, tw->stream));
+          vhalf_inplace(tw, X, nb, 1.0);
+          tw->tot_iters = tw->tot_h = 0;
+          wst = worst(wst, chi0_internal(tw, nb, X, (int)zw.size(), zw.data(), D, (long)nb * n3));
+          wt.add(tw);
+          vhalf_inplace(tw, D, (int)zw.size() * nb, -1.0);
+          for (size_t i = 0; i < zw.size(); ++i)
+            HIPCHK(hipMemcpyAsync(W + ((size_t)zw_idx[i] * k + from) * n3, D + i * (size_t)nb * n3,
+                                  (size_t)nb * n3 * sizeof(z64), hipMemcpyDeviceToDevice, tw->stream));
+          tw->check_launch();
+          from = job.first;
+        }
+        tw->sync();
+      } catch (const Fail& f) {
+        wst = f.st;
+        werr = f.msg;
+      }
+    });
+    int pushed = 0;
+    auto push = [&](int upto) {
+      hipEvent_t ev;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      events.push_back(ev);
+      HIPCHK(hipEventRecord(ev, c->stream));
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        queue.emplace_back(upto, ev);
+      }
+      cv.notify_one();
+      pushed = upto;
+    };
+    int m = 0;
+    lgw_status st = LGW_OK;
+    try {
+      st = lanczos_core(c, k, Qd, iz0 >= 0 ? W + (size_t)iz0 * k * n3 : nullptr, ab, ab + k, &m,
+                        [&](int avail) {
+                          if (avail - pushed >= kChunk) push(avail);
+                        });
+      if (m > pushed) push(m);
+    } catch (...) {
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        finished = true;
+      }
+      cv.notify_one();
+      worker.join();
+      for (hipEvent_t e : events) (void)hipEventDestroy(e);
+      throw;
+    }
+    SolveTally tally;
+    tally.add(c);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      finished = true;
+    }
+    cv.notify_one();
+    worker.join();
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (!werr.empty()) throw Fail{wst, werr};
+    st = worst(st, wst);
+    tally.it.insert(tally.it.end(), wt.it.begin(), wt.it.end());
+    tally.fl.insert(tally.fl.end(), wt.fl.begin(), wt.fl.end());
+    tally.sw.insert(tally.sw.end(), wt.sw.begin(), wt.sw.end());
+    tally.res.insert(tally.res.end(), wt.res.begin(), wt.res.end());
+    tally.tot_it += wt.tot_it;
+    tally.tot_h += wt.tot_h;
+    tally.store(c);
+    if (c->prof) {   // the projection's launches ran on the twin
+      for (int i = 0; i < 2 * LGW_K_FP32; ++i) {
+        c->kt_ms[i] += tw->kt_ms[i];
+        c->kt_bytes[i] += tw->kt_bytes[i];
+        c->kt_launches[i] += tw->kt_launches[i];
+        tw->kt_ms[i] = tw->kt_bytes[i] = 0;
+        tw->kt_launches[i] = 0;
+      }
+    }
+    // E[z][a][b] = <q_a, W[z][b]> for a, b < m (zero beyond)
+    z64* Et = c->buf<z64>("lp.E", (size_t)n_z * m * m);
+    z64* part = c->buf<z64>("lp.part", (size_t)m * m * 64);
+    for (int i = 0; i < n_z; ++i)
+      launch_gemm_hn(Qd, n3, m, W + (size_t)i * k * n3, n3, m, n3, Et + (size_t)i * m * m, part, c->stream);
+    c->check_launch();
+    std::vector<z64> h((size_t)n_z * m * m);
+    HIPCHK(hipMemcpyAsync(h.data(), Et, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    std::vector<z64> e((size_t)n_z * k * k, z64{0, 0});
+    for (int i = 0; i < n_z; ++i)
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) e[((size_t)i * k + a) * k + b] = h[((size_t)i * m + b) * m + a];
+    if (c->opts.mem == LGW_MEM_DEVICE) h2d(c, E, e.data(), e.size() * sizeof(z64));
+    else std::memcpy(E, e.data(), e.size() * sizeof(z64));
+    if (c->opts.mem == LGW_MEM_DEVICE) {
+      HIPCHK(hipMemcpyAsync(alpha, ab, m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(beta, ab + k, m * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(alpha, ab, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(beta, ab + k, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    if (Q) {
+      const size_t qb = (size_t)m * n3 * sizeof(z64);
+      z64* dq = static_cast<z64*>(stage_out(c, Q, qb, "io.Qout"));
+      launch_zxy_to_xyz(c->N, Qd, n3, dq, n3, m, c->stream);
+      c->check_launch();
+      c->sync();
+      finish_out(c, Q, dq, qb);
+    }
+    c->sync();
+    *k_done = m;
     if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
     return st;
   } catch (const Fail& f) {

@@ -78,6 +78,7 @@ def load_library():
                               C.POINTER(D), C.POINTER(Opts)]
     lib.lgw_chi0_apply.argtypes = [P, I, P, I, C.POINTER(c128), P]
     lib.lgw_lanczos.argtypes = [P, P, I, P, P, P, C.POINTER(I)]
+    lib.lgw_lanczos_project.argtypes = [P, P, I, I, C.POINTER(c128), P, P, P, P, C.POINTER(I)]
     lib.lgw_project.argtypes = [P, I, P, I, C.POINTER(c128), P]
     lib.lgw_block_lanczos.argtypes = [P, I, P, I, P, P, P, C.POINTER(I)]
     lib.lgw_chi0_apply_vjp.argtypes = [P, I, P, I, C.POINTER(c128), P, P, P]
@@ -253,6 +254,25 @@ class Lgw:
             self.ctx, q0.data_ptr(), k, nz, zarr, loss.data_ptr(),
             gV.data_ptr() if gV is not None else None, C.byref(kd)))
         return float(loss.item()), gV, kd.value
+
+    def lanczos_project(self, q0, k: int, z, want_Q: bool = True):
+        """lanczos(q0, k) and project(Q, z) in one call, the projection of
+        finished Lanczos vectors overlapped with the recursion.  Returns
+        (alpha, beta, Q, E [n_z, k_done, k_done], k_done)."""
+        t = self.torch
+        q0 = self._dev(q0, t.complex128).reshape(-1)
+        zarr, nz = _z(z)
+        alpha = t.zeros(k, dtype=t.float64, device="cuda")
+        beta = t.zeros(k, dtype=t.float64, device="cuda")
+        Q = t.zeros((k, self.N ** 3), dtype=t.complex128, device="cuda") if want_Q else None
+        E = t.zeros((nz, k, k), dtype=t.complex128, device="cuda")
+        kd = C.c_int(0)
+        t.cuda.synchronize()
+        self.last_status = self._check(self.lib.lgw_lanczos_project(
+            self.ctx, q0.data_ptr(), k, nz, zarr, alpha.data_ptr(), beta.data_ptr(),
+            Q.data_ptr() if Q is not None else None, E.data_ptr(), C.byref(kd)))
+        n = kd.value
+        return alpha[:n], beta[:n], (Q[:n] if Q is not None else None), E[:, :n, :n], n
 
     def block_lanczos(self, Q0, nblk: int, want_Q: bool = True):
         """Block Lanczos from the rows of Q0 [b, N^3]: returns A, B [nblk, b, b], Q, nblk_done."""

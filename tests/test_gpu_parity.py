@@ -417,3 +417,32 @@ def test_preconditioned_sqmr_does_not_iterate_past_attainable_accuracy():
     mf = MatrixFree(B2(w.L, w.N, w.ecut), w.V, w.psi, w.eps)
     o = mf.chi0(z[0], X[3].cpu().numpy())
     assert rel(dn[3], o) < 1e-9
+
+
+@pytest.mark.parametrize("fast", [False, True])
+def test_lanczos_project_overlapped_matches_separate_calls(sysc1, fast):
+    """Lanczos + projection in one call (projection of finished vectors on a
+    second stream) against lanczos() then project(), and E against the oracle;
+    k = 19 leaves a partial last chunk."""
+    from paper_1408_3036_amd import Lgw
+    w, b, s, _ = sysc1
+    kw = dict(precond=True, imag_form="shifted") if fast else {}
+    lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps, **kw)
+    try:
+        q0 = torch.from_numpy(random_potentials(w.N, 1, 80)[0])
+        zs = [0.3j, 0.0, 0.4 + 0.0036749j, 1.5j]
+        k = 19
+        a, be, Q, E, kd = lg.lanczos_project(q0, k, zs)
+        a2, b2, Q2, kd2 = lg.lanczos(q0, k)
+        E2 = lg.project(Q2, zs)
+        assert kd == kd2 == k
+        assert torch.equal(a, a2) and torch.equal(be, b2) and torch.equal(Q, Q2)
+        assert rel(E.cpu().numpy(), E2.cpu().numpy()) < 1e-12
+        ref = olz.project(lambda z, v: s.M(z, v), Q.cpu().numpy(), zs)
+        for i in range(len(zs)):
+            assert rel(E[i].cpu().numpy(), ref[i]) < 1e-10
+        # second call reuses the twin context
+        _, _, _, E3, _ = lg.lanczos_project(q0, k, zs, want_Q=False)
+        assert rel(E3.cpu().numpy(), E.cpu().numpy()) < 1e-12
+    finally:
+        lg.close()
