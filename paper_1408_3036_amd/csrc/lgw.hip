@@ -18,6 +18,15 @@
 
 #include "kernels.h"
 
+// lgw_lanczos_project: Lanczos vectors per projection chunk, and the number
+// of chunks projected at once (each on its own stream)
+#ifndef LGW_PROJECT_CHUNK
+#define LGW_PROJECT_CHUNK 8
+#endif
+#ifndef LGW_PROJECT_WORKERS
+#define LGW_PROJECT_WORKERS 2
+#endif
+
 using namespace lgw;
 
 namespace {
@@ -98,10 +107,10 @@ struct lgw_ctx {
   double kt_ms[2 * LGW_K_FP32] = {0};
   double kt_bytes[2 * LGW_K_FP32] = {0};
   long long kt_launches[2 * LGW_K_FP32] = {0};
-  // a second context on the same system with its own stream and copies of
-  // the read-only data, created on first use by calls that overlap two
+  // further contexts on the same system, each with its own stream and copies
+  // of the read-only data, created on first use by calls that overlap
   // independent streams of work (lgw_lanczos_project)
-  std::unique_ptr<lgw_ctx> twin;
+  std::vector<std::unique_ptr<lgw_ctx>> twins;
 
   template <class T>
   T* buf(const std::string& name, size_t count) {
@@ -154,9 +163,9 @@ struct lgw_ctx {
     pending.clear();
   }
   ~lgw_ctx() {
-    if (twin) {
-      hipStream_t ts = twin->own_stream ? twin->stream : nullptr;
-      twin.reset();
+    for (auto& t : twins) {
+      hipStream_t ts = t->own_stream ? t->stream : nullptr;
+      t.reset();
       if (ts) (void)hipStreamDestroy(ts);
     }
     if (stream) (void)hipStreamSynchronize(stream);
@@ -1147,10 +1156,11 @@ void dup_buf(lgw_ctx* c, DevBuf& dst, const DevBuf& src) {
   HIPCHK(hipMemcpyAsync(dst.p, src.p, src.n, hipMemcpyDeviceToDevice, c->stream));
 }
 
-// The context's twin (see lgw_ctx::twin): same system and options, own
+// The context's i-th twin (see lgw_ctx::twins): same system and options, own
 // stream, device copies of the read-only data.
-lgw_ctx* twin_of(lgw_ctx* c) {
-  if (c->twin) return c->twin.get();
+lgw_ctx* twin_of(lgw_ctx* c, size_t i) {
+  while (c->twins.size() <= i) c->twins.emplace_back();
+  if (c->twins[i]) return c->twins[i].get();
   std::unique_ptr<lgw_ctx> t(new lgw_ctx);
   t->device = c->device;
   HIPCHK(hipStreamCreateWithFlags(&t->stream, hipStreamNonBlocking));
@@ -1196,8 +1206,8 @@ lgw_ctx* twin_of(lgw_ctx* c) {
   c->sync();
   t->geom = Geom{t->N, t->npw, t->ncols, t->hx, t->hy, t->d_col_start.as<int>(), t->d_col_h.as<int>(),
                  t->d_col_pos.as<int>(), t->d_kin.as<double>()};
-  c->twin = std::move(t);
-  return c->twin.get();
+  c->twins[i] = std::move(t);
+  return c->twins[i].get();
 }
 
 // Lower Cholesky factor L of the Hermitian positive definite m x m matrix G
@@ -1884,24 +1894,32 @@ lgw_status lgw_lanczos_project(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, c
         zw_idx.push_back(i);
       }
     }
-    lgw_ctx* tw = twin_of(c);
-    tw->prof = c->prof;
-    // worker: projects chunks of finished Lanczos vectors on the twin's stream
-    constexpr int kChunk = 8;
+    // workers: each projects chunks of finished Lanczos vectors on a twin's
+    // stream; two run at once, so that one chunk's transforms (LDS-bound)
+    // overlap another's vector and projector kernels (HBM-bound)
+    constexpr int kChunk = LGW_PROJECT_CHUNK;
+    constexpr int kWorkers = LGW_PROJECT_WORKERS;
+    std::vector<lgw_ctx*> tws(kWorkers);
+    for (int i = 0; i < kWorkers; ++i) {
+      tws[i] = twin_of(c, i);
+      tws[i]->prof = c->prof;
+    }
+    struct Job {
+      int from, to;
+    };
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<std::pair<int, hipEvent_t>> queue;   // (end of chunk, event on c->stream)
+    std::deque<Job> queue;
     bool finished = false;
-    lgw_status wst = LGW_OK;
-    std::string werr;
-    SolveTally wt;
-    std::vector<hipEvent_t> events;
-    std::thread worker([&] {
-      int from = 0;
+    std::vector<lgw_status> wst(kWorkers, LGW_OK);
+    std::vector<std::string> werr(kWorkers);
+    std::vector<SolveTally> wt(kWorkers);
+    auto work = [&](int wi) {
+      lgw_ctx* tw = tws[wi];
       try {
         HIPCHK(hipSetDevice(c->device));
         for (;;) {
-          std::pair<int, hipEvent_t> job;
+          Job job;
           {
             std::unique_lock<std::mutex> lk(mu);
             cv.wait(lk, [&] { return !queue.empty() || finished; });
@@ -1909,42 +1927,48 @@ lgw_status lgw_lanczos_project(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, c
             job = queue.front();
             queue.pop_front();
           }
-          const int nb = job.first - from;
-          if (nb <= 0 || zw.empty()) {
-            from = job.first;
-            continue;
-          }
-          HIPCHK(hipStreamWaitEvent(tw->stream, job.second, 0));
+          const int nb = job.to - job.from;
+          if (nb <= 0 || zw.empty()) continue;
           z64* X = tw->buf<z64>("lp.X", (size_t)nb * n3);
           z64* D = tw->buf<z64>("lp.D", (size_t)zw.size() * nb * n3);
-          HIPCHK(hipMemcpyAsync(X, Qd + (size_t)from * n3, (size_t)nb * n3 * sizeof(z64),
+          HIPCHK(hipMemcpyAsync(X, Qd + (size_t)job.from * n3, (size_t)nb * n3 * sizeof(z64),
                                 hipMemcpyDeviceToDevice, tw->stream));
           vhalf_inplace(tw, X, nb, 1.0);
           tw->tot_iters = tw->tot_h = 0;
-          wst = worst(wst, chi0_internal(tw, nb, X, (int)zw.size(), zw.data(), D, (long)nb * n3));
-          wt.add(tw);
+          wst[wi] = worst(wst[wi], chi0_internal(tw, nb, X, (int)zw.size(), zw.data(), D, (long)nb * n3));
+          wt[wi].add(tw);
           vhalf_inplace(tw, D, (int)zw.size() * nb, -1.0);
           for (size_t i = 0; i < zw.size(); ++i)
-            HIPCHK(hipMemcpyAsync(W + ((size_t)zw_idx[i] * k + from) * n3, D + i * (size_t)nb * n3,
+            HIPCHK(hipMemcpyAsync(W + ((size_t)zw_idx[i] * k + job.from) * n3, D + i * (size_t)nb * n3,
                                   (size_t)nb * n3 * sizeof(z64), hipMemcpyDeviceToDevice, tw->stream));
           tw->check_launch();
-          from = job.first;
         }
         tw->sync();
       } catch (const Fail& f) {
-        wst = f.st;
-        werr = f.msg;
+        wst[wi] = f.st;
+        werr[wi] = f.msg;
       }
-    });
-    int pushed = 0;
-    auto push = [&](int upto) {
-      hipEvent_t ev;
-      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      events.push_back(ev);
-      HIPCHK(hipEventRecord(ev, c->stream));
+    };
+    std::vector<std::thread> workers;
+    for (int i = 0; i < kWorkers; ++i) workers.emplace_back(work, i);
+    auto join_all = [&] {
       {
         std::lock_guard<std::mutex> lk(mu);
-        queue.emplace_back(upto, ev);
+        finished = true;
+      }
+      cv.notify_all();
+      for (auto& t : workers) t.join();
+    };
+    int pushed = 0;
+    // A chunk is handed over once the recursion's stream has written its
+    // vectors (a host synchronisation between two steps).  No event of that
+    // stream is shared with the workers: waiting on one, from another stream
+    // or the host, breaks the HIP graph the recursion may be capturing then.
+    auto push = [&](int upto) {
+      c->sync();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        queue.push_back(Job{pushed, upto});
       }
       cv.notify_one();
       pushed = upto;
@@ -1958,41 +1982,34 @@ lgw_status lgw_lanczos_project(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, c
                         });
       if (m > pushed) push(m);
     } catch (...) {
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        finished = true;
-      }
-      cv.notify_one();
-      worker.join();
-      for (hipEvent_t e : events) (void)hipEventDestroy(e);
+      join_all();
       throw;
     }
     SolveTally tally;
     tally.add(c);
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      finished = true;
+    join_all();
+    for (int i = 0; i < kWorkers; ++i)
+      if (!werr[i].empty()) throw Fail{wst[i], werr[i]};
+    for (int i = 0; i < kWorkers; ++i) {
+      st = worst(st, wst[i]);
+      const SolveTally& w = wt[i];
+      tally.it.insert(tally.it.end(), w.it.begin(), w.it.end());
+      tally.fl.insert(tally.fl.end(), w.fl.begin(), w.fl.end());
+      tally.sw.insert(tally.sw.end(), w.sw.begin(), w.sw.end());
+      tally.res.insert(tally.res.end(), w.res.begin(), w.res.end());
+      tally.tot_it += w.tot_it;
+      tally.tot_h += w.tot_h;
     }
-    cv.notify_one();
-    worker.join();
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    if (!werr.empty()) throw Fail{wst, werr};
-    st = worst(st, wst);
-    tally.it.insert(tally.it.end(), wt.it.begin(), wt.it.end());
-    tally.fl.insert(tally.fl.end(), wt.fl.begin(), wt.fl.end());
-    tally.sw.insert(tally.sw.end(), wt.sw.begin(), wt.sw.end());
-    tally.res.insert(tally.res.end(), wt.res.begin(), wt.res.end());
-    tally.tot_it += wt.tot_it;
-    tally.tot_h += wt.tot_h;
     tally.store(c);
-    if (c->prof) {   // the projection's launches ran on the twin
-      for (int i = 0; i < 2 * LGW_K_FP32; ++i) {
-        c->kt_ms[i] += tw->kt_ms[i];
-        c->kt_bytes[i] += tw->kt_bytes[i];
-        c->kt_launches[i] += tw->kt_launches[i];
-        tw->kt_ms[i] = tw->kt_bytes[i] = 0;
-        tw->kt_launches[i] = 0;
-      }
+    if (c->prof) {   // the projection's launches ran on the twins
+      for (lgw_ctx* tw : tws)
+        for (int i = 0; i < 2 * LGW_K_FP32; ++i) {
+          c->kt_ms[i] += tw->kt_ms[i];
+          c->kt_bytes[i] += tw->kt_bytes[i];
+          c->kt_launches[i] += tw->kt_launches[i];
+          tw->kt_ms[i] = tw->kt_bytes[i] = 0;
+          tw->kt_launches[i] = 0;
+        }
     }
     // E[z][a][b] = <q_a, W[z][b]> for a, b < m (zero beyond)
     z64* Et = c->buf<z64>("lp.E", (size_t)n_z * m * m);
