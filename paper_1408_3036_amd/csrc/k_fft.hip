@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256)
 k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, long ldt, T scale,
        const cplx<T>* __restrict__ X, long ldx, const cplx<T>* __restrict__ shift,
        const cplx<T>* __restrict__ E, long lde, const T* __restrict__ ecoef,
-       cplx<T>* __restrict__ Y, long ldy, const int* __restrict__ act) {
+       cplx<T>* __restrict__ Y, long ldy, const int* __restrict__ act, const T* __restrict__ dout) {
   constexpr int LDZ = skew(N) + 1;
   __shared__ cplx<T> buf[kZCols * LDZ];
   __shared__ cplx<T> tws[N];
@@ -108,6 +108,7 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
       v = v + k * xv;
     }
     if (Es) v = v + ec * Es[i];
+    if (dout) v = dout[i] * v;
     Ys[i] = v;
   }
 }
@@ -302,11 +303,12 @@ void launch_plane_hv(const Geom& g, const cplx<T>* tw, cplx<T>* Tb, long ldt, co
 template <typename T>
 void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, T scale,
                  const cplx<T>* X, long ldx, const cplx<T>* shift, const cplx<T>* E, long lde,
-                 const T* ecoef, cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s) {
+                 const T* ecoef, cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s,
+                 const T* dout) {
   if (nsys <= 0) return;
   dim3 grid((g.ncols + kZCols - 1) / kZCols, nsys);
   LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E, lde,
-                                                        ecoef, Y, ldy, act)));
+                                                        ecoef, Y, ldy, act, dout)));
 }
 
 template <typename T>
@@ -352,7 +354,7 @@ void launch_zfull_mul(int N, const cplx<T>* tw, cplx<T>* G, long ldg, const T* m
                                    int, hipStream_t);                                                 \
   template void launch_zfwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, T, const cplx<T>*,  \
                                long, const cplx<T>*, const cplx<T>*, long, const T*, cplx<T>*, long,  \
-                               const int*, int, hipStream_t);                                         \
+                               const int*, int, hipStream_t, const T*);                               \
   template void launch_plane_pair_fwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, int,            \
                                          const cplx<T>*, long, int, cplx<T>*, long, hipStream_t);     \
   template void launch_plane_acc<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, const cplx<T>*, \

@@ -25,7 +25,8 @@ template <typename T>
 void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, T scale,
                  const cplx<T>* X, long ldx, const cplx<T>* shift,
                  const cplx<T>* E, long lde, const T* ecoef,
-                 cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s);
+                 cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s,
+                 const T* dout = nullptr);   // optional per-plane-wave scaling of Y
 // Tb[j*nv+v][z][c] = FFT_xy(U[v][z] * X[j][z]) at the column positions (unscaled)
 template <typename T>
 void launch_plane_pair_fwd(const Geom& g, const cplx<T>* tw, const cplx<T>* U, int nv,

@@ -220,7 +220,8 @@ void upload(lgw_ctx* c, DevBuf& b, const std::vector<T>& h) {
 // y = (H - shift) x [+ ecoef E] for nsys systems (device per-system arrays)
 template <class T>
 void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const cplx<T>* shift,
-            const cplx<T>* E, long lde, const T* ecoef, cplx<T>* Tb, const int* act, int nsys) {
+            const cplx<T>* E, long lde, const T* ecoef, cplx<T>* Tb, const int* act, int nsys,
+            const T* dout = nullptr) {
   const long ldt = (long)c->N * c->ncols;
   const double e = 2.0 * sizeof(T);   // bytes of one complex value
   const double cols = (double)nsys * c->N * c->ncols, sph = (double)nsys * c->npw;
@@ -233,7 +234,7 @@ void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const 
   c->end(t1, pk + LGW_K_PLANE_HV, e * 2.0 * cols + sizeof(T) * (double)c->n3);
   hipEvent_t t2 = c->begin(nsys);
   launch_zfwd<T>(c->geom, tw_of<T>(c), Tb, ldt, T(1.0 / (double)c->n3), X, ldx, shift, E, lde, ecoef, Y, ldy,
-                 act, nsys, c->stream);
+                 act, nsys, c->stream, dout);
   c->end(t2, pk + LGW_K_ZFWD, e * (cols + (E ? 3.0 : 2.0) * sph));
   c->tot_h += nsys;
 }
@@ -257,23 +258,28 @@ void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
 
 // Y = A X for the projected operator of the given kind (X is in range(P_c)).
 // With a preconditioner scaling S (pre != null): Y = S P A P S X, the product
-// S X staged in ptmp.
+// S X staged in ptmp.  In single precision the outer P is left out and S is
+// applied by the transform's store: A maps range(P) into itself up to the
+// valence orbitals' eigen-residual (1e-13 relative at the workloads), far
+// below FP32 rounding, and the FP64 refinement projects every correction.
 template <class T>
 void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, cplx<T>* Tb, long ld,
               const cplx<T>* shift, const T* w2, const int* act, int nsys, const T* pre = nullptr,
               cplx<T>* ptmp = nullptr) {
+  const bool fold = pre && sizeof(T) == 4;
   if (pre) {
     proj<T>(c, X, ptmp, ld, act, nsys, pre, nullptr);   // ptmp = P S X
     X = ptmp;
   }
+  const T* dout = fold ? pre : nullptr;
   if (kind == K_CGSQ) {
     happly<T>(c, X, ld, tmp, ld, shift, nullptr, 0, nullptr, Tb, act, nsys);
     proj<T>(c, tmp, ld, act, nsys);
-    happly<T>(c, tmp, ld, Y, ld, shift, X, ld, w2, Tb, act, nsys);
+    happly<T>(c, tmp, ld, Y, ld, shift, X, ld, w2, Tb, act, nsys, dout);
   } else {
-    happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys);
+    happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, dout);
   }
-  proj<T>(c, Y, Y, ld, act, nsys, nullptr, pre);          // Y = S P Y (S = 1 without preconditioner)
+  if (!fold) proj<T>(c, Y, Y, ld, act, nsys, nullptr, pre);   // Y = S P Y (S = 1 without preconditioner)
 }
 
 // Batched Krylov state for one precision.
