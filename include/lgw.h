@@ -82,6 +82,15 @@ typedef struct {
                           two shifted systems (H - e_v -+ i w) g = b solved by
                           SQMR as on the real axis (Eq. (P1)); fewer H
                           applications, same chi0                             */
+  int    multishift;   /* 1: a chi0 call with at least three shifts (two or
+                          more frequencies) solves them all from one Lanczos
+                          recursion per (column, band) on P (H - e_v) P: the
+                          Krylov space is shared by every shift (H - e_v -/+ z),
+                          each shift then needs a tridiagonal solve.  FP64
+                          whatever the precision; every solution is checked by
+                          its true residual, and those above tol are corrected
+                          by the shifted solver.  0 (default): one Krylov solve
+                          per shift                                           */
 } lgw_opts;
 
 /* Fill *opts with the defaults listed above. */

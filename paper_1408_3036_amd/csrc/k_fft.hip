@@ -9,7 +9,10 @@ namespace {
 
 constexpr int kZCols = 32;           // z-columns per workgroup in column passes
 
-template <int N> constexpr int plane_threads() { return N >= 64 ? 512 : 256; }
+#ifndef LGW_PLANE_THREADS_48
+#define LGW_PLANE_THREADS_48 256
+#endif
+template <int N> constexpr int plane_threads() { return N >= 64 ? 512 : (N == 48 ? LGW_PLANE_THREADS_48 : 256); }
 
 template <typename T, int N>
 __device__ __forceinline__ void load_tw(cplx<T>* tw_s, const cplx<T>* tw) {

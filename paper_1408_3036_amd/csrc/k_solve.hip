@@ -911,10 +911,15 @@ k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, cons
 
 }  // namespace
 
+// total single-wave workgroups the projector's dots launch aims for
+#ifndef LGW_PROJ_WAVES
+#define LGW_PROJ_WAVES 2048
+#endif
+
 template <typename T>
 int proj_ksplit(int npw, int nsys) {
   const int tiles = (nsys + 15) / 16;
-  int ks = (2048 + tiles - 1) / tiles;
+  int ks = (LGW_PROJ_WAVES + tiles - 1) / tiles;
   const int kmax = (npw + 63) / 64;         // keep slices >= 64 plane waves
   if (ks > kmax) ks = kmax;
   return ks < 1 ? 1 : ks;
@@ -1121,4 +1126,110 @@ template void launch_cg_step_split<double>(const SolveVecs<double>&, int, double
                                            hipStream_t);
 template void launch_cg_step_split<float>(const SolveVecs<float>&, int, float, const int*, int, int, float*,
                                           hipStream_t);
+}  // namespace lgw
+
+// ====================================================================
+// Multi-shift solves: one plain Lanczos recursion per system on
+// A = P (H - e) P from its right-hand side serves every shift (the Krylov
+// space of A - tau is that of A); see multishift() in the library.
+namespace lgw {
+namespace {
+// Q[s][0] = b_s / |b_s|, nrm[s] = |b_s|; b_s = B[bidx[s]]
+__global__ void __launch_bounds__(NT)
+k_ms_init(const z64* __restrict__ B, long ldb, const int* __restrict__ bidx, int npw, z64* __restrict__ Q,
+          long ldq, double* __restrict__ nrm) {
+  __shared__ double sm[NT / 64];
+  const int s = blockIdx.x;
+  const z64* b = B + (long)bidx[s] * ldb;
+  double acc[1] = {0.0};
+  for (int i = threadIdx.x; i < npw; i += NT) acc[0] += norm2(b[i]);
+  block_sum<double, 1>(acc, sm);
+  const double n = sqrt(acc[0]);
+  const double inv = n > 0.0 ? 1.0 / n : 0.0;
+  z64* q = Q + (long)s * ldq;
+  for (int i = threadIdx.x; i < npw; i += NT) q[i] = inv * b[i];
+  if (threadIdx.x == 0) nrm[s] = n;
+}
+
+// Step j of the recursion for the listed systems.  On entry Q[s][j+1] holds
+// A q_j; on exit alpha_j = Re <q_j, A q_j>, w = A q_j - alpha_j q_j -
+// beta_{j-1} q_{j-1}, beta_j = |w| and Q[s][j+1] = w / beta_j.
+__global__ void __launch_bounds__(NT)
+k_ms_step(z64* __restrict__ Q, long ldq, int npw, int j, const int* __restrict__ act, double* __restrict__ alpha,
+          double* __restrict__ beta, int kcap) {
+  __shared__ double sm[NT / 64];
+  const int s = act[blockIdx.x];
+  z64* q = Q + (long)s * ldq + (long)j * npw;
+  z64* w = q + npw;
+  const z64* qp = j > 0 ? q - npw : nullptr;
+  double acc[1] = {0.0};
+  for (int i = threadIdx.x; i < npw; i += NT) acc[0] += q[i].x * w[i].x + q[i].y * w[i].y;
+  block_sum<double, 1>(acc, sm);
+  const double a = acc[0];
+  const double bp = j > 0 ? beta[(long)s * kcap + j - 1] : 0.0;
+  acc[0] = 0.0;
+  for (int i = threadIdx.x; i < npw; i += NT) {
+    z64 v = w[i] - a * q[i];
+    if (qp) v = v - bp * qp[i];
+    w[i] = v;
+    acc[0] += norm2(v);
+  }
+  block_sum<double, 1>(acc, sm);
+  const double b = sqrt(acc[0]);
+  const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  for (int i = threadIdx.x; i < npw; i += NT) w[i] = inv * w[i];
+  if (threadIdx.x == 0) {
+    alpha[(long)s * kcap + j] = a;
+    beta[(long)s * kcap + j] = b;
+  }
+}
+
+// X[s][t] = sum_{j < k[s]} Y[s][t][j] Q[s][j] for t < ntau: 64 plane waves per
+// workgroup, the four waves splitting the shifts (at most 16 each)
+__global__ void __launch_bounds__(256)
+k_ms_combine(const z64* __restrict__ Q, long ldq, int npw, const int* __restrict__ kdone,
+             const z64* __restrict__ Y, int kcap, int ntau, z64* __restrict__ X) {
+  constexpr int TG = 16;
+  const int s = blockIdx.y;
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  const int per = (ntau + 3) / 4;
+  const int t0 = g * per, t1 = min(ntau, t0 + per);
+  if (i >= npw || t0 >= t1) return;
+  const z64* Qs = Q + (long)s * ldq;
+  const z64* Ys = Y + (long)s * ntau * kcap;
+  const int k = kdone[s];
+  for (int tb = t0; tb < t1; tb += TG) {
+    const int nt = min(TG, t1 - tb);
+    z64 acc[TG];
+#pragma unroll
+    for (int u = 0; u < TG; ++u) acc[u] = z64{0.0, 0.0};
+    for (int jj = 0; jj < k; ++jj) {
+      const z64 qv = Qs[(long)jj * npw + i];
+#pragma unroll
+      for (int u = 0; u < TG; ++u)
+        if (u < nt) acc[u] = acc[u] + Ys[(long)(tb + u) * kcap + jj] * qv;
+    }
+    for (int u = 0; u < nt; ++u) X[((long)s * ntau + tb + u) * npw + i] = acc[u];
+  }
+}
+}  // namespace
+
+void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, long ldq, double* nrm, int nsys,
+                    hipStream_t s) {
+  if (nsys <= 0) return;
+  k_ms_init<<<nsys, NT, 0, s>>>(B, ldb, bidx, npw, Q, ldq, nrm);
+}
+
+void launch_ms_step(z64* Q, long ldq, int npw, int j, const int* act, int na, double* alpha, double* beta, int kcap,
+                    hipStream_t s) {
+  if (na <= 0) return;
+  k_ms_step<<<na, NT, 0, s>>>(Q, ldq, npw, j, act, alpha, beta, kcap);
+}
+
+void launch_ms_combine(const z64* Q, long ldq, int npw, const int* kdone, const z64* Y, int kcap, int ntau, z64* X,
+                       int nsys, hipStream_t s) {
+  if (nsys <= 0 || ntau <= 0) return;
+  k_ms_combine<<<dim3((npw + 63) / 64, nsys), 256, 0, s>>>(Q, ldq, npw, kdone, Y, kcap, ntau, X);
+}
 }  // namespace lgw

@@ -160,3 +160,14 @@ template <typename T>
 void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
                           hipStream_t s);
 }  // namespace lgw
+
+namespace lgw {
+// Multi-shift Lanczos: Q rows of system s at Q + s * ldq (k vectors of npw);
+// alpha/beta [nsys][kcap]; Y [nsys][ntau][kcap]
+void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, long ldq, double* nrm, int nsys,
+                    hipStream_t s);
+void launch_ms_step(z64* Q, long ldq, int npw, int j, const int* act, int na, double* alpha, double* beta, int kcap,
+                    hipStream_t s);
+void launch_ms_combine(const z64* Q, long ldq, int npw, const int* kdone, const z64* Y, int kcap, int ntau, z64* X,
+                       int nsys, hipStream_t s);
+}  // namespace lgw

@@ -26,6 +26,11 @@
 #ifndef LGW_PROJECT_WORKERS
 #define LGW_PROJECT_WORKERS 2
 #endif
+// chunk with the multi-shift solver: its recursion is latency-bound for a few
+// systems, so it takes more vectors at a time
+#ifndef LGW_PROJECT_CHUNK_MS
+#define LGW_PROJECT_CHUNK_MS 16
+#endif
 
 using namespace lgw;
 
@@ -137,8 +142,9 @@ struct lgw_ctx {
   // batched launches (more than kTimedMin systems) are timed: small launch-
   // bound batches run as replayed graphs.
   static constexpr int kTimedMin = 64;
+  bool time_all = false;   // set by solvers that capture no graphs (multi-shift)
   hipEvent_t begin(int nsys) {
-    if (!prof || nsys <= kTimedMin) return nullptr;
+    if (!prof || (nsys <= kTimedMin && !time_all)) return nullptr;
     hipEvent_t a = ev();
     HIPCHK(hipEventRecord(a, stream));
     return a;
@@ -655,6 +661,259 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
   for (int s = 0; s < nsys; ++s) c->tot_iters += out.iters[s];
 }
 
+// ---------------------------------------------------------------- multi-shift
+// Solution of (T - tau) y = r0 e_1 for the real symmetric tridiagonal T
+// (diagonal al[0..k), off-diagonal be[0..k-1)), Gaussian elimination with
+// partial pivoting (one extra super-diagonal appears).
+void tri_shift_solve(const double* al, const double* be, int k, z64 tau, double r0, z64* y) {
+  std::vector<z64> d(k), du(k > 1 ? k - 1 : 1), dl(k > 1 ? k - 1 : 1), du2(k > 2 ? k - 2 : 1), b(k, z64{0, 0});
+  for (int i = 0; i < k; ++i) d[i] = z64{al[i] - tau.x, -tau.y};
+  for (int i = 0; i + 1 < k; ++i) du[i] = dl[i] = z64{be[i], 0.0};
+  b[0] = z64{r0, 0.0};
+  auto div = [](z64 a, z64 c) {
+    const double den = c.x * c.x + c.y * c.y;
+    return z64{(a.x * c.x + a.y * c.y) / den, (a.y * c.x - a.x * c.y) / den};
+  };
+  auto mag = [](z64 a) { return std::abs(a.x) + std::abs(a.y); };
+  for (int i = 0; i + 1 < k; ++i) {
+    if (mag(d[i]) >= mag(dl[i])) {
+      const z64 f = div(dl[i], d[i]);
+      d[i + 1] = d[i + 1] - f * du[i];
+      b[i + 1] = b[i + 1] - f * b[i];
+      if (i + 2 < k) du2[i] = z64{0, 0};
+    } else {
+      const z64 f = div(d[i], dl[i]);
+      d[i] = dl[i];
+      const z64 t = d[i + 1];
+      d[i + 1] = du[i] - f * t;
+      if (i + 2 < k) {
+        du2[i] = du[i + 1];
+        du[i + 1] = z64{0, 0} - f * du2[i];
+      }
+      du[i] = t;
+      const z64 bt = b[i];
+      b[i] = b[i + 1];
+      b[i + 1] = bt - f * b[i + 1];
+    }
+  }
+  y[k - 1] = div(b[k - 1], d[k - 1]);
+  if (k > 1) y[k - 2] = div(b[k - 2] - du[k - 2] * y[k - 1], d[k - 2]);
+  for (int i = k - 3; i >= 0; --i) y[i] = div(b[i] - du[i] * y[i + 1] - du2[i] * y[i + 2], d[i]);
+}
+
+lgw_status worst(lgw_status a, lgw_status b);
+
+// Every frequency of a chi0 call from one Lanczos recursion per system: with
+// A_p = P (H - e_v) P and b_p = B0[p] (p = j * nv + v),
+//   F[z][p] = (A_p - z)^-1 b_p + (A_p + z)^-1 b_p       (2 A_p^-1 b_p at z = 0),
+// the sum the shifted pair and the squared form both produce.  The Krylov
+// space of A_p - tau is that of A_p, so plain Lanczos (A Q = Q T + beta q e^T)
+// gives every shift as x_tau = Q y_tau, (T - tau) y_tau = |b| e_1, with
+// residual |b - (A - tau) x_tau| = beta_k |e_k^T y_tau|.  A system stops when
+// that bound is below tol for all its shifts; every x_tau is then checked by
+// its true residual, and any above tol is corrected by the shifted solver.
+lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128* zl, z64* F) {
+  const int npw = c->npw, nv = c->nv;
+  const long ldt = (long)c->N * c->ncols;
+  const double tol = c->opts.tol;
+  std::vector<z64> tau;
+  std::vector<int> tpos(nz), tneg(nz);
+  for (int k = 0; k < nz; ++k) {
+    const z64 z{zl[k].re, zl[k].im};
+    if (z.x == 0.0 && z.y == 0.0) {
+      tpos[k] = tneg[k] = (int)tau.size();
+      tau.push_back(z64{0, 0});
+    } else {
+      tpos[k] = (int)tau.size();
+      tau.push_back(z);
+      tneg[k] = (int)tau.size();
+      tau.push_back(z64{-z.x, -z.y});
+    }
+  }
+  const int ntau = (int)tau.size();
+  const int kcap = std::max(16, std::min(c->opts.max_iter, 384));
+  // its launches are timed whatever their size (no graph capture here)
+  struct TimeAll {
+    lgw_ctx* c;
+    bool old;
+    ~TimeAll() { c->time_all = old; }
+  } time_all_guard{c, c->time_all};
+  c->time_all = true;
+  const int check = std::max(1, c->opts.check_every);
+  const double per = 16.0 * npw * ((kcap + 1) + 3.0 * ntau) + 16.0 * ldt * (1.0 + ntau);
+  const double budget = std::max(0.25, c->opts.mem_budget_gb) * 1e9;
+  const int cap = std::max(1, (int)std::min((double)nb, budget / per));
+  lgw_status st = LGW_OK;
+  for (int s0 = 0; s0 < nb; s0 += cap) {
+    const int n = std::min(cap, nb - s0);
+    const long ldq = (long)(kcap + 1) * npw;
+    z64* Q = c->buf<z64>("ms.Q", (size_t)n * ldq);
+    double* alpha = c->buf<double>("ms.al", (size_t)n * kcap);
+    double* beta = c->buf<double>("ms.be", (size_t)n * kcap);
+    double* nrm = c->buf<double>("ms.nrm", n);
+    int* d_idx = c->buf<int>("ms.idx", n);
+    int* d_act = c->buf<int>("ms.act", n);
+    z64* d_sh = c->buf<z64>("ms.sh", n);
+    z64* Tb = c->buf<z64>("ms.Tb", (size_t)n * ldt);
+    std::vector<int> idx(n);
+    std::vector<z64> sh(n);
+    for (int s = 0; s < n; ++s) {
+      idx[s] = s0 + s;
+      sh[s] = z64{c->eps[(s0 + s) % nv], 0.0};
+    }
+    h2d(c, d_idx, idx.data(), n * sizeof(int));
+    h2d(c, d_sh, sh.data(), n * sizeof(z64));
+    launch_ms_init(B0, npw, d_idx, npw, Q, ldq, nrm, n, c->stream);
+    c->check_launch();
+    std::vector<double> hn(n), ha((size_t)n * kcap), hb((size_t)n * kcap);
+    HIPCHK(hipMemcpyAsync(hn.data(), nrm, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    std::vector<int> act, kd(n, 0);
+    for (int s = 0; s < n; ++s)
+      if (hn[s] > 0.0) act.push_back(s);
+    std::vector<z64> y(kcap);
+    int j = 0;
+    while (!act.empty() && j < kcap) {
+      h2d(c, d_act, act.data(), act.size() * sizeof(int));
+      const int na = (int)act.size();
+      const int steps = std::min(check, kcap - j);
+      for (int t = 0; t < steps; ++t, ++j) {
+        apply_op<double>(c, K_CGLIN, Q + (size_t)j * npw, Q + (size_t)(j + 1) * npw, nullptr, Tb, ldq, d_sh,
+                         nullptr, d_act, na);
+        launch_ms_step(Q, ldq, npw, j, d_act, na, alpha, beta, kcap, c->stream);
+      }
+      c->check_launch();
+      HIPCHK(hipMemcpyAsync(ha.data(), alpha, ha.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(hb.data(), beta, hb.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      std::vector<int> next;
+      for (int s : act) {
+        const double* al = ha.data() + (size_t)s * kcap;
+        const double* be = hb.data() + (size_t)s * kcap;
+        double amax = 0.0;
+        for (int i = 0; i < j; ++i) amax = std::max(amax, std::abs(al[i]));
+        bool done = be[j - 1] <= 1e-14 * amax;   // invariant subspace: exact for every shift
+        if (!done) {
+          double est = 0.0;
+          for (int t = 0; t < ntau && est <= tol * hn[s]; ++t) {
+            tri_shift_solve(al, be, j, tau[t], hn[s], y.data());
+            est = std::max(est, be[j - 1] * std::sqrt(norm2(y[j - 1])));
+          }
+          done = est <= tol * hn[s];
+        }
+        if (done) kd[s] = j;
+        else next.push_back(s);
+      }
+      act.swap(next);
+    }
+    for (int s : act) kd[s] = j;   // not converged in kcap steps: the check below decides
+    c->tot_iters += [&] { long long t = 0; for (int s = 0; s < n; ++s) t += kd[s]; return t; }();
+    // x_tau = Q y_tau for every system and shift
+    std::vector<z64> hy((size_t)n * ntau * kcap, z64{0, 0});
+    for (int s = 0; s < n; ++s) {
+      if (kd[s] == 0) continue;
+      const double* al = ha.data() + (size_t)s * kcap;
+      const double* be = hb.data() + (size_t)s * kcap;
+      for (int t = 0; t < ntau; ++t) tri_shift_solve(al, be, kd[s], tau[t], hn[s], &hy[((size_t)s * ntau + t) * kcap]);
+    }
+    z64* Yd = c->buf<z64>("ms.Y", hy.size());
+    int* d_kd = c->buf<int>("ms.kd", n);
+    h2d(c, Yd, hy.data(), hy.size() * sizeof(z64));
+    h2d(c, d_kd, kd.data(), n * sizeof(int));
+    const int nr = n * ntau;
+    z64* X = c->buf<z64>("ms.X", (size_t)nr * npw);
+    launch_ms_combine(Q, ldq, npw, d_kd, Yd, kcap, ntau, X, n, c->stream);
+    proj<double>(c, X, npw, nullptr, nr);
+    // true residuals b - (H - e_v - tau) x of every (system, shift)
+    std::vector<int> rb(nr);
+    std::vector<z64> rs(nr);
+    for (int s = 0; s < n; ++s)
+      for (int t = 0; t < ntau; ++t) {
+        rb[(size_t)s * ntau + t] = s0 + s;
+        rs[(size_t)s * ntau + t] = z64{sh[s].x + tau[t].x, tau[t].y};
+      }
+    int* d_rb = c->buf<int>("ms.rb", nr);
+    z64* d_rs = c->buf<z64>("ms.rs", nr);
+    h2d(c, d_rb, rb.data(), nr * sizeof(int));
+    h2d(c, d_rs, rs.data(), nr * sizeof(z64));
+    z64* AX = c->buf<z64>("ms.AX", (size_t)nr * npw);
+    z64* R = c->buf<z64>("ms.R", (size_t)nr * npw);
+    z64* TbV = c->buf<z64>("ms.TbV", (size_t)nr * ldt);
+    double* res = c->buf<double>("ms.res", nr);
+    apply_op<double>(c, K_SQMR, X, AX, nullptr, TbV, npw, d_rs, nullptr, nullptr, nr);
+    launch_resid<double>(B0, npw, d_rb, AX, npw, R, npw, res, npw, nullptr, nr, c->stream);
+    std::vector<double> hr(nr);
+    HIPCHK(hipMemcpyAsync(hr.data(), res, nr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    std::vector<double> rel(nr, 0.0);
+    std::vector<int> fit(nr, 0), flg(nr, FLAG_CONV), bad;
+    for (int r = 0; r < nr; ++r) {
+      const double nb2 = hn[r / ntau];
+      rel[r] = nb2 > 0.0 ? std::sqrt(hr[r]) / nb2 : 0.0;
+      if (rel[r] > tol) bad.push_back(r);
+    }
+    if (!bad.empty()) {
+      // correction on the true residual with the shifted solver (SQMR)
+      std::vector<z64> bsh(bad.size());
+      for (size_t i = 0; i < bad.size(); ++i) bsh[i] = rs[bad[i]];
+      // The correction needs tol |b| / |R| relative to its own right-hand
+      // side: solve at the tightest of those (all are at least tol) and judge
+      // each system by its combined residual relative to |b|.
+      double rtol = 0.5;
+      for (int r : bad) rtol = std::min(rtol, tol * hn[r / ntau] / std::sqrt(hr[r]));
+      rtol = std::max(rtol, tol);
+      z64* E = c->buf<z64>("ms.E", bad.size() * (size_t)npw);
+      SolveOut so;
+      const double tol_saved = c->opts.tol;
+      c->opts.tol = rtol;
+      c->time_all = false;   // the shifted solver may capture graphs
+      try {
+        solve(c, K_SQMR, R, bad, bsh, {}, E, so);
+      } catch (...) {
+        c->opts.tol = tol_saved;
+        throw;
+      }
+      c->opts.tol = tol_saved;
+      c->time_all = true;
+      for (size_t i = 0; i < bad.size(); ++i) {
+        z64* xr = X + (size_t)bad[i] * npw;
+        launch_add(xr, xr, E + i * (size_t)npw, npw, c->stream);
+        const int r = bad[i];
+        rel[r] = so.rel[i] * std::sqrt(hr[r]) / hn[r / ntau];
+        fit[r] = so.iters[i];
+        flg[r] = rel[r] <= 10 * tol ? FLAG_CONV : (so.flags[i] == FLAG_BREAK ? FLAG_BREAK : FLAG_MAXIT);
+      }
+      c->check_launch();
+    }
+    // F[z][p] = x(+z) + x(-z)
+    std::vector<int> oi(3 * (size_t)n * nz);
+    const int np = n * nz;
+    for (int s = 0; s < n; ++s)
+      for (int k = 0; k < nz; ++k) {
+        const int q = s * nz + k;
+        oi[q] = k * nb + s0 + s;
+        oi[np + q] = s * ntau + tpos[k];
+        oi[2 * np + q] = s * ntau + tneg[k];
+      }
+    int* d_oi = c->buf<int>("ms.oi", oi.size());
+    h2d(c, d_oi, oi.data(), oi.size() * sizeof(int));
+    launch_rows_out(X, npw, F, npw, d_oi, d_oi + np, d_oi + 2 * np, npw, np, c->stream);
+    c->check_launch();
+    c->sync();
+    for (int s = 0; s < n; ++s)
+      for (int t = 0; t < ntau; ++t) {
+        const int r = s * ntau + t;
+        c->st_iters.push_back(kd[s] + fit[r]);
+        c->st_flags.push_back(flg[r]);
+        c->st_sweeps.push_back(1);
+        c->st_res.push_back(rel[r]);
+        if (flg[r] == FLAG_BREAK) st = worst(st, LGW_EBREAKDOWN);
+        else if (flg[r] != FLAG_CONV) st = worst(st, LGW_ENOCONV);
+      }
+  }
+  return st;
+}
+
 // ---------------------------------------------------------------- v^1/2
 // in-place on zxy grid vectors: G <- scale_sign * v^1/2 G
 void vhalf_inplace(lgw_ctx* c, z64* G, int n, double sign) {
@@ -684,8 +943,13 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
                       nullptr, 0, nullptr, B0, npw, nullptr, nb, c->stream);
   proj<double>(c, B0, npw, nullptr, nb);
   launch_add(B2, B0, B0, (long)nb * npw, c->stream);
+  // all frequencies from one Lanczos recursion per system when there are at
+  // least three shifts (one frequency is left to the preconditioned solvers)
+  int nshift = 0;
+  for (int k = 0; k < nz; ++k) nshift += (zl[k].re == 0.0 && zl[k].im == 0.0) ? 1 : 2;
+  const bool ms = c->opts.multishift == 1 && nshift >= 3;
   // imaginary frequencies in the squared form need 2 P (H - e_v) b
-  const bool squared = c->opts.imag_form == 0;
+  const bool squared = c->opts.imag_form == 0 && !ms;
   bool any_imag = false;
   for (int k = 0; k < nz; ++k)
     if (squared && zl[k].re == 0.0 && zl[k].im != 0.0) any_imag = true;
@@ -772,9 +1036,13 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
       }
     }
   };
-  run_kind(K_CGLIN, lin);
-  run_kind(K_CGSQ, sq);
-  run_kind(K_SQMR, qm);
+  if (ms) {
+    st = multishift(c, B0, nb, nz, zl, F);
+  } else {
+    run_kind(K_CGLIN, lin);
+    run_kind(K_CGSQ, sq);
+    run_kind(K_SQMR, qm);
+  }
   // dn_j(z) = -2 sum_v psi_v Scatter(f_{j,v}(z))
   for (int k = 0; k < nz; ++k) {
     launch_zinv<double>(c->geom, c->d_tw64.as<z64>(), F + (size_t)k * nb * npw, npw, Tb, ldt, 1.0, nullptr, nb,
@@ -1377,6 +1645,7 @@ void lgw_default_opts(lgw_opts* o) {
   o->use_graph = 1;
   o->precond_shift = 3.0;
   o->imag_form = 0;
+  o->multishift = 0;
 }
 
 lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], double ecut, const double* V_loc,
@@ -1410,6 +1679,7 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
   if (o.precond == 1 && !(o.precond_shift > 0.0 && std::isfinite(o.precond_shift)))
     return bad("precond_shift must be positive");
   if (o.imag_form != 0 && o.imag_form != 1) return bad("imag_form must be 0 or 1");
+  if (o.multishift != 0 && o.multishift != 1) return bad("multishift must be 0 or 1");
   if (o.mem != LGW_MEM_DEVICE && o.mem != LGW_MEM_HOST) return bad("invalid mem mode");
   const int N = grid[0];
   const long n3 = (long)N * N * N;
@@ -1903,7 +2173,7 @@ lgw_status lgw_lanczos_project(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, c
     // workers: each projects chunks of finished Lanczos vectors on a twin's
     // stream; two run at once, so that one chunk's transforms (LDS-bound)
     // overlap another's vector and projector kernels (HBM-bound)
-    constexpr int kChunk = LGW_PROJECT_CHUNK;
+    const int kChunk = c->opts.multishift == 1 ? LGW_PROJECT_CHUNK_MS : LGW_PROJECT_CHUNK;
     constexpr int kWorkers = LGW_PROJECT_WORKERS;
     std::vector<lgw_ctx*> tws(kWorkers);
     for (int i = 0; i < kWorkers; ++i) {

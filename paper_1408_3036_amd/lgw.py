@@ -36,7 +36,7 @@ class Opts(C.Structure):
                 ("check_every", C.c_int), ("precond", C.c_int), ("deterministic", C.c_int),
                 ("mem", C.c_int), ("stream", C.c_void_p), ("mem_budget_gb", C.c_double),
                 ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("use_graph", C.c_int),
-                ("precond_shift", C.c_double), ("imag_form", C.c_int)]
+                ("precond_shift", C.c_double), ("imag_form", C.c_int), ("multishift", C.c_int)]
 
 
 class Info(C.Structure):
@@ -118,7 +118,9 @@ class Lgw:
     tensor; eps: n_v floats; cell: box edges (Lx, Ly, Lz) in bohr.  Solver
     options left as None keep the library defaults; precond=True turns on the
     diagonal kinetic preconditioner and imag_form="shifted" solves the
-    imaginary axis as two shifted SQMR systems instead of the squared form.
+    imaginary axis as two shifted SQMR systems instead of the squared form;
+    multishift=True solves all frequencies of a call from one Lanczos recursion
+    per (column, band).
     """
 
     def __init__(self, L, N: int, ecut: float, V, psi, eps, precision: str = "fp64",
@@ -126,7 +128,8 @@ class Lgw:
                  check_every: int | None = None, mem_budget_gb: float | None = None,
                  inner_tol: float | None = None, max_sweeps: int | None = None,
                  use_graph: bool | None = None, precond: bool | None = None,
-                 precond_shift: float | None = None, imag_form: str | None = None):
+                 precond_shift: float | None = None, imag_form: str | None = None,
+                 multishift: bool | None = None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -156,6 +159,8 @@ class Lgw:
             opts.precond_shift = precond_shift
         if imag_form is not None:
             opts.imag_form = {"squared": 0, "shifted": 1}[imag_form]
+        if multishift is not None:
+            opts.multishift = int(multishift)
         self.opts = opts
         V = self._dev(V, torch.float64).reshape(-1)
         psi = self._dev(psi, torch.complex128).reshape(len(eps), -1)

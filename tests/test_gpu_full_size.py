@@ -113,6 +113,34 @@ def test_silane48_batched_sampled_against_oracle():
         assert e_64 < 1e-10
 
 
+def test_silane48_multishift_against_shifted_solvers():
+    """Silane-48, 8 columns x all 32 frequencies: the multi-shift recursion
+    against the per-shift solvers, and the H applications each needs."""
+    w = make_workload(2)
+    ms = _lgw(w, tol=1e-13, multishift=True)
+    ps = _lgw(w, tol=1e-13, **FAST)
+    try:
+        X = ms.vhalf(torch.from_numpy(random_potentials(w.N, 8, 75)))
+        zs = list(w.z)
+        t = time.time()
+        d_ms = ms.chi0_apply(X, zs).cpu().numpy()
+        t_ms = time.time() - t
+        st = ms.stats()
+        t = time.time()
+        d_ps = ps.chi0_apply(X, zs).cpu().numpy()
+        t_ps = time.time() - t
+        h_ps = ps.stats()["total_happly"]
+    finally:
+        ms.close()
+        ps.close()
+    err = max(colwise_rel(d_ms[k], d_ps[k]) for k in range(len(zs)))
+    print(f"silane-48 multishift: steps {st['iters'].min()}..{st['iters'].max()}, H {st['total_happly']} "
+          f"({t_ms:.2f}s) vs per-shift H {h_ps} ({t_ps:.2f}s); max rel diff {err:.2e}")
+    assert np.all(st["flags"] == 1)
+    assert err < 1e-10
+    assert st["total_happly"] < 0.5 * h_ps
+
+
 def test_large72_full_size():
     """72^3 box, 38,401 plane waves, 16 valence bands: one static column against
     the oracle; Hermiticity and sign at an imaginary frequency; solver forms
