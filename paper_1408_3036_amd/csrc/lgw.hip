@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -116,15 +117,32 @@ struct lgw_ctx {
   // of the read-only data, created on first use by calls that overlap
   // independent streams of work (lgw_lanczos_project)
   std::vector<std::unique_ptr<lgw_ctx>> twins;
+  // pinned staging ring for small host->device uploads on the context stream
+  // (h2d_async); a slot is written again only after a stream synchronisation
+  static constexpr size_t kPinBytes = size_t(1) << 20;
+  char* pin = nullptr;
+  size_t pin_off = 0;
+  // instantiated graphs of small-batch Krylov chunks, kept across solves and
+  // keyed by every pointer and size their capture bakes in; all are dropped
+  // before any workspace buffer is reallocated
+  std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+  void drop_graphs() {
+    if (graphs.empty()) return;
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+  }
 
   template <class T>
   T* buf(const std::string& name, size_t count) {
     DevBuf& b = ws[name];
+    if (!(count * sizeof(T) <= b.n && b.p)) drop_graphs();
     b.ensure(count * sizeof(T));
     return b.as<T>();
   }
   void sync() {
     HIPCHK(hipStreamSynchronize(stream));
+    pin_off = 0;
     harvest();
   }
   void check_launch() { HIPCHK(hipGetLastError()); }
@@ -175,6 +193,8 @@ struct lgw_ctx {
       if (ts) (void)hipStreamDestroy(ts);
     }
     if (stream) (void)hipStreamSynchronize(stream);
+    drop_graphs();
+    if (pin) (void)hipHostFree(pin);
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     for (const Timed& t : pending) {
       (void)hipEventDestroy(t.a);
@@ -215,6 +235,24 @@ double pre_ratio(const lgw_ctx* c, int kind) {
 void h2d(lgw_ctx* c, void* dst, const void* src, size_t bytes) {
   HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// host -> device copy of a small block, ordered on the context stream without
+// waiting for it: the host data are staged in the pinned ring first, so the
+// caller may reuse its buffer on return.  The ring is reused from its start
+// after a stream synchronisation (every earlier copy has then read its slot).
+void h2d_async(lgw_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return;
+  if (bytes > lgw_ctx::kPinBytes / 4) {
+    h2d(c, dst, src, bytes);
+    return;
+  }
+  if (!c->pin) HIPCHK(hipHostMalloc((void**)&c->pin, lgw_ctx::kPinBytes, hipHostMallocDefault));
+  const size_t n = (bytes + 255) & ~size_t(255);
+  if (c->pin_off + n > lgw_ctx::kPinBytes) c->sync();
+  std::memcpy(c->pin + c->pin_off, src, bytes);
+  HIPCHK(hipMemcpyAsync(dst, c->pin + c->pin_off, bytes, hipMemcpyHostToDevice, c->stream));
+  c->pin_off += n;
 }
 
 template <class T>
@@ -304,8 +342,6 @@ struct Batch {
   const T* pre = nullptr;      // preconditioner scaling or null
   cplx<T>* ptmp = nullptr;
   std::vector<int> h_iters, h_flags;
-  hipGraphExec_t gexec = nullptr;
-  int g_na = -1;
   Batch() = default;
   Batch(const Batch&) = delete;
   Batch& operator=(const Batch&) = delete;
@@ -314,11 +350,7 @@ struct Batch {
     kind = o.kind; nsys = o.nsys; ld = o.ld; v = o.v; tmp = o.tmp; Tb = o.Tb; shift = o.shift; w2 = o.w2;
     act = o.act; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp;
     h_iters = std::move(o.h_iters); h_flags = std::move(o.h_flags);
-    gexec = o.gexec; g_na = o.g_na; o.gexec = nullptr;
     return *this;
-  }
-  ~Batch() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
   }
 };
 
@@ -358,10 +390,10 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
     cap = std::max(cap, (size_t)proj_ksplit<T>(c->npw, nsys) * nsys) + 64;
     (void)c->buf<cplx<T>>(sizeof(T) == 8 ? "proj.part64" : "proj.part32", cap * c->nv);
   }
-  h2d(c, b.shift, shift.data(), nsys * sizeof(cplx<T>));
+  h2d_async(c, b.shift, shift.data(), nsys * sizeof(cplx<T>));
   std::vector<T> w(w2);
   w.resize(nsys, T(0));
-  h2d(c, b.w2, w.data(), nsys * sizeof(T));
+  h2d_async(c, b.w2, w.data(), nsys * sizeof(T));
   b.h_iters.assign(nsys, 0);
   b.h_flags.assign(nsys, 0);
   return b;
@@ -379,7 +411,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   std::vector<int> act(start);
   if (act.empty()) return;
   const int npw = c->npw;
-  h2d(c, b.act, act.data(), act.size() * sizeof(int));
+  h2d_async(c, b.act, act.data(), act.size() * sizeof(int));
   if (b.kind == K_SQMR)
     launch_sqmr_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream);
   else
@@ -390,38 +422,39 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   std::vector<int> flags(b.nsys), iters(b.nsys);
   std::vector<T> est(b.nsys);
   std::vector<double> best(b.nsys, 0.0);
-  std::vector<int> best_it(b.nsys, 0);
+  std::vector<int> best_it(b.nsys, -1);
   int it = 0;
-  while (!act.empty()) {
-    // drop systems converged at initialisation or in the last chunk
-    HIPCHK(hipMemcpyAsync(flags.data(), b.v.flag, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    if (stall > 0) HIPCHK(hipMemcpyAsync(est.data(), b.v.rr, b.nsys * sizeof(T), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
-    std::vector<int> next, stalled;
-    for (int s : act) {
-      if (flags[s]) continue;
-      if (stall > 0) {
-        const double e = b.kind == K_SQMR ? (double)est[s] : std::sqrt((double)est[s]);
-        if (it == 0 || e < 0.5 * best[s]) {
-          best[s] = e;
-          best_it[s] = it;
-        } else if (it - best_it[s] >= stall) {
-          stalled.push_back(s);
-          continue;
-        }
-      }
-      next.push_back(s);
-    }
-    for (int s : stalled) b.h_flags[s] = FLAG_MAXIT;
-    if (!stalled.empty()) {
-      std::vector<int> fl(stalled.size(), FLAG_MAXIT);
-      for (size_t i = 0; i < stalled.size(); ++i)
-        HIPCHK(hipMemcpyAsync(b.v.flag + stalled[i], &fl[i], sizeof(int), hipMemcpyHostToDevice, c->stream));
+  while (true) {
+    // after each chunk: drop converged (or broken-down) systems.  The step
+    // kernels skip flagged systems, so the first chunk runs without a poll
+    // (initialisation flags only zero right-hand sides).
+    if (it > 0) {
+      HIPCHK(hipMemcpyAsync(flags.data(), b.v.flag, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(iters.data(), b.v.iters, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      if (stall > 0) HIPCHK(hipMemcpyAsync(est.data(), b.v.rr, b.nsys * sizeof(T), hipMemcpyDeviceToHost, c->stream));
       c->sync();
+      std::vector<int> next, stalled;
+      for (int s : act) {
+        if (flags[s]) continue;
+        if (stall > 0) {
+          const double e = b.kind == K_SQMR ? (double)est[s] : std::sqrt((double)est[s]);
+          if (best_it[s] < 0 || e < 0.5 * best[s]) {
+            best[s] = e;
+            best_it[s] = it;
+          } else if (it - best_it[s] >= stall) {
+            stalled.push_back(s);
+            continue;
+          }
+        }
+        next.push_back(s);
+      }
+      for (int s : stalled) b.h_flags[s] = FLAG_MAXIT;
+      const int fl = FLAG_MAXIT;
+      for (int s : stalled) h2d_async(c, b.v.flag + s, &fl, sizeof(int));
+      act.swap(next);
+      if (act.empty() || it >= maxit) break;
+      h2d_async(c, b.act, act.data(), act.size() * sizeof(int));
     }
-    act.swap(next);
-    if (act.empty() || it >= maxit) break;
-    h2d(c, b.act, act.data(), act.size() * sizeof(int));
     const int chunk = std::min(check, maxit - it);
     const int na = (int)act.size();
     auto iterate = [&](int n_it) {
@@ -442,26 +475,40 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
         }
       }
     };
-    // Small, launch-bound batches replay their full chunks as a HIP graph
-    // (captured again whenever the active set changes); the first chunk runs
-    // eagerly so that every workspace buffer exists before capture.
-    const bool graph = c->opts.use_graph && it > 0 && chunk == check && na <= lgw_ctx::kTimedMin;
-    if (graph) {
-      if (!b.gexec || b.g_na != na) {
-        if (b.gexec) (void)hipGraphExecDestroy(b.gexec);
-        b.gexec = nullptr;
+    // Small, launch-bound batches replay their full chunks as HIP graphs,
+    // instantiated once per key and kept by the context (the active list is
+    // read from device memory, so only its length is baked in).  A chunk is
+    // captured only after an eager one, so that every workspace buffer exists.
+    hipGraphExec_t gx = nullptr;
+    if (c->opts.use_graph && chunk == check && na <= lgw_ctx::kTimedMin && !c->time_all) {
+      uint64_t tb;
+      std::memcpy(&tb, &tol, sizeof tb);
+      const std::vector<uintptr_t> key = {
+          (uintptr_t)b.kind, sizeof(T), (uintptr_t)na, (uintptr_t)chunk, (uintptr_t)tb, (uintptr_t)b.nsplit,
+          (uintptr_t)npw, (uintptr_t)b.ld, (uintptr_t)b.v.x, (uintptr_t)b.v.r, (uintptr_t)b.v.p,
+          (uintptr_t)b.v.Ap, (uintptr_t)b.v.d, (uintptr_t)b.v.rr, (uintptr_t)b.v.bb, (uintptr_t)b.v.theta,
+          (uintptr_t)b.v.rho, (uintptr_t)b.v.flag, (uintptr_t)b.v.iters, (uintptr_t)b.tmp, (uintptr_t)b.Tb,
+          (uintptr_t)b.shift, (uintptr_t)b.w2, (uintptr_t)b.act, (uintptr_t)b.split_part, (uintptr_t)b.pre,
+          (uintptr_t)b.ptmp};
+      auto f = c->graphs.find(key);
+      if (f != c->graphs.end()) {
+        gx = f->second;
+      } else if (it > 0) {
+        if (c->graphs.size() >= 64) c->drop_graphs();
         const long long h0 = c->tot_h;
         hipGraph_t gr = nullptr;
         HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         iterate(chunk);
         HIPCHK(hipStreamEndCapture(c->stream, &gr));
-        const hipError_t ie = hipGraphInstantiate(&b.gexec, gr, nullptr, nullptr, 0);
+        const hipError_t ie = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         HIPCHK(ie);
-        b.g_na = na;
+        c->graphs.emplace(key, gx);
         c->tot_h = h0;
       }
-      HIPCHK(hipGraphLaunch(b.gexec, c->stream));
+    }
+    if (gx) {
+      HIPCHK(hipGraphLaunch(gx, c->stream));
       c->tot_h += (long long)chunk * na * (b.kind == K_CGSQ ? 2 : 1);
     } else {
       iterate(chunk);
@@ -469,14 +516,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     c->check_launch();
     it += chunk;
   }
-  if (b.gexec) {
-    (void)hipGraphExecDestroy(b.gexec);
-    b.gexec = nullptr;
-    b.g_na = -1;
-  }
-  HIPCHK(hipMemcpyAsync(flags.data(), b.v.flag, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(iters.data(), b.v.iters, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  c->sync();
+  // the loop ends at a poll, after the last launch: flags and iters are final
   for (int s : start) {
     b.h_flags[s] = flags[s] ? flags[s] : FLAG_MAXIT;
     b.h_iters[s] = iters[s];
@@ -501,7 +541,7 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
   out.sweeps.assign(nsys, 0);
   out.rel.assign(nsys, 0.0);
   int* d_bidx = c->buf<int>("sv.bidx", nsys);
-  h2d(c, d_bidx, bidx.data(), nsys * sizeof(int));
+  h2d_async(c, d_bidx, bidx.data(), nsys * sizeof(int));
   z64* R = c->buf<z64>("sv.R", (size_t)nsys * npw);
   z64* AX = c->buf<z64>("sv.AX", (size_t)nsys * npw);
   z64* tmp = c->buf<z64>("sv.tmp", kind == K_CGSQ ? (size_t)nsys * npw : 1);
@@ -511,13 +551,13 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
   z64* d_shift = c->buf<z64>("sv.shift", nsys);
   double* d_w2 = c->buf<double>("sv.w2", nsys);
   int* d_act = c->buf<int>("sv.act", nsys);
-  h2d(c, d_shift, shift.data(), nsys * sizeof(z64));
+  h2d_async(c, d_shift, shift.data(), nsys * sizeof(z64));
   std::vector<double> w2v(w2);
   w2v.resize(nsys, 0.0);
-  h2d(c, d_w2, w2v.data(), nsys * sizeof(double));
+  h2d_async(c, d_w2, w2v.data(), nsys * sizeof(double));
   std::vector<int> all(nsys);
   for (int s = 0; s < nsys; ++s) all[s] = s;
-  h2d(c, d_act, all.data(), nsys * sizeof(int));
+  h2d_async(c, d_act, all.data(), nsys * sizeof(int));
   // |b|^2 per system
   std::vector<double> h_bb(nsys), h_res(nsys);
   {
@@ -530,7 +570,7 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
   // true residual R = B - A X over the listed systems; returns rel. residuals
   auto true_resid = [&](const std::vector<int>& lst) {
     if (lst.empty()) return;
-    h2d(c, d_act, lst.data(), lst.size() * sizeof(int));
+    h2d_async(c, d_act, lst.data(), lst.size() * sizeof(int));
     // the solution lives in the conduction space: remove what rounding (or the
     // single-precision corrections) left in the valence space, which the
     // projected residual below cannot see
@@ -586,10 +626,10 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
         if (out.rel[s] > tol && b.h_flags[s] != FLAG_BREAK) bad.push_back(s);
       if (bad.empty()) break;
       // restart from x with the true residual: b.v.x already holds X (or y)
-      h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
+      h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
       if (pre) launch_scale_diag<double>(R, npw, d_act, R, npw, d_act, pre, npw, (int)bad.size(), c->stream);
       run_batch<double>(c, b, R, npw, nullptr, true, itol, bad, stall);
-      h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
+      h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
       x_out(d_act, (int)bad.size());
       lst = bad;
     }
@@ -635,16 +675,16 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
         out.sweeps[s] += 1;
         prev[s] = out.rel[s];
       }
-      h2d(c, rs, h_rs.data(), nsys * sizeof(double));
-      h2d(c, irs, h_irs.data(), nsys * sizeof(double));
-      h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
+      h2d_async(c, rs, h_rs.data(), nsys * sizeof(double));
+      h2d_async(c, irs, h_irs.data(), nsys * sizeof(double));
+      h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
       launch_scale_cvt(R, npw, R32, npw, irs, d_act, npw, (int)bad.size(), c->stream);
       if (b.pre) launch_scale_diag<float>(R32, npw, d_act, R32, npw, d_act, b.pre, npw, (int)bad.size(), c->stream);
       // FP32 SQMR stops on a 32-iteration stagnation window like the FP64 one
       // (an iterate pushed past its attainable accuracy spoils the correction);
       // CG keeps a longer window for slowly converging imaginary-axis systems
       run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad, kind == K_SQMR ? 32 : 96);
-      h2d(c, d_act, bad.data(), bad.size() * sizeof(int));
+      h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
       if (b.pre) launch_scale_diag<float>(b.v.x, npw, d_act, b.v.x, npw, d_act, b.pre, npw, (int)bad.size(), c->stream);
       launch_cvt_32_64_axpy(b.v.x, X, rs, d_act, npw, npw, (int)bad.size(), c->stream);
       true_resid(bad);
@@ -761,8 +801,8 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
       idx[s] = s0 + s;
       sh[s] = z64{c->eps[(s0 + s) % nv], 0.0};
     }
-    h2d(c, d_idx, idx.data(), n * sizeof(int));
-    h2d(c, d_sh, sh.data(), n * sizeof(z64));
+    h2d_async(c, d_idx, idx.data(), n * sizeof(int));
+    h2d_async(c, d_sh, sh.data(), n * sizeof(z64));
     launch_ms_init(B0, npw, d_idx, npw, Q, ldq, nrm, n, c->stream);
     c->check_launch();
     std::vector<double> hn(n), ha((size_t)n * kcap), hb((size_t)n * kcap);
@@ -774,7 +814,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     std::vector<z64> y(kcap);
     int j = 0;
     while (!act.empty() && j < kcap) {
-      h2d(c, d_act, act.data(), act.size() * sizeof(int));
+      h2d_async(c, d_act, act.data(), act.size() * sizeof(int));
       const int na = (int)act.size();
       const int steps = std::min(check, kcap - j);
       for (int t = 0; t < steps; ++t, ++j) {
@@ -818,8 +858,8 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     }
     z64* Yd = c->buf<z64>("ms.Y", hy.size());
     int* d_kd = c->buf<int>("ms.kd", n);
-    h2d(c, Yd, hy.data(), hy.size() * sizeof(z64));
-    h2d(c, d_kd, kd.data(), n * sizeof(int));
+    h2d_async(c, Yd, hy.data(), hy.size() * sizeof(z64));
+    h2d_async(c, d_kd, kd.data(), n * sizeof(int));
     const int nr = n * ntau;
     z64* X = c->buf<z64>("ms.X", (size_t)nr * npw);
     launch_ms_combine(Q, ldq, npw, d_kd, Yd, kcap, ntau, X, n, c->stream);
@@ -834,8 +874,8 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
       }
     int* d_rb = c->buf<int>("ms.rb", nr);
     z64* d_rs = c->buf<z64>("ms.rs", nr);
-    h2d(c, d_rb, rb.data(), nr * sizeof(int));
-    h2d(c, d_rs, rs.data(), nr * sizeof(z64));
+    h2d_async(c, d_rb, rb.data(), nr * sizeof(int));
+    h2d_async(c, d_rs, rs.data(), nr * sizeof(z64));
     z64* AX = c->buf<z64>("ms.AX", (size_t)nr * npw);
     z64* R = c->buf<z64>("ms.R", (size_t)nr * npw);
     z64* TbV = c->buf<z64>("ms.TbV", (size_t)nr * ldt);
@@ -896,7 +936,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
         oi[2 * np + q] = s * ntau + tneg[k];
       }
     int* d_oi = c->buf<int>("ms.oi", oi.size());
-    h2d(c, d_oi, oi.data(), oi.size() * sizeof(int));
+    h2d_async(c, d_oi, oi.data(), oi.size() * sizeof(int));
     launch_rows_out(X, npw, F, npw, d_oi, d_oi + np, d_oi + 2 * np, npw, np, c->stream);
     c->check_launch();
     c->sync();
@@ -959,7 +999,7 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
   if (any_imag) {
     B1 = c->buf<z64>("c.B1", (size_t)nb * npw);
     z64* d_sh = c->buf<z64>("c.sh", nb);
-    h2d(c, d_sh, eps_shift.data(), nb * sizeof(z64));
+    h2d_async(c, d_sh, eps_shift.data(), nb * sizeof(z64));
     happly<double>(c, B2, npw, B1, npw, d_sh, nullptr, 0, nullptr, Tb, nullptr, nb);
     proj<double>(c, B1, npw, nullptr, nb);
   }
@@ -1022,7 +1062,7 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
       std::vector<int> all(didx);
       all.insert(all.end(), a.begin(), a.end());
       all.insert(all.end(), b.begin(), b.end());
-      h2d(c, d_idx, all.data(), all.size() * sizeof(int));
+      h2d_async(c, d_idx, all.data(), all.size() * sizeof(int));
       launch_rows_out(Xs, npw, F, npw, d_idx, d_idx + np, kind == K_SQMR ? d_idx + 2 * np : nullptr, npw, np,
                       c->stream);
       c->sync();
@@ -1920,6 +1960,7 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
       launch_cvt_64_32(c->d_Phi.as<z64>(), c->d_Phi32.as<z32>(), (long)n_v * npw, cp->stream);
       cp->sync();
     }
+    c->drop_graphs();
     c->ws.clear();
     *out = c.release();
     return LGW_OK;
@@ -2738,6 +2779,7 @@ void lgw_free(lgw_ctx* c) {
     c->harvest();
   } catch (const Fail&) {
   }
+  c->drop_graphs();
   c->ws.clear();
   c->stream = nullptr;
   delete c;
