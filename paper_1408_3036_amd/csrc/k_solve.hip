@@ -950,6 +950,52 @@ void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* 
   launch_proj_mfma<T>(Phi, ldphi, nv, npw, Y, Y, ldy, act, nsys, part, nullptr, nullptr, s);
 }
 
+// C[b * ldc + a] = sum over the ks slices of part[k][b][a] (a < mb), in slice order
+__global__ void __launch_bounds__(256) k_sum_slices(const z64* __restrict__ part, int ks, int p, int mb,
+                                                    z64* __restrict__ C, long ldc) {
+  const long total = (long)p * mb;
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  z64 acc{0, 0};
+  for (int k = 0; k < ks; ++k) acc = acc + part[(long)k * total + i];
+  const long b = i / mb;
+  C[b * ldc + (i - b * mb)] = acc;
+}
+
+int gemm_hn_slices(long n, int p) { return proj_ksplit<double>((int)n, p); }
+
+// The band dots of the projector with A's rows as the bands (blocks of up to
+// 64, eight 8-row groups per wave) and B's rows as the systems:
+// partial[k][b][a], then the slice sum into C's columns of the block.
+void launch_gemm_hn_mfma(const z64* A, long lda, int m, const z64* B, long ldb, int p, long n, z64* C, z64* partial,
+                         hipStream_t s) {
+  if (m <= 0 || p <= 0) return;
+  const int nk = (int)n;
+  const int ks = gemm_hn_slices(n, p);
+  int kchunk = (nk + ks - 1) / ks;
+  kchunk = (kchunk + 3) & ~3;
+  const dim3 grid(ks, (p + 15) / 16);
+  for (int a0 = 0; a0 < m; a0 += 64) {
+    const int mb = m - a0 < 64 ? m - a0 : 64;
+    const z64* Ab = A + (long)a0 * lda;
+    switch ((mb + 7) / 8) {
+#define LGW_GEMM_HN_CASE(G) \
+      case G: k_proj_dots<double, G><<<grid, 64, 0, s>>>(Ab, lda, mb, nk, B, ldb, nullptr, p, kchunk, partial, nullptr); break;
+      LGW_GEMM_HN_CASE(1)
+      LGW_GEMM_HN_CASE(2)
+      LGW_GEMM_HN_CASE(3)
+      LGW_GEMM_HN_CASE(4)
+      LGW_GEMM_HN_CASE(5)
+      LGW_GEMM_HN_CASE(6)
+      LGW_GEMM_HN_CASE(7)
+      default: k_proj_dots<double, 8><<<grid, 64, 0, s>>>(Ab, lda, mb, nk, B, ldb, nullptr, p, kchunk, partial, nullptr); break;
+#undef LGW_GEMM_HN_CASE
+    }
+    const long total = (long)p * mb;
+    k_sum_slices<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(partial, ks, p, mb, C + a0, m);
+  }
+}
+
 template int proj_ksplit<double>(int, int);
 template int proj_ksplit<float>(int, int);
 template void launch_proj_mfma<double>(const z64*, long, int, int, z64*, long, const int*, int, z64*, hipStream_t);
@@ -1184,34 +1230,69 @@ k_ms_step(z64* __restrict__ Q, long ldq, int npw, int j, const int* __restrict__
   }
 }
 
-// X[s][t] = sum_{j < k[s]} Y[s][t][j] Q[s][j] for t < ntau: 64 plane waves per
-// workgroup, the four waves splitting the shifts (at most 16 each)
+// X[s][t] = sum_{j < k[s]} Y[s][j][t] Q[s][j] for t < ntau, on
+// v_mfma_f64_16x16x4f64 (lane l holds A[l%16][l/16], B[l/16][l%16] and
+// D[4r + l/16][l%16]).  A wave computes a 64-shift x 32-plane-wave block: up
+// to four 16-row shift tiles (A = Y, rows padded to ntp, a multiple of 16;
+// grid z selects the group of 64 shifts) by two 16-column tiles (B = Q), each
+// complex product as four real ones; the Krylov index runs in steps of 4.
+// Rows j >= k[s] of Q are never read.
 __global__ void __launch_bounds__(256)
 k_ms_combine(const z64* __restrict__ Q, long ldq, int npw, const int* __restrict__ kdone,
-             const z64* __restrict__ Y, int kcap, int ntau, z64* __restrict__ X) {
-  constexpr int TG = 16;
+             const z64* __restrict__ Y, int ldyj, int ntp, int ntau, z64* __restrict__ X) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
   const int s = blockIdx.y;
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int g = threadIdx.x >> 6;
-  const int per = (ntau + 3) / 4;
-  const int t0 = g * per, t1 = min(ntau, t0 + per);
-  if (i >= npw || t0 >= t1) return;
-  const z64* Qs = Q + (long)s * ldq;
-  const z64* Ys = Y + (long)s * ntau * kcap;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = (blockIdx.x * 4 + w) * 32;
+  if (i0 >= npw) return;   // no barriers below
   const int k = kdone[s];
-  for (int tb = t0; tb < t1; tb += TG) {
-    const int nt = min(TG, t1 - tb);
-    z64 acc[TG];
+  const z64* Qs = Q + (long)s * ldq;
+  const z64* Ys = Y + (long)s * ldyj * ntp;
+  const int col = lane & 15, kl = lane >> 4;
+  const int tb = 64 * blockIdx.z;                 // first shift of the group
+  const int nm = min(4, (ntp - tb) >> 4);         // its 16-row tiles
+  d4 cr[4][2], ci[4][2];
 #pragma unroll
-    for (int u = 0; u < TG; ++u) acc[u] = z64{0.0, 0.0};
-    for (int jj = 0; jj < k; ++jj) {
-      const z64 qv = Qs[(long)jj * npw + i];
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int u = 0; u < TG; ++u)
-        if (u < nt) acc[u] = acc[u] + Ys[(long)(tb + u) * kcap + jj] * qv;
+    for (int n = 0; n < 2; ++n) {
+      cr[m][n] = d4{0, 0, 0, 0};
+      ci[m][n] = d4{0, 0, 0, 0};
     }
-    for (int u = 0; u < nt; ++u) X[((long)s * ntau + tb + u) * npw + i] = acc[u];
+  for (int j0 = 0; j0 < k; j0 += 4) {
+    const int j = j0 + kl;
+    const bool jv = j < k;
+    z64 q[2], a[4];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      const int i = i0 + 16 * n + col;
+      q[n] = (jv && i < npw) ? Qs[(long)j * npw + i] : z64{0, 0};
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a[m] = (jv && m < nm) ? Ys[(long)j * ntp + tb + 16 * m + col] : z64{0, 0};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (m < nm) {
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          cr[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, q[n].x, cr[m][n], 0, 0, 0);
+          cr[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[m].y, q[n].y, cr[m][n], 0, 0, 0);
+          ci[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, q[n].y, ci[m][n], 0, 0, 0);
+          ci[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].y, q[n].x, ci[m][n], 0, 0, 0);
+        }
+      }
+    }
   }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int t = tb + 16 * m + 4 * r + kl;
+        const int i = i0 + 16 * n + col;
+        if (t < ntau && i < npw) X[((long)s * ntau + t) * npw + i] = z64{cr[m][n][r], ci[m][n][r]};
+      }
 }
 }  // namespace
 
@@ -1227,9 +1308,11 @@ void launch_ms_step(z64* Q, long ldq, int npw, int j, const int* act, int na, do
   k_ms_step<<<na, NT, 0, s>>>(Q, ldq, npw, j, act, alpha, beta, kcap);
 }
 
-void launch_ms_combine(const z64* Q, long ldq, int npw, const int* kdone, const z64* Y, int kcap, int ntau, z64* X,
-                       int nsys, hipStream_t s) {
+void launch_ms_combine(const z64* Q, long ldq, int npw, const int* kdone, const z64* Y, int ldyj, int ntp, int ntau,
+                       z64* X, int nsys, hipStream_t s) {
+  // ntp: ntau rounded up to a multiple of 16 (the caller's Y layout)
   if (nsys <= 0 || ntau <= 0) return;
-  k_ms_combine<<<dim3((npw + 63) / 64, nsys), 256, 0, s>>>(Q, ldq, npw, kdone, Y, kcap, ntau, X);
+  k_ms_combine<<<dim3((npw + 127) / 128, nsys, (ntp + 63) / 64), 256, 0, s>>>(Q, ldq, npw, kdone, Y, ldyj, ntp,
+                                                                              ntau, X);
 }
 }  // namespace lgw

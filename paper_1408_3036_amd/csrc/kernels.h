@@ -168,6 +168,13 @@ void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, lo
                     hipStream_t s);
 void launch_ms_step(z64* Q, long ldq, int npw, int j, const int* act, int na, double* alpha, double* beta, int kcap,
                     hipStream_t s);
-void launch_ms_combine(const z64* Q, long ldq, int npw, const int* kdone, const z64* Y, int kcap, int ntau, z64* X,
-                       int nsys, hipStream_t s);
+// X[s][t] = sum_{j < kdone[s]} Y[s][j][t] Q[s][j] (Y: [nsys][ldyj][ntp], ntp =
+// ntau rounded up to a multiple of 16)
+void launch_ms_combine(const z64* Q, long ldq, int npw, const int* kdone, const z64* Y, int ldyj, int ntp, int ntau,
+                       z64* X, int nsys, hipStream_t s);
+// C[b][a] = sum_e conj(A[a][e]) B[b][e] for a < m, b < p, on the matrix cores;
+// partial needs gemm_hn_slices(n, p) * min(m, 64) * p entries
+int gemm_hn_slices(long n, int p);
+void launch_gemm_hn_mfma(const z64* A, long lda, int m, const z64* B, long ldb, int p, long n, z64* C, z64* partial,
+                         hipStream_t s);
 }  // namespace lgw

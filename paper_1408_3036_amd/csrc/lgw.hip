@@ -122,6 +122,23 @@ struct lgw_ctx {
   static constexpr size_t kPinBytes = size_t(1) << 20;
   char* pin = nullptr;
   size_t pin_off = 0;
+  // pinned host buffer for large uploads: its user rewrites it only after a
+  // stream synchronisation; growing it synchronises first
+  char* pinb = nullptr;
+  size_t pinb_n = 0;
+  void* pinned(size_t bytes) {
+    if (bytes > pinb_n) {
+      if (pinb) {
+        HIPCHK(hipStreamSynchronize(stream));
+        (void)hipHostFree(pinb);
+        pinb = nullptr;
+        pinb_n = 0;
+      }
+      HIPCHK(hipHostMalloc((void**)&pinb, bytes, hipHostMallocDefault));
+      pinb_n = bytes;
+    }
+    return pinb;
+  }
   // instantiated graphs of small-batch Krylov chunks, kept across solves and
   // keyed by every pointer and size their capture bakes in; all are dropped
   // before any workspace buffer is reallocated
@@ -195,6 +212,7 @@ struct lgw_ctx {
     if (stream) (void)hipStreamSynchronize(stream);
     drop_graphs();
     if (pin) (void)hipHostFree(pin);
+    if (pinb) (void)hipHostFree(pinb);
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     for (const Timed& t : pending) {
       (void)hipEventDestroy(t.a);
@@ -811,7 +829,13 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     std::vector<int> act, kd(n, 0);
     for (int s = 0; s < n; ++s)
       if (hn[s] > 0.0) act.push_back(s);
-    std::vector<z64> y(kcap);
+    // Residual estimates |b - (A - tau) x_j| = |b| |e_j^T (T_j - tau)^-1 e_1| beta_j
+    // = |b| prod_i beta_i / |det(T_j - tau)|, extended step by step through the
+    // ratios u_i = det(T_i - tau) / det(T_{i-1} - tau) (continued fraction
+    // u_{i+1} = alpha_i - tau - beta_{i-1}^2 / u_i); rho = prod beta / prod |u|.
+    std::vector<z64> cu((size_t)n * ntau, z64{0, 0});
+    std::vector<double> crho((size_t)n * ntau, 1.0);
+    std::vector<int> cj(n, 0);
     int j = 0;
     while (!act.empty() && j < kcap) {
       h2d_async(c, d_act, act.data(), act.size() * sizeof(int));
@@ -833,14 +857,32 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
         double amax = 0.0;
         for (int i = 0; i < j; ++i) amax = std::max(amax, std::abs(al[i]));
         bool done = be[j - 1] <= 1e-14 * amax;   // invariant subspace: exact for every shift
-        if (!done) {
-          double est = 0.0;
-          for (int t = 0; t < ntau && est <= tol * hn[s]; ++t) {
-            tri_shift_solve(al, be, j, tau[t], hn[s], y.data());
-            est = std::max(est, be[j - 1] * std::sqrt(norm2(y[j - 1])));
+        double worst_rho = 0.0;
+        for (int t = 0; t < ntau; ++t) {
+          z64& u = cu[(size_t)s * ntau + t];
+          double& rho = crho[(size_t)s * ntau + t];
+          for (int i = cj[s]; i < j; ++i) {
+            const z64 d{al[i] - tau[t].x, -tau[t].y};
+            if (i == 0) {
+              u = d;
+            } else {
+              const double den = norm2(u);
+              const double b2 = be[i - 1] * be[i - 1];
+              u = z64{d.x - b2 * u.x / den, d.y + b2 * u.y / den};   // d - b2 / u
+            }
+            // a (nearly) singular leading block, possible for real shifts only,
+            // gives a huge estimate at that step and recovers at the next
+            double au = std::sqrt(norm2(u));
+            if (!(au >= 1e-150)) {
+              u = z64{1e-150, 0.0};
+              au = 1e-150;
+            }
+            rho *= be[i] / au;
           }
-          done = est <= tol * hn[s];
+          worst_rho = std::max(worst_rho, rho);
         }
+        cj[s] = j;
+        done = done || worst_rho <= tol;
         if (done) kd[s] = j;
         else next.push_back(s);
       }
@@ -848,21 +890,39 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     }
     for (int s : act) kd[s] = j;   // not converged in kcap steps: the check below decides
     c->tot_iters += [&] { long long t = 0; for (int s = 0; s < n; ++s) t += kd[s]; return t; }();
-    // x_tau = Q y_tau for every system and shift
-    std::vector<z64> hy((size_t)n * ntau * kcap, z64{0, 0});
-    for (int s = 0; s < n; ++s) {
-      if (kd[s] == 0) continue;
-      const double* al = ha.data() + (size_t)s * kcap;
-      const double* be = hb.data() + (size_t)s * kcap;
-      for (int t = 0; t < ntau; ++t) tri_shift_solve(al, be, kd[s], tau[t], hn[s], &hy[((size_t)s * ntau + t) * kcap]);
+    // x_tau = Q y_tau for every system and shift: the tridiagonal solves on
+    // host threads into pinned Y[s][j][t] (shifts padded to ntp), then one
+    // combine on the matrix cores
+    const int kmax = std::max(1, *std::max_element(kd.begin(), kd.end()));
+    const int ntp = (ntau + 15) / 16 * 16;
+    const size_t ybytes = (size_t)n * kmax * ntp * sizeof(z64);
+    z64* hy = static_cast<z64*>(c->pinned(ybytes));   // the stream is idle here (synchronised at the last poll)
+    {
+      auto fill = [&](int sb, int se) {
+        std::vector<z64> yv(kmax);
+        for (int s = sb; s < se; ++s) {
+          const double* al = ha.data() + (size_t)s * kcap;
+          const double* be = hb.data() + (size_t)s * kcap;
+          z64* ys = hy + (size_t)s * kmax * ntp;
+          for (int t = 0; t < ntp; ++t) {
+            if (t < ntau && kd[s] > 0) tri_shift_solve(al, be, kd[s], tau[t], hn[s], yv.data());
+            for (int jj = 0; jj < kmax; ++jj) ys[(size_t)jj * ntp + t] = (t < ntau && jj < kd[s]) ? yv[jj] : z64{0, 0};
+          }
+        }
+      };
+      const int nth = std::max(1, std::min({8, n, (int)std::thread::hardware_concurrency() / 2}));
+      std::vector<std::thread> th;
+      for (int q = 1; q < nth; ++q) th.emplace_back(fill, (int)((long)n * q / nth), (int)((long)n * (q + 1) / nth));
+      fill(0, n / nth);
+      for (auto& x : th) x.join();
     }
-    z64* Yd = c->buf<z64>("ms.Y", hy.size());
+    z64* Yd = c->buf<z64>("ms.Y", ybytes / sizeof(z64));
     int* d_kd = c->buf<int>("ms.kd", n);
-    h2d_async(c, Yd, hy.data(), hy.size() * sizeof(z64));
+    HIPCHK(hipMemcpyAsync(Yd, hy, ybytes, hipMemcpyHostToDevice, c->stream));
     h2d_async(c, d_kd, kd.data(), n * sizeof(int));
     const int nr = n * ntau;
     z64* X = c->buf<z64>("ms.X", (size_t)nr * npw);
-    launch_ms_combine(Q, ldq, npw, d_kd, Yd, kcap, ntau, X, n, c->stream);
+    launch_ms_combine(Q, ldq, npw, d_kd, Yd, kmax, ntp, ntau, X, n, c->stream);
     proj<double>(c, X, npw, nullptr, nr);
     // true residuals b - (H - e_v - tau) x of every (system, shift)
     std::vector<int> rb(nr);
@@ -2107,7 +2167,8 @@ lgw_status lgw_lanczos_loss_vjp(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, 
     z64* Gb = grad ? c->buf<z64>("ll.Gb", (size_t)m * n3) : nullptr;   // adjoint of Q
     double* gV = grad ? c->buf<double>("ll.gV", n3) : nullptr;
     z64* Et = c->buf<z64>("ll.E", (size_t)m * m);
-    z64* part = c->buf<z64>("ll.part", (size_t)m * m * 64);
+    z64* part = c->buf<z64>("ll.part", (size_t)std::max<long>((long)m * m * 64,
+                                                               (long)gemm_hn_slices(n3, m) * std::min(m, 64) * m));
     z64* Cm = c->buf<z64>("ll.Cm", (size_t)m * m);
     if (grad) {
       HIPCHK(hipMemsetAsync(Gb, 0, (size_t)m * n3 * sizeof(z64), c->stream));
@@ -2127,7 +2188,7 @@ lgw_status lgw_lanczos_loss_vjp(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, 
         vhalf_inplace(c, Wz, m, -1.0);
         W = Wz;
       }
-      launch_gemm_hn(Qd, n3, m, W, n3, m, n3, Et, part, c->stream);   // Et[b][a] = <q_a, W_b>
+      launch_gemm_hn_mfma(Qd, n3, m, W, n3, m, n3, Et, part, c->stream);   // Et[b][a] = <q_a, W_b>
       HIPCHK(hipMemcpyAsync(h.data(), Et, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
       c->sync();
       // I + E, made exactly Hermitian; log det and inverse through Cholesky
@@ -2328,19 +2389,20 @@ lgw_status lgw_lanczos_project(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, c
           tw->kt_launches[i] = 0;
         }
     }
-    // E[z][a][b] = <q_a, W[z][b]> for a, b < m (zero beyond)
-    z64* Et = c->buf<z64>("lp.E", (size_t)n_z * m * m);
-    z64* part = c->buf<z64>("lp.part", (size_t)m * m * 64);
-    for (int i = 0; i < n_z; ++i)
-      launch_gemm_hn(Qd, n3, m, W + (size_t)i * k * n3, n3, m, n3, Et + (size_t)i * m * m, part, c->stream);
+    // E[z][a][b] = <q_a, W[z][b]> for a, b < m (zero beyond): every frequency
+    // in one product, Et[z * k + b][a] (rows b >= m of each W[z] are unused)
+    const int pz = n_z * k;
+    z64* Et = c->buf<z64>("lp.E", (size_t)pz * m);
+    z64* part = c->buf<z64>("lp.part", (size_t)gemm_hn_slices(n3, pz) * std::min(m, 64) * pz);
+    launch_gemm_hn_mfma(Qd, n3, m, W, n3, pz, n3, Et, part, c->stream);
     c->check_launch();
-    std::vector<z64> h((size_t)n_z * m * m);
+    std::vector<z64> h((size_t)pz * m);
     HIPCHK(hipMemcpyAsync(h.data(), Et, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
     c->sync();
     std::vector<z64> e((size_t)n_z * k * k, z64{0, 0});
     for (int i = 0; i < n_z; ++i)
       for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b) e[((size_t)i * k + a) * k + b] = h[((size_t)i * m + b) * m + a];
+        for (int b = 0; b < m; ++b) e[((size_t)i * k + a) * k + b] = h[((size_t)i * k + b) * m + a];
     if (c->opts.mem == LGW_MEM_DEVICE) h2d(c, E, e.data(), e.size() * sizeof(z64));
     else std::memcpy(E, e.data(), e.size() * sizeof(z64));
     if (c->opts.mem == LGW_MEM_DEVICE) {
@@ -2570,9 +2632,8 @@ lgw_status lgw_project(lgw_ctx* c, int k, const lgw_c128* Q, int n_z, const lgw_
     lgw_status st = chi0_internal(c, k, X, n_z, z, D, (long)k * n3);
     vhalf_inplace(c, D, n_z * k, -1.0);
     z64* Et = c->buf<z64>("pj.E", (size_t)n_z * k * k);
-    z64* part = c->buf<z64>("pj.part", (size_t)k * k * 64);
-    for (int i = 0; i < n_z; ++i)
-      launch_gemm_hn(Qz, n3, k, D + (size_t)i * k * n3, n3, k, n3, Et + (size_t)i * k * k, part, c->stream);
+    z64* part = c->buf<z64>("pj.part", (size_t)gemm_hn_slices(n3, n_z * k) * std::min(k, 64) * n_z * k);
+    launch_gemm_hn_mfma(Qz, n3, k, D, n3, n_z * k, n3, Et, part, c->stream);   // Et[z * k + b][a]
     c->check_launch();
     std::vector<z64> h((size_t)n_z * k * k);
     HIPCHK(hipMemcpyAsync(h.data(), Et, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
