@@ -962,35 +962,98 @@ __global__ void __launch_bounds__(256) k_sum_slices(const z64* __restrict__ part
   C[b * ldc + (i - b * mb)] = acc;
 }
 
-int gemm_hn_slices(long n, int p) { return proj_ksplit<double>((int)n, p); }
+// C^T block of C[b][a] = sum_e conj(A[a][e]) B[b][e]: one workgroup takes a
+// K range and 128 rows of B against up to 64 rows of A.  Chunks of 16 K
+// elements of both are staged in LDS with row-contiguous loads; each wave then
+// computes a 64 x 32 block (four 16-row A tiles by two 16-row B tiles) on
+// v_mfma_f64_16x16x4f64 (lane l: A[l%16][l/16], B[l/16][l%16],
+// D[4r + l/16][l%16]), the complex product as four real ones, and writes
+// partial[slice][b][a].
+constexpr int kGemmKC = 16;                // K elements per LDS chunk
+constexpr int kGemmBRows = 128;            // B rows per workgroup
+constexpr int kGemmLd = kGemmKC + 1;       // padded LDS row (complex values)
+__global__ void __launch_bounds__(256)
+k_gemm_hn_tiled(const z64* __restrict__ A, long lda, int mb, const z64* __restrict__ B, long ldb, int p, long n,
+                long kchunk, z64* __restrict__ partial) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  __shared__ z64 As[64 * kGemmLd];
+  __shared__ z64 Bs[kGemmBRows * kGemmLd];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = lane & 15, kl = lane >> 4;
+  const int b0 = blockIdx.y * kGemmBRows;
+  const long e_begin = (long)blockIdx.x * kchunk;
+  const long e_end = e_begin + kchunk < n ? e_begin + kchunk : n;
+  d4 cr[4][2], ci[4][2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      cr[m][q] = d4{0, 0, 0, 0};
+      ci[m][q] = d4{0, 0, 0, 0};
+    }
+  const int lr = threadIdx.x >> 4, le = threadIdx.x & 15;   // loader: 16 rows x 16 elements per pass
+  for (long e0 = e_begin; e0 < e_end; e0 += kGemmKC) {
+    const long e = e0 + le;
+    const bool ev = e < e_end;
+#pragma unroll
+    for (int r = lr; r < 64; r += 16) As[r * kGemmLd + le] = (ev && r < mb) ? A[(long)r * lda + e] : z64{0, 0};
+#pragma unroll
+    for (int r = lr; r < kGemmBRows; r += 16)
+      Bs[r * kGemmLd + le] = (ev && b0 + r < p) ? B[(long)(b0 + r) * ldb + e] : z64{0, 0};
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < kGemmKC; k4 += 4) {
+      z64 av[4], bv[2];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) av[m] = As[(16 * m + col) * kGemmLd + k4 + kl];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) bv[q] = Bs[(32 * w + 16 * q + col) * kGemmLd + k4 + kl];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
+          cr[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m].x, bv[q].x, cr[m][q], 0, 0, 0);
+          cr[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m].y, bv[q].y, cr[m][q], 0, 0, 0);
+          ci[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m].x, bv[q].y, ci[m][q], 0, 0, 0);
+          ci[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[m].y, bv[q].x, ci[m][q], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  z64* P = partial + (long)blockIdx.x * p * mb;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * m + 4 * r + kl;
+        const int b = b0 + 32 * w + 16 * q + col;
+        if (a < mb && b < p) P[(long)b * mb + a] = z64{cr[m][q][r], ci[m][q][r]};
+      }
+}
 
-// The band dots of the projector with A's rows as the bands (blocks of up to
-// 64, eight 8-row groups per wave) and B's rows as the systems:
-// partial[k][b][a], then the slice sum into C's columns of the block.
+int gemm_hn_slices(long n, int p) {
+  const int btiles = (p + kGemmBRows - 1) / kGemmBRows;
+  int ks = (1024 + btiles - 1) / btiles;                  // about four workgroups per compute unit
+  const long kmax = (n + 8 * kGemmKC - 1) / (8 * kGemmKC);   // at least 8 chunks per slice
+  if (ks > kmax) ks = (int)kmax;
+  return ks < 1 ? 1 : ks;
+}
+
+// Blocks of up to 64 rows of A: partial[k][b][a] from the tiled kernel, then
+// the slice sum into C's columns of the block.
 void launch_gemm_hn_mfma(const z64* A, long lda, int m, const z64* B, long ldb, int p, long n, z64* C, z64* partial,
                          hipStream_t s) {
-  if (m <= 0 || p <= 0) return;
-  const int nk = (int)n;
+  if (m <= 0 || p <= 0 || n <= 0) return;
   const int ks = gemm_hn_slices(n, p);
-  int kchunk = (nk + ks - 1) / ks;
-  kchunk = (kchunk + 3) & ~3;
-  const dim3 grid(ks, (p + 15) / 16);
+  long kchunk = (n + ks - 1) / ks;
+  kchunk = (kchunk + kGemmKC - 1) / kGemmKC * kGemmKC;
+  const dim3 grid(ks, (p + kGemmBRows - 1) / kGemmBRows);
   for (int a0 = 0; a0 < m; a0 += 64) {
     const int mb = m - a0 < 64 ? m - a0 : 64;
-    const z64* Ab = A + (long)a0 * lda;
-    switch ((mb + 7) / 8) {
-#define LGW_GEMM_HN_CASE(G) \
-      case G: k_proj_dots<double, G><<<grid, 64, 0, s>>>(Ab, lda, mb, nk, B, ldb, nullptr, p, kchunk, partial, nullptr); break;
-      LGW_GEMM_HN_CASE(1)
-      LGW_GEMM_HN_CASE(2)
-      LGW_GEMM_HN_CASE(3)
-      LGW_GEMM_HN_CASE(4)
-      LGW_GEMM_HN_CASE(5)
-      LGW_GEMM_HN_CASE(6)
-      LGW_GEMM_HN_CASE(7)
-      default: k_proj_dots<double, 8><<<grid, 64, 0, s>>>(Ab, lda, mb, nk, B, ldb, nullptr, p, kchunk, partial, nullptr); break;
-#undef LGW_GEMM_HN_CASE
-    }
+    k_gemm_hn_tiled<<<grid, 256, 0, s>>>(A + (long)a0 * lda, lda, mb, B, ldb, p, n, kchunk, partial);
     const long total = (long)p * mb;
     k_sum_slices<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(partial, ks, p, mb, C + a0, m);
   }
