@@ -143,6 +143,9 @@ struct lgw_ctx {
   // keyed by every pointer and size their capture bakes in; all are dropped
   // before any workspace buffer is reallocated
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+  // iterations the last small-batch solve of each (kind, precision) took: the
+  // next one runs that many before its first convergence poll
+  std::map<std::pair<int, int>, int> it_hint;
   void drop_graphs() {
     if (graphs.empty()) return;
     if (stream) (void)hipStreamSynchronize(stream);
@@ -437,6 +440,12 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   c->check_launch();
   const int check = std::max(1, c->opts.check_every);
   const int maxit = std::max(1, c->opts.max_iter);
+  // Small, launch-bound batches replay their chunks as HIP graphs; their first
+  // chunk is as long as the last solve of the same kind took (consecutive
+  // solves of a recursion need similar counts), then polls come every two
+  // iterations for a while, since a poll costs less than a few wasted ones.
+  const bool small = c->opts.use_graph && (int)act.size() <= lgw_ctx::kTimedMin && !c->time_all;
+  int& hint = c->it_hint[{b.kind, (int)sizeof(T)}];
   std::vector<int> flags(b.nsys), iters(b.nsys);
   std::vector<T> est(b.nsys);
   std::vector<double> best(b.nsys, 0.0);
@@ -473,7 +482,11 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
       if (act.empty() || it >= maxit) break;
       h2d_async(c, b.act, act.data(), act.size() * sizeof(int));
     }
-    const int chunk = std::min(check, maxit - it);
+    int chunk = std::min(check, maxit - it);
+    if (small && hint > 0) {
+      if (it == 0) chunk = std::min(hint, maxit);
+      else if (it < hint + check) chunk = std::min(2, maxit - it);
+    }
     const int na = (int)act.size();
     auto iterate = [&](int n_it) {
       for (int k = 0; k < n_it; ++k) {
@@ -493,12 +506,12 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
         }
       }
     };
-    // Small, launch-bound batches replay their full chunks as HIP graphs,
-    // instantiated once per key and kept by the context (the active list is
-    // read from device memory, so only its length is baked in).  A chunk is
-    // captured only after an eager one, so that every workspace buffer exists.
+    // Graphs are instantiated once per key and kept by the context (the active
+    // list is read from device memory, so only its length is baked in).  The
+    // projector's partial sums are sized for this batch before a capture, so
+    // that nothing allocates inside it.
     hipGraphExec_t gx = nullptr;
-    if (c->opts.use_graph && chunk == check && na <= lgw_ctx::kTimedMin && !c->time_all) {
+    if (small && na <= lgw_ctx::kTimedMin) {
       uint64_t tb;
       std::memcpy(&tb, &tol, sizeof tb);
       const std::vector<uintptr_t> key = {
@@ -511,8 +524,10 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
       auto f = c->graphs.find(key);
       if (f != c->graphs.end()) {
         gx = f->second;
-      } else if (it > 0) {
+      } else {
         if (c->graphs.size() >= 64) c->drop_graphs();
+        (void)c->buf<cplx<T>>(sizeof(T) == 8 ? "proj.part64" : "proj.part32",
+                              (size_t)proj_ksplit<T>(c->npw, na) * na * c->nv);
         const long long h0 = c->tot_h;
         hipGraph_t gr = nullptr;
         HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -535,10 +550,13 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     it += chunk;
   }
   // the loop ends at a poll, after the last launch: flags and iters are final
+  int most = 0;
   for (int s : start) {
     b.h_flags[s] = flags[s] ? flags[s] : FLAG_MAXIT;
     b.h_iters[s] = iters[s];
+    most = std::max(most, iters[s]);
   }
+  if (small) hint = most;
 }
 
 struct SolveOut {
