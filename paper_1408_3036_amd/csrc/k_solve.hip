@@ -1260,25 +1260,27 @@ k_ms_init(const z64* __restrict__ B, long ldb, const int* __restrict__ bidx, int
   if (threadIdx.x == 0) nrm[s] = n;
 }
 
-// Step j of the recursion for the listed systems.  On entry Q[s][j+1] holds
-// A q_j; on exit alpha_j = Re <q_j, A q_j>, w = A q_j - alpha_j q_j -
-// beta_{j-1} q_{j-1}, beta_j = |w| and Q[s][j+1] = w / beta_j.
+// Step j of the recursion for the listed systems.  On entry AQ[s][j] holds
+// A q_j (kept: the true residuals are formed from it); on exit
+// alpha_j = Re <q_j, A q_j>, w = A q_j - alpha_j q_j - beta_{j-1} q_{j-1},
+// beta_j = |w| and Q[s][j+1] = w / beta_j.
 __global__ void __launch_bounds__(NT)
-k_ms_step(z64* __restrict__ Q, long ldq, int npw, int j, const int* __restrict__ act, double* __restrict__ alpha,
-          double* __restrict__ beta, int kcap) {
+k_ms_step(z64* __restrict__ Q, const z64* __restrict__ AQ, long ldq, int npw, int j, const int* __restrict__ act,
+          double* __restrict__ alpha, double* __restrict__ beta, int kcap) {
   __shared__ double sm[NT / 64];
   const int s = act[blockIdx.x];
-  z64* q = Q + (long)s * ldq + (long)j * npw;
-  z64* w = q + npw;
+  const z64* q = Q + (long)s * ldq + (long)j * npw;
+  const z64* aq = AQ + (long)s * ldq + (long)j * npw;
+  z64* w = Q + (long)s * ldq + (long)(j + 1) * npw;
   const z64* qp = j > 0 ? q - npw : nullptr;
   double acc[1] = {0.0};
-  for (int i = threadIdx.x; i < npw; i += NT) acc[0] += q[i].x * w[i].x + q[i].y * w[i].y;
+  for (int i = threadIdx.x; i < npw; i += NT) acc[0] += q[i].x * aq[i].x + q[i].y * aq[i].y;
   block_sum<double, 1>(acc, sm);
   const double a = acc[0];
   const double bp = j > 0 ? beta[(long)s * kcap + j - 1] : 0.0;
   acc[0] = 0.0;
   for (int i = threadIdx.x; i < npw; i += NT) {
-    z64 v = w[i] - a * q[i];
+    z64 v = aq[i] - a * q[i];
     if (qp) v = v - bp * qp[i];
     w[i] = v;
     acc[0] += norm2(v);
@@ -1293,69 +1295,88 @@ k_ms_step(z64* __restrict__ Q, long ldq, int npw, int j, const int* __restrict__
   }
 }
 
-// X[s][t] = sum_{j < k[s]} Y[s][j][t] Q[s][j] for t < ntau, on
-// v_mfma_f64_16x16x4f64 (lane l holds A[l%16][l/16], B[l/16][l%16] and
-// D[4r + l/16][l%16]).  A wave computes a 64-shift x 32-plane-wave block: up
-// to four 16-row shift tiles (A = Y, rows padded to ntp, a multiple of 16;
-// grid z selects the group of 64 shifts) by two 16-column tiles (B = Q), each
-// complex product as four real ones; the Krylov index runs in steps of 4.
-// Rows j >= k[s] of Q are never read.
+// X[s][t] = Q[s] y and the true residual r = b_s - (A - tau_t) X[s][t] =
+// b_s - AQ[s] y + tau_t Q[s] y of every (system, shift), y = Y[s][.][t]
+// (rows padded to ntp, a multiple of 16; grid z selects the group of 64
+// shifts), AQ[s][j] = A q_j as the recursion applied it.  Rows j >= k[s] are
+// never read.  On v_mfma_f64_16x16x4f64 (lane l holds A[l%16][l/16],
+// B[l/16][l%16] and D[4r + l/16][l%16]) a wave computes 64 shifts x 16 plane
+// waves twice (Q y and AQ y), each complex product as four real ones; |r|^2
+// over the wave's 16 plane waves goes to part[(s * ntp + t) * nwt + tile].
 __global__ void __launch_bounds__(256)
-k_ms_combine(const z64* __restrict__ Q, long ldq, int npw, const int* __restrict__ kdone,
-             const z64* __restrict__ Y, int ldyj, int ntp, int ntau, z64* __restrict__ X) {
+k_ms_combine_res(const z64* __restrict__ Q, const z64* __restrict__ AQ, long ldq, int npw,
+                 const int* __restrict__ kdone, const z64* __restrict__ Y, int ldyj, int ntp, int ntau,
+                 const z64* __restrict__ tau, const z64* __restrict__ B, long ldb, const int* __restrict__ bidx,
+                 z64* __restrict__ X, double* __restrict__ part, int nwt) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   const int s = blockIdx.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i0 = (blockIdx.x * 4 + w) * 32;
+  const int wt = blockIdx.x * 4 + w;   // 16-plane-wave tile
+  const int i0 = wt * 16;
   if (i0 >= npw) return;   // no barriers below
   const int k = kdone[s];
   const z64* Qs = Q + (long)s * ldq;
+  const z64* AQs = AQ + (long)s * ldq;
   const z64* Ys = Y + (long)s * ldyj * ntp;
   const int col = lane & 15, kl = lane >> 4;
-  const int tb = 64 * blockIdx.z;                 // first shift of the group
-  const int nm = min(4, (ntp - tb) >> 4);         // its 16-row tiles
-  d4 cr[4][2], ci[4][2];
+  const int tb = 64 * blockIdx.z;
+  const int nm = min(4, (ntp - tb) >> 4);
+  const int i = i0 + col;
+  d4 xr[4], xi[4], ar[4], ai[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int n = 0; n < 2; ++n) {
-      cr[m][n] = d4{0, 0, 0, 0};
-      ci[m][n] = d4{0, 0, 0, 0};
-    }
+  for (int m = 0; m < 4; ++m) xr[m] = xi[m] = ar[m] = ai[m] = d4{0, 0, 0, 0};
   for (int j0 = 0; j0 < k; j0 += 4) {
     const int j = j0 + kl;
-    const bool jv = j < k;
-    z64 q[2], a[4];
+    const bool v = j < k && i < npw;
+    const z64 q = v ? Qs[(long)j * npw + i] : z64{0, 0};
+    const z64 aq = v ? AQs[(long)j * npw + i] : z64{0, 0};
+    z64 a[4];
 #pragma unroll
-    for (int n = 0; n < 2; ++n) {
-      const int i = i0 + 16 * n + col;
-      q[n] = (jv && i < npw) ? Qs[(long)j * npw + i] : z64{0, 0};
-    }
-#pragma unroll
-    for (int m = 0; m < 4; ++m) a[m] = (jv && m < nm) ? Ys[(long)j * ntp + tb + 16 * m + col] : z64{0, 0};
+    for (int m = 0; m < 4; ++m) a[m] = (j < k && m < nm) ? Ys[(long)j * ntp + tb + 16 * m + col] : z64{0, 0};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       if (m < nm) {
-#pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          cr[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, q[n].x, cr[m][n], 0, 0, 0);
-          cr[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[m].y, q[n].y, cr[m][n], 0, 0, 0);
-          ci[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, q[n].y, ci[m][n], 0, 0, 0);
-          ci[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].y, q[n].x, ci[m][n], 0, 0, 0);
-        }
+        xr[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, q.x, xr[m], 0, 0, 0);
+        xr[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[m].y, q.y, xr[m], 0, 0, 0);
+        xi[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, q.y, xi[m], 0, 0, 0);
+        xi[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].y, q.x, xi[m], 0, 0, 0);
+        ar[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, aq.x, ar[m], 0, 0, 0);
+        ar[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[m].y, aq.y, ar[m], 0, 0, 0);
+        ai[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].x, aq.y, ai[m], 0, 0, 0);
+        ai[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m].y, aq.x, ai[m], 0, 0, 0);
       }
     }
   }
+  const z64 bv = i < npw ? B[(long)bidx[s] * ldb + i] : z64{0, 0};
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int n = 0; n < 2; ++n)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int t = tb + 16 * m + 4 * r + kl;
-        const int i = i0 + 16 * n + col;
-        if (t < ntau && i < npw) X[((long)s * ntau + t) * npw + i] = z64{cr[m][n][r], ci[m][n][r]};
+    for (int r = 0; r < 4; ++r) {
+      const int t = tb + 16 * m + 4 * r + kl;   // one shift per 16-lane row group
+      double e = 0.0;
+      if (m < nm && t < ntau && i < npw) {
+        const z64 x{xr[m][r], xi[m][r]};
+        X[((long)s * ntau + t) * npw + i] = x;
+        const z64 ta = tau[t];
+        const double rx = bv.x - ar[m][r] + (ta.x * x.x - ta.y * x.y);
+        const double ry = bv.y - ai[m][r] + (ta.x * x.y + ta.y * x.x);
+        e = rx * rx + ry * ry;
       }
+      // sum over the 16 plane waves of the row group, fixed order
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) e += __shfl_xor(e, o, 16);
+      if (col == 0 && m < nm) part[((long)s * ntp + t) * nwt + wt] = e;
+    }
+}
+
+// res[r] = sum_w part[r * nwt + w], in order
+__global__ void __launch_bounds__(256) k_ms_res_sum(const double* __restrict__ part, int nwt, int rows,
+                                                    double* __restrict__ res) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  double acc = 0.0;
+  for (int w = 0; w < nwt; ++w) acc += part[(long)r * nwt + w];
+  res[r] = acc;
 }
 }  // namespace
 
@@ -1365,17 +1386,22 @@ void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, lo
   k_ms_init<<<nsys, NT, 0, s>>>(B, ldb, bidx, npw, Q, ldq, nrm);
 }
 
-void launch_ms_step(z64* Q, long ldq, int npw, int j, const int* act, int na, double* alpha, double* beta, int kcap,
-                    hipStream_t s) {
+void launch_ms_step(z64* Q, const z64* AQ, long ldq, int npw, int j, const int* act, int na, double* alpha,
+                    double* beta, int kcap, hipStream_t s) {
   if (na <= 0) return;
-  k_ms_step<<<na, NT, 0, s>>>(Q, ldq, npw, j, act, alpha, beta, kcap);
+  k_ms_step<<<na, NT, 0, s>>>(Q, AQ, ldq, npw, j, act, alpha, beta, kcap);
 }
 
-void launch_ms_combine(const z64* Q, long ldq, int npw, const int* kdone, const z64* Y, int ldyj, int ntp, int ntau,
-                       z64* X, int nsys, hipStream_t s) {
-  // ntp: ntau rounded up to a multiple of 16 (the caller's Y layout)
+int ms_res_tiles(int npw) { return (npw + 15) / 16; }
+
+void launch_ms_combine_res(const z64* Q, const z64* AQ, long ldq, int npw, const int* kdone, const z64* Y, int ldyj,
+                           int ntp, int ntau, const z64* tau, const z64* B, long ldb, const int* bidx, z64* X,
+                           double* part, double* res, int nsys, hipStream_t s) {
   if (nsys <= 0 || ntau <= 0) return;
-  k_ms_combine<<<dim3((npw + 127) / 128, nsys, (ntp + 63) / 64), 256, 0, s>>>(Q, ldq, npw, kdone, Y, ldyj, ntp,
-                                                                              ntau, X);
+  const int nwt = ms_res_tiles(npw);
+  k_ms_combine_res<<<dim3((nwt + 3) / 4, nsys, (ntp + 63) / 64), 256, 0, s>>>(Q, AQ, ldq, npw, kdone, Y, ldyj, ntp,
+                                                                               ntau, tau, B, ldb, bidx, X, part, nwt);
+  const int rows = nsys * ntp;
+  k_ms_res_sum<<<(rows + 255) / 256, 256, 0, s>>>(part, nwt, rows, res);
 }
 }  // namespace lgw

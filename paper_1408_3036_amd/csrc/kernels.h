@@ -166,12 +166,15 @@ namespace lgw {
 // alpha/beta [nsys][kcap]; Y [nsys][ntau][kcap]
 void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, long ldq, double* nrm, int nsys,
                     hipStream_t s);
-void launch_ms_step(z64* Q, long ldq, int npw, int j, const int* act, int na, double* alpha, double* beta, int kcap,
-                    hipStream_t s);
-// X[s][t] = sum_{j < kdone[s]} Y[s][j][t] Q[s][j] (Y: [nsys][ldyj][ntp], ntp =
-// ntau rounded up to a multiple of 16)
-void launch_ms_combine(const z64* Q, long ldq, int npw, const int* kdone, const z64* Y, int ldyj, int ntp, int ntau,
-                       z64* X, int nsys, hipStream_t s);
+void launch_ms_step(z64* Q, const z64* AQ, long ldq, int npw, int j, const int* act, int na, double* alpha,
+                    double* beta, int kcap, hipStream_t s);
+// X[s][t] = Q[s] y and res[s * ntp + t] = |b - AQ[s] y + tau_t X[s][t]|^2 with
+// y = Y[s][.][t], b = B[bidx[s]]; part needs nsys * ntp * ms_res_tiles(npw)
+// entries (rows t >= ntau of res are zero)
+int ms_res_tiles(int npw);
+void launch_ms_combine_res(const z64* Q, const z64* AQ, long ldq, int npw, const int* kdone, const z64* Y, int ldyj,
+                           int ntp, int ntau, const z64* tau, const z64* B, long ldb, const int* bidx, z64* X,
+                           double* part, double* res, int nsys, hipStream_t s);
 // C[b][a] = sum_e conj(A[a][e]) B[b][e] for a < m, b < p, on the matrix cores;
 // partial needs gemm_hn_slices(n, p) * min(m, 64) * p entries
 int gemm_hn_slices(long n, int p);

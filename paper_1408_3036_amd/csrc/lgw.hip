@@ -816,7 +816,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
   } time_all_guard{c, c->time_all};
   c->time_all = true;
   const int check = std::max(1, c->opts.check_every);
-  const double per = 16.0 * npw * ((kcap + 1) + 3.0 * ntau) + 16.0 * ldt * (1.0 + ntau);
+  const double per = 16.0 * npw * (2.0 * (kcap + 1) + 3.0 * ntau) + 16.0 * ldt * (1.0 + ntau);
   const double budget = std::max(0.25, c->opts.mem_budget_gb) * 1e9;
   const int cap = std::max(1, (int)std::min((double)nb, budget / per));
   lgw_status st = LGW_OK;
@@ -824,6 +824,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     const int n = std::min(cap, nb - s0);
     const long ldq = (long)(kcap + 1) * npw;
     z64* Q = c->buf<z64>("ms.Q", (size_t)n * ldq);
+    z64* AQ = c->buf<z64>("ms.AQ", (size_t)n * ldq);   // A q_j as applied, for the true residuals
     double* alpha = c->buf<double>("ms.al", (size_t)n * kcap);
     double* beta = c->buf<double>("ms.be", (size_t)n * kcap);
     double* nrm = c->buf<double>("ms.nrm", n);
@@ -860,9 +861,9 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
       const int na = (int)act.size();
       const int steps = std::min(check, kcap - j);
       for (int t = 0; t < steps; ++t, ++j) {
-        apply_op<double>(c, K_CGLIN, Q + (size_t)j * npw, Q + (size_t)(j + 1) * npw, nullptr, Tb, ldq, d_sh,
+        apply_op<double>(c, K_CGLIN, Q + (size_t)j * npw, AQ + (size_t)j * npw, nullptr, Tb, ldq, d_sh,
                          nullptr, d_act, na);
-        launch_ms_step(Q, ldq, npw, j, d_act, na, alpha, beta, kcap, c->stream);
+        launch_ms_step(Q, AQ, ldq, npw, j, d_act, na, alpha, beta, kcap, c->stream);
       }
       c->check_launch();
       HIPCHK(hipMemcpyAsync(ha.data(), alpha, ha.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -940,35 +941,54 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     h2d_async(c, d_kd, kd.data(), n * sizeof(int));
     const int nr = n * ntau;
     z64* X = c->buf<z64>("ms.X", (size_t)nr * npw);
-    launch_ms_combine(Q, ldq, npw, d_kd, Yd, kmax, ntp, ntau, X, n, c->stream);
+    // x_tau and its true residual b - (A - tau) x_tau = b - (A Q) y_tau + tau Q y_tau
+    // from the products A q_j the recursion applied (linearity of A; rounding
+    // of the same order as applying A to x_tau), for every (system, shift)
+    std::vector<z64> taup(ntp, z64{0, 0});
+    std::copy(tau.begin(), tau.end(), taup.begin());
+    z64* d_tau = c->buf<z64>("ms.tau", ntp);
+    h2d_async(c, d_tau, taup.data(), ntp * sizeof(z64));
+    double* rpart = c->buf<double>("ms.rpart", (size_t)n * ntp * ms_res_tiles(npw));
+    double* res = c->buf<double>("ms.res", (size_t)n * ntp);
+    launch_ms_combine_res(Q, AQ, ldq, npw, d_kd, Yd, kmax, ntp, ntau, d_tau, B0, npw, d_idx, X, rpart, res, n,
+                          c->stream);
     proj<double>(c, X, npw, nullptr, nr);
-    // true residuals b - (H - e_v - tau) x of every (system, shift)
-    std::vector<int> rb(nr);
-    std::vector<z64> rs(nr);
-    for (int s = 0; s < n; ++s)
-      for (int t = 0; t < ntau; ++t) {
-        rb[(size_t)s * ntau + t] = s0 + s;
-        rs[(size_t)s * ntau + t] = z64{sh[s].x + tau[t].x, tau[t].y};
-      }
-    int* d_rb = c->buf<int>("ms.rb", nr);
-    z64* d_rs = c->buf<z64>("ms.rs", nr);
-    h2d_async(c, d_rb, rb.data(), nr * sizeof(int));
-    h2d_async(c, d_rs, rs.data(), nr * sizeof(z64));
-    z64* AX = c->buf<z64>("ms.AX", (size_t)nr * npw);
-    z64* R = c->buf<z64>("ms.R", (size_t)nr * npw);
-    z64* TbV = c->buf<z64>("ms.TbV", (size_t)nr * ldt);
-    double* res = c->buf<double>("ms.res", nr);
-    apply_op<double>(c, K_SQMR, X, AX, nullptr, TbV, npw, d_rs, nullptr, nullptr, nr);
-    launch_resid<double>(B0, npw, d_rb, AX, npw, R, npw, res, npw, nullptr, nr, c->stream);
-    std::vector<double> hr(nr);
-    HIPCHK(hipMemcpyAsync(hr.data(), res, nr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> hres((size_t)n * ntp);
+    HIPCHK(hipMemcpyAsync(hres.data(), res, hres.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     c->sync();
-    std::vector<double> rel(nr, 0.0);
+    std::vector<double> hr(nr), rel(nr, 0.0);
     std::vector<int> fit(nr, 0), flg(nr, FLAG_CONV), bad;
     for (int r = 0; r < nr; ++r) {
+      hr[r] = hres[(size_t)(r / ntau) * ntp + r % ntau];
       const double nb2 = hn[r / ntau];
       rel[r] = nb2 > 0.0 ? std::sqrt(hr[r]) / nb2 : 0.0;
       if (rel[r] > tol) bad.push_back(r);
+    }
+    // shifts of row r = s * ntau + t: e_v + tau_t (the systems (H - e_v - tau) x = b)
+    std::vector<z64> rs(nr);
+    for (int s = 0; s < n; ++s)
+      for (int t = 0; t < ntau; ++t) rs[(size_t)s * ntau + t] = z64{sh[s].x + tau[t].x, tau[t].y};
+    z64* R = nullptr;
+    if (!bad.empty()) {
+      // the residual vectors of the rows to correct, from an explicit H application
+      std::vector<int> rb(nr);
+      for (int r = 0; r < nr; ++r) rb[r] = s0 + r / ntau;
+      int* d_rb = c->buf<int>("ms.rb", nr);
+      z64* d_rs = c->buf<z64>("ms.rs", nr);
+      int* d_bad = c->buf<int>("ms.bad", bad.size());
+      h2d_async(c, d_rb, rb.data(), nr * sizeof(int));
+      h2d_async(c, d_rs, rs.data(), nr * sizeof(z64));
+      h2d_async(c, d_bad, bad.data(), bad.size() * sizeof(int));
+      z64* AX = c->buf<z64>("ms.AX", (size_t)nr * npw);
+      R = c->buf<z64>("ms.R", (size_t)nr * npw);
+      z64* TbV = c->buf<z64>("ms.TbV", (size_t)nr * ldt);
+      double* rres = c->buf<double>("ms.rres", nr);
+      apply_op<double>(c, K_SQMR, X, AX, nullptr, TbV, npw, d_rs, nullptr, d_bad, (int)bad.size());
+      launch_resid<double>(B0, npw, d_rb, AX, npw, R, npw, rres, npw, d_bad, (int)bad.size(), c->stream);
+      std::vector<double> hrr(nr);
+      HIPCHK(hipMemcpyAsync(hrr.data(), rres, nr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      for (int r : bad) hr[r] = hrr[r];
     }
     if (!bad.empty()) {
       // correction on the true residual with the shifted solver (SQMR)
@@ -2369,12 +2389,19 @@ lgw_status lgw_lanczos_project(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, c
       cv.notify_one();
       pushed = upto;
     };
+    // Chunks taper towards the end of the recursion (full ones while two remain,
+    // then half of what remains, at least a quarter chunk), so that the work
+    // left once the last vector exists is a small chunk.
+    auto next_size = [&] {
+      const int rem = k - pushed;
+      return rem >= 2 * kChunk ? kChunk : std::max(std::max(1, kChunk / 4), rem / 2);
+    };
     int m = 0;
     lgw_status st = LGW_OK;
     try {
       st = lanczos_core(c, k, Qd, iz0 >= 0 ? W + (size_t)iz0 * k * n3 : nullptr, ab, ab + k, &m,
                         [&](int avail) {
-                          if (avail - pushed >= kChunk) push(avail);
+                          if (avail - pushed >= next_size()) push(avail);
                         });
       if (m > pushed) push(m);
     } catch (...) {
