@@ -198,6 +198,25 @@ lgw_status lgw_chi0_apply_vjp(lgw_ctx* ctx, int n_rhs, const lgw_c128* dV, int n
 lgw_status lgw_lanczos_project(lgw_ctx* ctx, const lgw_c128* q0, int k, int n_z, const lgw_c128* z,
                                double* alpha, double* beta, lgw_c128* Q, lgw_c128* E, int* k_done);
 
+/* Frequency recycling (Sec. VI): the static Lanczos basis of lgw_lanczos and
+ * eps(i w) - 1 projected on it at imaginary frequencies without a Sternheimer
+ * solve per frequency.  For every valence band the recursion's right-hand
+ * sides b_{l,v} and static solutions x_{l,v}(0), with the large-frequency
+ * directions P (H - e_v) b_{l,v}, span a basis gamma_v (Gram eigen-
+ * decomposition, directions below 1e-7 of the largest singular value dropped,
+ * then orthonormalised to rounding); H - e_v and b are expressed in it once,
+ * and each imaginary-axis band solution is taken as
+ * gamma 2 h (h^2 + w^2)^-1 gamma^H b with h = gamma^H (H - e_v) gamma.  The
+ * result is exact at w = 0 and an approximation elsewhere (Sec. VI checks it by
+ * enlarging the basis).
+ *   w      [n_w]  frequencies w >= 0 of the points i*w (host memory); EINVAL
+ *                 otherwise (the real axis is not recycled)
+ *   alpha, beta, Q, k_done as lgw_lanczos; E [n_w][k][k] as lgw_project (the
+ *          leading k_done x k_done block written, the rest zero).
+ * Workspace: 2 k N_v N_pw for the captured vectors and about 6 k N_v N_pw more. */
+lgw_status lgw_lanczos_recycle(lgw_ctx* ctx, const lgw_c128* q0, int k, int n_w, const double* w,
+                               double* alpha, double* beta, lgw_c128* Q, lgw_c128* E, int* k_done);
+
 /* Loss of the Lanczos-projected dielectric matrix and its gradient:
  *   L = sum_z log det(I + E(z)),  E(z) = Q^H (eps(z) - 1) Q,
  * with Q the k Lanczos vectors of eps(0) - 1 from q0 (as lgw_lanczos: the

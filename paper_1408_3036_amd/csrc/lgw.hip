@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
@@ -11,12 +12,14 @@
 #include <memory>
 #include <string>
 #include <thread>
+#include <exception>
 #include <functional>
 #include <mutex>
 #include <condition_variable>
 #include <deque>
 #include <vector>
 
+#include "herm_eig.h"
 #include "kernels.h"
 
 // lgw_lanczos_project: Lanczos vectors per projection chunk, and the number
@@ -143,6 +146,11 @@ struct lgw_ctx {
   // keyed by every pointer and size their capture bakes in; all are dropped
   // before any workspace buffer is reallocated
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+  // frequency recycling: per-step copies of the band right-hand sides and the
+  // static solutions of the recursion's chi0 applications (off while null)
+  z64* keep_b = nullptr;
+  z64* keep_f = nullptr;
+  int keep_n = 0, keep_cap = 0;
   // iterations the last small-batch solve of each (kind, precision) took: the
   // next one runs that many before its first convergence poll
   std::map<std::pair<int, int>, int> it_hint;
@@ -1181,6 +1189,12 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
     run_kind(K_CGSQ, sq);
     run_kind(K_SQMR, qm);
   }
+  if (c->keep_b && nz == 1 && zl[0].re == 0.0 && zl[0].im == 0.0 && c->keep_n + nrhs <= c->keep_cap) {
+    const size_t off = (size_t)c->keep_n * nb * npw, bytes = (size_t)nb * npw * sizeof(z64);
+    HIPCHK(hipMemcpyAsync(c->keep_b + off, B0, bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->keep_f + off, F, bytes, hipMemcpyDeviceToDevice, c->stream));
+    c->keep_n += nrhs;
+  }
   // dn_j(z) = -2 sum_v psi_v Scatter(f_{j,v}(z))
   for (int k = 0; k < nz; ++k) {
     launch_zinv<double>(c->geom, c->d_tw64.as<z64>(), F + (size_t)k * nb * npw, npw, Tb, ldt, 1.0, nullptr, nb,
@@ -1761,6 +1775,216 @@ lgw_status lanczos_reverse(lgw_ctx* c, int m, const z64* Qd, const z64* W0, cons
   return st;
 }
 
+
+// ---------------------------------------------------------------- recycling
+// Frequency recycling of the static basis (Sec. VI).  Bk, Fk: [m][nv][npw]
+// right-hand sides b_{l,v} and static solutions f_{l,v}(0) of the recursion.
+// For every band: the basis gamma of span{f_{l,v}(0), P (H - e_v) P b_{l,v}}
+// (Gram matrix on the matrix cores, its eigen-decomposition on the host with
+// directions below 1e-7 of the largest singular value dropped, then a Cholesky
+// pass so that gamma is orthonormal to rounding), h = gamma^H (H - e_v) gamma,
+// and gamma^H b.  The imaginary-axis solution f = 2 A (A^2 + w^2)^-1 b
+// (A = P (H - e_v) P) is taken as gamma 2 h (h^2 + w^2)^-1 gamma^H b, so with
+// h = W diag(e) W^H and B' = W^H gamma^H b,
+//   E(i w)[a][b] = <q_a, (eps(i w) - 1) q_b> = (2 / dV) sum_v <b_{a,v}, f_{b,v}>
+//                = (4 / dV) sum_v sum_i conj(B'_v[i][a]) e_i / (e_i^2 + w^2) B'_v[i][b].
+// E: host [n_w][m][m].
+void recycle_E(lgw_ctx* c, int m, const z64* Bk, const z64* Fk, int n_w, const double* w, std::vector<z64>& E) {
+  const int nv = c->nv, npw = c->npw, n2 = 2 * m;
+  const long ldt = (long)c->N * c->ncols;
+  const int nb = m * nv;
+  E.assign((size_t)n_w * m * m, z64{0, 0});
+  // large-frequency directions D = P (H - e_v) P b (b is projected)
+  z64* D = c->buf<z64>("rc.D", (size_t)nb * npw);
+  z64* Tb = c->buf<z64>("rc.Tb", (size_t)std::max(nb, nv * n2) * ldt);
+  z64* d_sh = c->buf<z64>("rc.sh", (size_t)std::max(nb, nv * n2));
+  std::vector<z64> sh(nb);
+  for (int p = 0; p < nb; ++p) sh[p] = z64{c->eps[p % nv], 0.0};
+  h2d_async(c, d_sh, sh.data(), nb * sizeof(z64));
+  happly<double>(c, Bk, npw, D, npw, d_sh, nullptr, 0, nullptr, Tb, nullptr, nb);
+  proj<double>(c, D, npw, nullptr, nb);
+  // V_v = [f_{0..m-1,v}(0); D_{0..m-1,v}] contiguous, and their Gram matrices
+  z64* Vb = c->buf<z64>("rc.V", (size_t)nv * n2 * npw);
+  const size_t row = (size_t)npw * sizeof(z64);
+  for (int v = 0; v < nv; ++v) {
+    z64* Vv = Vb + (size_t)v * n2 * npw;
+    HIPCHK(hipMemcpy2DAsync(Vv, row, Fk + (size_t)v * npw, nv * row, row, m, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpy2DAsync(Vv + (size_t)m * npw, row, D + (size_t)v * npw, nv * row, row, m,
+                            hipMemcpyDeviceToDevice, c->stream));
+  }
+  z64* Gd = c->buf<z64>("rc.G", (size_t)nv * n2 * n2);
+  // the K split is largest for the fewest B rows: size for one, times the most rows
+  z64* part = c->buf<z64>("rc.part", (size_t)gemm_hn_slices(npw, 1) * std::min(n2, 64) * n2);
+  for (int v = 0; v < nv; ++v)
+    launch_gemm_hn_mfma(Vb + (size_t)v * n2 * npw, npw, n2, Vb + (size_t)v * n2 * npw, npw, n2, npw,
+                        Gd + (size_t)v * n2 * n2, part, c->stream);
+  std::vector<z64> hG((size_t)nv * n2 * n2);
+  HIPCHK(hipMemcpyAsync(hG.data(), Gd, hG.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  // bands in parallel host threads
+  auto par = [&](auto&& fn) {
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> ex(nv);
+    for (int v = 0; v < nv; ++v)
+      th.emplace_back([&, v] {
+        try {
+          fn(v);
+        } catch (...) {
+          ex[v] = std::current_exception();
+        }
+      });
+    for (auto& t : th) t.join();
+    for (auto& e : ex)
+      if (e) std::rethrow_exception(e);
+  };
+  // first pass: M = U diag(lam) U^H (M[a][b] = <V_a, V_b>), T1[k][l] = lam_k^-1/2 U[l][k]
+  std::vector<int> r(nv, 0);
+  std::vector<std::vector<z64>> T1(nv);
+  par([&](int v) {
+    std::vector<std::complex<double>> M((size_t)n2 * n2);
+    for (int a = 0; a < n2; ++a)
+      for (int b = 0; b < n2; ++b) {
+        const z64 g = hG[((size_t)v * n2 + b) * n2 + a];
+        const z64 gt = hG[((size_t)v * n2 + a) * n2 + b];
+        M[(size_t)a * n2 + b] = {0.5 * (g.x + gt.x), 0.5 * (g.y - gt.y)};   // exactly Hermitian
+      }
+    std::vector<double> lam;
+    std::vector<std::complex<double>> U;
+    herm_eig(n2, M.data(), lam, U);
+    const double top = lam.empty() ? 0.0 : lam.back();
+    std::vector<int> keep;
+    for (int k = n2 - 1; k >= 0; --k)
+      if (top > 0.0 && lam[k] > 1e-14 * top) keep.push_back(k);
+    r[v] = (int)keep.size();
+    T1[v].assign((size_t)r[v] * n2, z64{0, 0});
+    for (int i = 0; i < r[v]; ++i) {
+      const int k = keep[i];
+      const double sc = 1.0 / std::sqrt(lam[k]);
+      for (int l = 0; l < n2; ++l) {
+        const auto u = U[(size_t)l * n2 + k];
+        T1[v][(size_t)i * n2 + l] = z64{sc * u.real(), sc * u.imag()};
+      }
+    }
+  });
+  int rsum = 0;
+  for (int v = 0; v < nv; ++v) rsum += r[v];
+  if (rsum == 0) return;
+  // gamma = T V (block_sub subtracts: coefficients negated into a zeroed buffer)
+  z64* Gam = c->buf<z64>("rc.Gam", (size_t)nv * n2 * npw);
+  z64* Cm = c->buf<z64>("rc.Cm", (size_t)nv * n2 * n2);
+  auto combine = [&](const std::vector<std::vector<z64>>& T) {
+    std::vector<z64> hc((size_t)nv * n2 * n2, z64{0, 0});
+    for (int v = 0; v < nv; ++v)
+      for (size_t q = 0; q < T[v].size(); ++q) hc[(size_t)v * n2 * n2 + q] = z64{-T[v][q].x, -T[v][q].y};
+    h2d(c, Cm, hc.data(), hc.size() * sizeof(z64));
+    HIPCHK(hipMemsetAsync(Gam, 0, (size_t)nv * n2 * npw * sizeof(z64), c->stream));
+    for (int v = 0; v < nv; ++v)
+      launch_block_sub(Gam + (size_t)v * n2 * npw, npw, r[v], Vb + (size_t)v * n2 * npw, npw, n2,
+                       Cm + (size_t)v * n2 * n2, npw, c->stream);
+  };
+  combine(T1);
+  // second pass: M2[a][b] = <g1_a, g1_b> = L L^H, T = conj(L^-1) T1
+  for (int v = 0; v < nv; ++v)
+    if (r[v] > 0)
+      launch_gemm_hn_mfma(Gam + (size_t)v * n2 * npw, npw, r[v], Gam + (size_t)v * n2 * npw, npw, r[v], npw,
+                          Gd + (size_t)v * n2 * n2, part, c->stream);
+  HIPCHK(hipMemcpyAsync(hG.data(), Gd, hG.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  std::vector<std::vector<z64>> T(nv);
+  for (int v = 0; v < nv; ++v) {
+    const int rv = r[v];
+    if (rv == 0) continue;
+    std::vector<z64> M2((size_t)rv * rv), Linv;
+    for (int a = 0; a < rv; ++a)
+      for (int b = 0; b < rv; ++b) {
+        const z64 g = hG[(size_t)v * n2 * n2 + (size_t)b * rv + a];
+        const z64 gt = hG[(size_t)v * n2 * n2 + (size_t)a * rv + b];
+        M2[(size_t)a * rv + b] = z64{0.5 * (g.x + gt.x), 0.5 * (g.y - gt.y)};
+      }
+    if (!chol_lower_inverse(M2, rv, Linv)) throw Fail{LGW_EBREAKDOWN, "recycling basis lost orthogonality"};
+    T[v].assign((size_t)rv * n2, z64{0, 0});
+    for (int i = 0; i < rv; ++i)
+      for (int j = 0; j <= i; ++j) {
+        const z64 li{Linv[(size_t)i * rv + j].x, -Linv[(size_t)i * rv + j].y};
+        for (int l = 0; l < n2; ++l)
+          T[v][(size_t)i * n2 + l] = T[v][(size_t)i * n2 + l] + li * T1[v][(size_t)j * n2 + l];
+      }
+  }
+  combine(T);
+  // h and gamma^H b: (H - e_v) gamma for every band in one application (rows v * n2 + i)
+  z64* HG = c->buf<z64>("rc.HG", (size_t)nv * n2 * npw);
+  std::vector<int> rows;
+  std::vector<z64> shg((size_t)nv * n2, z64{0, 0});
+  for (int v = 0; v < nv; ++v)
+    for (int i = 0; i < r[v]; ++i) {
+      rows.push_back(v * n2 + i);
+      shg[(size_t)v * n2 + i] = z64{c->eps[v], 0.0};
+    }
+  int* d_rows = c->buf<int>("rc.rows", rows.size());
+  h2d_async(c, d_rows, rows.data(), rows.size() * sizeof(int));
+  h2d_async(c, d_sh, shg.data(), shg.size() * sizeof(z64));
+  happly<double>(c, Gam, npw, HG, npw, d_sh, nullptr, 0, nullptr, Tb, d_rows, (int)rows.size());
+  proj<double>(c, HG, npw, d_rows, (int)rows.size());
+  z64* Hh = c->buf<z64>("rc.h", (size_t)nv * n2 * n2);
+  z64* Bg = c->buf<z64>("rc.bg", (size_t)nv * n2 * m);
+  for (int v = 0; v < nv; ++v) {
+    if (r[v] == 0) continue;
+    const z64* Gv = Gam + (size_t)v * n2 * npw;
+    launch_gemm_hn_mfma(Gv, npw, r[v], HG + (size_t)v * n2 * npw, npw, r[v], npw, Hh + (size_t)v * n2 * n2, part,
+                        c->stream);   // [b][a] = <g_a, H g_b>
+    launch_gemm_hn_mfma(Gv, npw, r[v], Bk + (size_t)v * npw, (long)nv * npw, m, npw, Bg + (size_t)v * n2 * m, part,
+                        c->stream);   // [l][a] = <g_a, b_l>
+  }
+  std::vector<z64> hh((size_t)nv * n2 * n2), hb((size_t)nv * n2 * m);
+  HIPCHK(hipMemcpyAsync(hh.data(), Hh, hh.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(hb.data(), Bg, hb.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  // per band: h = W diag(e) W^H, B' = W^H (gamma^H b), and its part of E
+  std::vector<std::vector<z64>> Ev(nv);
+  const double pref = 4.0 / c->dV;
+  par([&](int v) {
+    const int rv = r[v];
+    Ev[v].assign((size_t)n_w * m * m, z64{0, 0});
+    if (rv == 0) return;
+    std::vector<std::complex<double>> h((size_t)rv * rv);
+    for (int a = 0; a < rv; ++a)
+      for (int b = 0; b < rv; ++b) {
+        const z64 x = hh[(size_t)v * n2 * n2 + (size_t)b * rv + a];    // <g_a, H g_b>
+        const z64 xt = hh[(size_t)v * n2 * n2 + (size_t)a * rv + b];   // <g_b, H g_a>
+        h[(size_t)a * rv + b] = {0.5 * (x.x + xt.x), 0.5 * (x.y - xt.y)};
+      }
+    std::vector<double> e;
+    std::vector<std::complex<double>> W;
+    herm_eig(rv, h.data(), e, W);
+    std::vector<std::complex<double>> Bp((size_t)rv * m);   // B'[i][l]
+    for (int i = 0; i < rv; ++i)
+      for (int l = 0; l < m; ++l) {
+        std::complex<double> acc(0, 0);
+        for (int a = 0; a < rv; ++a) {
+          const z64 g = hb[(size_t)v * n2 * m + (size_t)l * rv + a];
+          acc += std::conj(W[(size_t)a * rv + i]) * std::complex<double>(g.x, g.y);
+        }
+        Bp[(size_t)i * m + l] = acc;
+      }
+    for (int q = 0; q < n_w; ++q) {
+      const double w2 = w[q] * w[q];
+      for (int i = 0; i < rv; ++i) {
+        const double f = pref * e[i] / (e[i] * e[i] + w2);
+        for (int a = 0; a < m; ++a) {
+          const std::complex<double> ca = f * std::conj(Bp[(size_t)i * m + a]);
+          z64* Er = Ev[v].data() + ((size_t)q * m + a) * m;
+          for (int b = 0; b < m; ++b) {
+            const std::complex<double> t = ca * Bp[(size_t)i * m + b];
+            Er[b] = z64{Er[b].x + t.real(), Er[b].y + t.imag()};
+          }
+        }
+      }
+    }
+  });
+  for (int v = 0; v < nv; ++v)
+    for (size_t q = 0; q < E.size(); ++q) E[q] = E[q] + Ev[v][q];
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -2161,6 +2385,70 @@ lgw_status lgw_lanczos(lgw_ctx* c, const lgw_c128* q0, int k, double* alpha, dou
     } else {
       HIPCHK(hipMemcpyAsync(alpha, d_alpha, done * sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipMemcpyAsync(beta, d_beta, done * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    if (Q) {
+      const size_t qb = (size_t)done * n3 * sizeof(z64);
+      z64* dq = static_cast<z64*>(stage_out(c, Q, qb, "io.Qout"));
+      launch_zxy_to_xyz(c->N, Qd, n3, dq, n3, done, c->stream);
+      c->check_launch();
+      c->sync();
+      finish_out(c, Q, dq, qb);
+    }
+    c->sync();
+    *k_done = done;
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_lanczos_recycle(lgw_ctx* c, const lgw_c128* q0, int k, int n_w, const double* w, double* alpha,
+                               double* beta, lgw_c128* Q, lgw_c128* E, int* k_done) {
+  if (!c) return LGW_EINVAL;
+  if (k < 1 || n_w < 1 || !q0 || !w || !alpha || !beta || !E || !k_done)
+    return set_err(c, LGW_EINVAL, "invalid arguments");
+  for (int i = 0; i < n_w; ++i)
+    if (!std::isfinite(w[i]) || w[i] < 0.0)
+      return set_err(c, LGW_EINVAL, "recycling frequencies are i*w with finite w >= 0");
+  struct KeepOff {
+    lgw_ctx* c;
+    ~KeepOff() {
+      c->keep_b = c->keep_f = nullptr;
+      c->keep_n = c->keep_cap = 0;
+    }
+  } keep_off{c};
+  try {
+    const long n3 = c->n3;
+    const int nv = c->nv, npw = c->npw;
+    z64* Qd = c->buf<z64>("lz.Q", (size_t)k * n3);
+    double* ab = c->buf<double>("lz.ab", 2 * (size_t)k);
+    z64* Bk = c->buf<z64>("rc.Bk", (size_t)k * nv * npw);
+    z64* Fk = c->buf<z64>("rc.Fk", (size_t)k * nv * npw);
+    const lgw_status pre = lanczos_start(c, q0, Qd);
+    if (pre != LGW_OK) return pre;
+    c->keep_b = Bk;
+    c->keep_f = Fk;
+    c->keep_n = 0;
+    c->keep_cap = k;
+    int done = 0;
+    const lgw_status st = lanczos_core(c, k, Qd, nullptr, ab, ab + k, &done);
+    const int m = std::min(done, c->keep_n);
+    c->keep_b = c->keep_f = nullptr;
+    std::vector<z64> Eh;
+    if (m > 0) recycle_E(c, m, Bk, Fk, n_w, w, Eh);
+    std::vector<z64> e((size_t)n_w * k * k, z64{0, 0});
+    for (int i = 0; i < n_w; ++i)
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) e[((size_t)i * k + a) * k + b] = Eh[((size_t)i * m + a) * m + b];
+    if (c->opts.mem == LGW_MEM_DEVICE) {
+      h2d(c, E, e.data(), e.size() * sizeof(z64));
+      HIPCHK(hipMemcpyAsync(alpha, ab, done * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(beta, ab + k, done * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      std::memcpy(E, e.data(), e.size() * sizeof(z64));
+      HIPCHK(hipMemcpyAsync(alpha, ab, done * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(beta, ab + k, done * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     }
     if (Q) {
       const size_t qb = (size_t)done * n3 * sizeof(z64);

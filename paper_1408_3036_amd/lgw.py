@@ -79,6 +79,7 @@ def load_library():
     lib.lgw_chi0_apply.argtypes = [P, I, P, I, C.POINTER(c128), P]
     lib.lgw_lanczos.argtypes = [P, P, I, P, P, P, C.POINTER(I)]
     lib.lgw_lanczos_project.argtypes = [P, P, I, I, C.POINTER(c128), P, P, P, P, C.POINTER(I)]
+    lib.lgw_lanczos_recycle.argtypes = [P, P, I, I, C.POINTER(C.c_double), P, P, P, P, C.POINTER(I)]
     lib.lgw_project.argtypes = [P, I, P, I, C.POINTER(c128), P]
     lib.lgw_block_lanczos.argtypes = [P, I, P, I, P, P, P, C.POINTER(I)]
     lib.lgw_chi0_apply_vjp.argtypes = [P, I, P, I, C.POINTER(c128), P, P, P]
@@ -275,6 +276,26 @@ class Lgw:
         t.cuda.synchronize()
         self.last_status = self._check(self.lib.lgw_lanczos_project(
             self.ctx, q0.data_ptr(), k, nz, zarr, alpha.data_ptr(), beta.data_ptr(),
+            Q.data_ptr() if Q is not None else None, E.data_ptr(), C.byref(kd)))
+        n = kd.value
+        return alpha[:n], beta[:n], (Q[:n] if Q is not None else None), E[:, :n, :n], n
+
+    def lanczos_recycle(self, q0, k: int, w, want_Q: bool = True):
+        """lanczos(q0, k) and eps(i w) - 1 on its vectors at the imaginary
+        frequencies i*w by frequency recycling (one small basis per band).
+        Returns (alpha, beta, Q, E [n_w, k_done, k_done], k_done)."""
+        t = self.torch
+        q0 = self._dev(q0, t.complex128).reshape(-1)
+        wl = [float(x) for x in w]
+        warr = (C.c_double * len(wl))(*wl)
+        alpha = t.zeros(k, dtype=t.float64, device="cuda")
+        beta = t.zeros(k, dtype=t.float64, device="cuda")
+        Q = t.zeros((k, self.N ** 3), dtype=t.complex128, device="cuda") if want_Q else None
+        E = t.zeros((len(wl), k, k), dtype=t.complex128, device="cuda")
+        kd = C.c_int(0)
+        t.cuda.synchronize()
+        self.last_status = self._check(self.lib.lgw_lanczos_recycle(
+            self.ctx, q0.data_ptr(), k, len(wl), warr, alpha.data_ptr(), beta.data_ptr(),
             Q.data_ptr() if Q is not None else None, E.data_ptr(), C.byref(kd)))
         n = kd.value
         return alpha[:n], beta[:n], (Q[:n] if Q is not None else None), E[:, :n, :n], n

@@ -230,3 +230,38 @@ def test_lanczos_loss_gradient_silane48():
         err = abs(got - fd) / abs(fd)
         print(f"silane-48 loss gradient, direction {i}: grad.d {got:.10e} FD {fd:.10e} rel {err:.2e}")
         assert err < 1e-5
+
+
+def test_silane48_recycling_against_direct_projection():
+    """Frequency recycling at the benchmark's size: 64 static Lanczos vectors,
+    the 16 imaginary frequencies of the workload.  The static block equals T;
+    the recycled E(i w) is compared with the direct projection (multi-shift
+    solves) on the same basis, and the time of the recycling step reported."""
+    w = make_workload(2)
+    zs = [z for z in w.z if z.real == 0.0]
+    ws = [z.imag for z in zs]
+    q0 = torch.from_numpy(random_potentials(w.N, 1, 76)[0])
+    lg = _lgw(w, precision="mixed", tol=1e-10, precond=True, imag_form="shifted", multishift=True)
+    try:
+        lg.lanczos_recycle(q0, 8, ws[:2], want_Q=False)   # warm-up
+        torch.cuda.synchronize()
+        t = time.time()
+        a, be, Q, E, kd = lg.lanczos_recycle(q0, 64, ws)
+        torch.cuda.synchronize()
+        t_rec = time.time() - t
+        t = time.time()
+        a2, be2, Q2, kd2 = lg.lanczos(q0, 64)
+        torch.cuda.synchronize()
+        t_lz = time.time() - t
+        Ed = lg.project(Q, zs).cpu().numpy()
+    finally:
+        lg.close()
+    assert kd == 64
+    E = E.cpu().numpy()
+    T = olz.tridiag(a.cpu().numpy(), be.cpu().numpy())
+    assert rel(E[0], T) < 1e-8
+    errs = [rel(E[i], Ed[i]) for i in range(len(ws))]
+    print(f"silane-48 recycling: lanczos+recycle {t_rec:.3f}s (lanczos alone {t_lz:.3f}s); "
+          f"rel. deviation from direct projection: max {max(errs):.2e} "
+          f"(w=0 {errs[0]:.1e}, w={ws[5]:.3f} {errs[5]:.1e}, w={ws[-1]:.2f} {errs[-1]:.1e})")
+    assert max(errs) < 0.1
