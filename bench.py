@@ -52,7 +52,7 @@ def hpsi_model_bytes(npw: int, ncols: int, N: int, elem: int) -> float:
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ["k_fft.hip", "fft_lds.h", "common.h"]:
+    for f in ["k_fft.hip", "fft_lds.h", "common.h", "k_solve.hip"]:
         with open(os.path.join(ROOT, "paper_1408_3036_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
