@@ -91,6 +91,14 @@ typedef struct {
                           its true residual, and those above tol are corrected
                           by the shifted solver.  0 (default): one Krylov solve
                           per shift                                           */
+  int    model;        /* 1: the model dielectric operator of Sec. V (Eq.
+                          (model_eq)): H -> T in the Sternheimer equations, so
+                          each band solution is P (T - e_v -+ z)^-1 P b, one
+                          diagonal division instead of a Krylov solve (terms
+                          with a vanishing denominator are dropped).  Every
+                          chi0 / Lanczos / projection call then works on
+                          eps~ - 1, the second basis of Sec. V; the VJP and
+                          recycling calls return EINVAL.  0 (default): H      */
 } lgw_opts;
 
 /* Fill *opts with the defaults listed above. */

@@ -1380,6 +1380,34 @@ __global__ void __launch_bounds__(256) k_ms_res_sum(const double* __restrict__ p
 }
 }  // namespace
 
+namespace {
+// F[k][p][i] = b_p[i] / (kin[i] - e_v - z_k) + b_p[i] / (kin[i] - e_v + z_k),
+// v = p mod nv; a term whose denominator vanishes is dropped
+__global__ void __launch_bounds__(256)
+k_model_div(const z64* __restrict__ B, int npw, const double* __restrict__ kin, const double* __restrict__ eps, int nv,
+            int nb, const z64* __restrict__ zl, z64* __restrict__ F) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int p = blockIdx.y, k = blockIdx.z;
+  if (i >= npw) return;
+  const z64 b = B[(long)p * npw + i];
+  const double d = kin[i] - eps[p % nv];
+  const z64 z = zl[k];
+  z64 f{0, 0};
+  for (int sgn = -1; sgn <= 1; sgn += 2) {
+    const double dr = d + sgn * z.x, di = sgn * z.y;   // d -+ z with sgn = -1, +1
+    const double den = dr * dr + di * di;
+    if (den > 0.0) f = f + z64{(b.x * dr + b.y * di) / den, (b.y * dr - b.x * di) / den};
+  }
+  F[((long)k * nb + p) * npw + i] = f;
+}
+}  // namespace
+
+void launch_model_div(const z64* B, int npw, const double* kin, const double* eps, int nv, int nb, const z64* zl,
+                      int nz, z64* F, hipStream_t s) {
+  if (nb <= 0 || nz <= 0) return;
+  k_model_div<<<dim3((npw + 255) / 256, nb, nz), 256, 0, s>>>(B, npw, kin, eps, nv, nb, zl, F);
+}
+
 void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, long ldq, double* nrm, int nsys,
                     hipStream_t s) {
   if (nsys <= 0) return;

@@ -164,6 +164,10 @@ void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act
 namespace lgw {
 // Multi-shift Lanczos: Q rows of system s at Q + s * ldq (k vectors of npw);
 // alpha/beta [nsys][kcap]; Y [nsys][ntau][kcap]
+// model operator (H -> T): F[k][p] = B[p] / (kin - e_{p mod nv} - z_k) + B[p] / (kin - e_{p mod nv} + z_k),
+// terms with a vanishing denominator dropped
+void launch_model_div(const z64* B, int npw, const double* kin, const double* eps, int nv, int nb, const z64* zl,
+                      int nz, z64* F, hipStream_t s);
 void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, long ldq, double* nrm, int nsys,
                     hipStream_t s);
 void launch_ms_step(z64* Q, const z64* AQ, long ldq, int npw, int j, const int* act, int na, double* alpha,

@@ -1089,6 +1089,30 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
                       nullptr, 0, nullptr, B0, npw, nullptr, nb, c->stream);
   proj<double>(c, B0, npw, nullptr, nb);
   launch_add(B2, B0, B0, (long)nb * npw, c->stream);
+  if (c->opts.model == 1) {
+    // model operator (H -> T): f[z][p] = P ((T - e_v - z)^-1 + (T - e_v + z)^-1) b_p
+    z64* F = c->buf<z64>("c.F", (size_t)nz * nb * npw);
+    double* d_eps = c->buf<double>("c.eps", nv);
+    z64* d_z = c->buf<z64>("c.z", nz);
+    std::vector<z64> hz(nz);
+    for (int k = 0; k < nz; ++k) hz[k] = z64{zl[k].re, zl[k].im};
+    h2d_async(c, d_eps, c->eps.data(), nv * sizeof(double));
+    h2d_async(c, d_z, hz.data(), nz * sizeof(z64));
+    launch_model_div(B0, npw, c->d_kin.as<double>(), d_eps, nv, nb, d_z, nz, F, c->stream);
+    proj<double>(c, F, npw, nullptr, nz * nb);
+    c->st_iters.assign((size_t)nz * nb, 0);
+    c->st_flags.assign((size_t)nz * nb, FLAG_CONV);
+    c->st_sweeps.assign((size_t)nz * nb, 0);
+    c->st_res.assign((size_t)nz * nb, 0.0);
+    for (int k = 0; k < nz; ++k) {
+      launch_zinv<double>(c->geom, c->d_tw64.as<z64>(), F + (size_t)k * nb * npw, npw, Tb, ldt, 1.0, nullptr, nb,
+                          c->stream);
+      launch_plane_acc<double>(c->geom, c->d_tw64.as<z64>(), Tb, ldt, c->d_psi.as<z64>(), nv,
+                               out + (size_t)k * ldz, n3, -2.0 / std::sqrt(c->omega), nrhs, false, c->stream);
+    }
+    c->check_launch();
+    return LGW_OK;
+  }
   // all frequencies from one Lanczos recursion per system when there are at
   // least three shifts (one frequency is left to the preconditioned solvers)
   int nshift = 0;
@@ -2008,6 +2032,7 @@ void lgw_default_opts(lgw_opts* o) {
   o->precond_shift = 3.0;
   o->imag_form = 0;
   o->multishift = 0;
+  o->model = 0;
 }
 
 lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], double ecut, const double* V_loc,
@@ -2042,6 +2067,7 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
     return bad("precond_shift must be positive");
   if (o.imag_form != 0 && o.imag_form != 1) return bad("imag_form must be 0 or 1");
   if (o.multishift != 0 && o.multishift != 1) return bad("multishift must be 0 or 1");
+  if (o.model != 0 && o.model != 1) return bad("model must be 0 or 1");
   if (o.mem != LGW_MEM_DEVICE && o.mem != LGW_MEM_HOST) return bad("invalid mem mode");
   const int N = grid[0];
   const long n3 = (long)N * N * N;
@@ -2406,6 +2432,7 @@ lgw_status lgw_lanczos(lgw_ctx* c, const lgw_c128* q0, int k, double* alpha, dou
 lgw_status lgw_lanczos_recycle(lgw_ctx* c, const lgw_c128* q0, int k, int n_w, const double* w, double* alpha,
                                double* beta, lgw_c128* Q, lgw_c128* E, int* k_done) {
   if (!c) return LGW_EINVAL;
+  if (c->opts.model == 1) return set_err(c, LGW_EINVAL, "recycling works on the exact operator (model = 0)");
   if (k < 1 || n_w < 1 || !q0 || !w || !alpha || !beta || !E || !k_done)
     return set_err(c, LGW_EINVAL, "invalid arguments");
   for (int i = 0; i < n_w; ++i)
@@ -2470,6 +2497,7 @@ lgw_status lgw_lanczos_recycle(lgw_ctx* c, const lgw_c128* q0, int k, int n_w, c
 lgw_status lgw_lanczos_loss_vjp(lgw_ctx* c, const lgw_c128* q0, int k, int n_z, const lgw_c128* z, double* loss,
                                 double* g_Vloc, int* k_done) {
   if (!c) return LGW_EINVAL;
+  if (c->opts.model == 1) return set_err(c, LGW_EINVAL, "the adjoint is of the exact operator (model = 0)");
   if (k < 1 || n_z < 1 || !q0 || !z || !loss) return set_err(c, LGW_EINVAL, "invalid arguments");
   for (int i = 0; i < n_z; ++i) {
     if (!std::isfinite(z[i].re) || !std::isfinite(z[i].im)) return set_err(c, LGW_ENAN, "non-finite frequency");
@@ -2991,6 +3019,7 @@ lgw_status lgw_project(lgw_ctx* c, int k, const lgw_c128* Q, int n_z, const lgw_
 lgw_status lgw_chi0_apply_vjp(lgw_ctx* c, int n_rhs, const lgw_c128* dV, int n_z, const lgw_c128* z,
                               const lgw_c128* g_dn, lgw_c128* g_dV, double* g_Vloc) {
   if (!c) return LGW_EINVAL;
+  if (c->opts.model == 1) return set_err(c, LGW_EINVAL, "the adjoint is of the exact operator (model = 0)");
   if (n_rhs < 1 || n_z < 1 || !dV || !z || !g_dn || (!g_dV && !g_Vloc))
     return set_err(c, LGW_EINVAL, "invalid arguments");
   for (int k = 0; k < n_z; ++k)

@@ -36,7 +36,8 @@ class Opts(C.Structure):
                 ("check_every", C.c_int), ("precond", C.c_int), ("deterministic", C.c_int),
                 ("mem", C.c_int), ("stream", C.c_void_p), ("mem_budget_gb", C.c_double),
                 ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("use_graph", C.c_int),
-                ("precond_shift", C.c_double), ("imag_form", C.c_int), ("multishift", C.c_int)]
+                ("precond_shift", C.c_double), ("imag_form", C.c_int), ("multishift", C.c_int),
+                ("model", C.c_int)]
 
 
 class Info(C.Structure):
@@ -121,7 +122,8 @@ class Lgw:
     diagonal kinetic preconditioner and imag_form="shifted" solves the
     imaginary axis as two shifted SQMR systems instead of the squared form;
     multishift=True solves all frequencies of a call from one Lanczos recursion
-    per (column, band).
+    per (column, band); model=True works on the model dielectric operator
+    (H -> T in the Sternheimer equations).
     """
 
     def __init__(self, L, N: int, ecut: float, V, psi, eps, precision: str = "fp64",
@@ -130,7 +132,7 @@ class Lgw:
                  inner_tol: float | None = None, max_sweeps: int | None = None,
                  use_graph: bool | None = None, precond: bool | None = None,
                  precond_shift: float | None = None, imag_form: str | None = None,
-                 multishift: bool | None = None):
+                 multishift: bool | None = None, model: bool | None = None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -162,6 +164,8 @@ class Lgw:
             opts.imag_form = {"squared": 0, "shifted": 1}[imag_form]
         if multishift is not None:
             opts.multishift = int(multishift)
+        if model is not None:
+            opts.model = int(model)
         self.opts = opts
         V = self._dev(V, torch.float64).reshape(-1)
         psi = self._dev(psi, torch.complex128).reshape(len(eps), -1)

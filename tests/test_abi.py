@@ -60,6 +60,8 @@ def _setup(lib, **kw):
     (dict(opts={"precond": 2}), "precond"),
     (dict(opts={"precond": 1, "precond_shift": 0.0}), "precond_shift"),
     (dict(opts={"imag_form": 3}), "imag_form"),
+    (dict(opts={"multishift": 2}), "multishift"),
+    (dict(opts={"model": 2}), "model"),
 ])
 def test_setup_rejects_invalid_arguments_on_the_host(kw, msg):
     lib = _lib()

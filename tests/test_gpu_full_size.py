@@ -265,3 +265,21 @@ def test_silane48_recycling_against_direct_projection():
           f"rel. deviation from direct projection: max {max(errs):.2e} "
           f"(w=0 {errs[0]:.1e}, w={ws[5]:.3f} {errs[5]:.1e}, w={ws[-1]:.2f} {errs[-1]:.1e})")
     assert max(errs) < 0.1
+
+
+def test_silane48_model_operator_against_oracle():
+    """The model dielectric operator (H -> T) at the benchmark's size: four
+    columns at three frequencies against the oracle."""
+    from oracle.model import Model
+    w = make_workload(2)
+    md = Model(Basis(w.L, w.N, w.ecut), w.psi, w.eps)
+    lg = _lgw(w, model=True)
+    try:
+        x = random_potentials(w.N, 4, 77)
+        zs = [0.0, 0.7j, 0.5 + 0.0036749j]
+        dn = lg.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+    finally:
+        lg.close()
+    for k, z in enumerate(zs):
+        for j in range(4):
+            assert rel(dn[k, j], md.chi0(z, x[j])) < 1e-12

@@ -522,3 +522,38 @@ def test_recycling_matches_oracle(sysc1, prec):
         exact = olz.project(lambda z, v: s.M(z, v), Q, [1j * x])[0]
         print(f"recycling {prec} w={x}: vs oracle {err:.2e}; vs direct projection {rel(E[i], exact):.2e}")
         assert err < bar
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_model_operator_matches_oracle(sysc1, prec):
+    """The model dielectric operator of Sec. V (H -> T, option model): chi0~
+    against the oracle at four frequencies, the Lanczos basis of eps~(0) - 1 and
+    E~(z) on it; the adjoint and recycling calls refuse the option."""
+    from paper_1408_3036_amd import Lgw
+    from oracle.model import Model
+    w, b, s, _ = sysc1
+    md = Model(b, w.psi, w.eps)
+    kw = dict(tol=1e-13) if prec == "fp64" else dict(precision="mixed", tol=1e-10)
+    lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps, model=True, **kw)
+    try:
+        x = random_potentials(w.N, 2, 94)
+        zs = [0.0, 0.4j, 0.3 + 0.0036749j, 2.0j]
+        dn = lg.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+        for k, z in enumerate(zs):
+            for j in range(2):
+                assert rel(dn[k, j], md.chi0(z, x[j])) < 1e-12
+        q0 = random_potentials(w.N, 1, 95)[0]
+        a, be, Q, E, kd = lg.lanczos_project(torch.from_numpy(q0), 6, zs)
+        ra, rb, _, _ = olz.lanczos(lambda v: md.M(0.0, v), q0, 6)
+        assert kd == 6
+        assert np.abs(a.cpu().numpy() - ra).max() < 1e-11 * np.abs(ra).max()
+        assert np.abs(be.cpu().numpy() - rb).max() < 1e-11 * np.abs(ra).max()
+        ref = olz.project(md.M, Q.cpu().numpy(), zs)
+        for k in range(len(zs)):
+            assert rel(E[k].cpu().numpy(), ref[k]) < 1e-11
+        with pytest.raises(RuntimeError):
+            lg.lanczos_recycle(torch.from_numpy(q0), 4, [0.5])
+        with pytest.raises(RuntimeError):
+            lg.lanczos_loss_vjp(torch.from_numpy(q0), 4, [0.5j])
+    finally:
+        lg.close()
