@@ -1260,39 +1260,79 @@ k_ms_init(const z64* __restrict__ B, long ldb, const int* __restrict__ bidx, int
   if (threadIdx.x == 0) nrm[s] = n;
 }
 
-// Step j of the recursion for the listed systems.  On entry AQ[s][j] holds
-// A q_j (kept: the true residuals are formed from it); on exit
+// Step j of the recursion for the listed systems, spread over kMsSplit
+// workgroups per system (three launches, fixed-order sums).  On entry
+// AQ[s][j] holds A q_j (kept: the true residuals are formed from it); on exit
 // alpha_j = Re <q_j, A q_j>, w = A q_j - alpha_j q_j - beta_{j-1} q_{j-1},
 // beta_j = |w| and Q[s][j+1] = w / beta_j.
+constexpr int kMsSplit = 16;
+
+__device__ __forceinline__ void ms_slice(int npw, int& i0, int& i1) {
+  const int chunk = (npw + kMsSplit - 1) / kMsSplit;
+  i0 = blockIdx.x * chunk;
+  i1 = min(npw, i0 + chunk);
+}
+
+// part[slot][blk] = the slice's share of Re <q_j, A q_j>
 __global__ void __launch_bounds__(NT)
-k_ms_step(z64* __restrict__ Q, const z64* __restrict__ AQ, long ldq, int npw, int j, const int* __restrict__ act,
-          double* __restrict__ alpha, double* __restrict__ beta, int kcap) {
+k_ms_dot(const z64* __restrict__ Q, const z64* __restrict__ AQ, long ldq, int npw, int j,
+         const int* __restrict__ act, double* __restrict__ part) {
   __shared__ double sm[NT / 64];
-  const int s = act[blockIdx.x];
+  const int s = act[blockIdx.y];
+  int i0, i1;
+  ms_slice(npw, i0, i1);
   const z64* q = Q + (long)s * ldq + (long)j * npw;
   const z64* aq = AQ + (long)s * ldq + (long)j * npw;
-  z64* w = Q + (long)s * ldq + (long)(j + 1) * npw;
-  const z64* qp = j > 0 ? q - npw : nullptr;
   double acc[1] = {0.0};
-  for (int i = threadIdx.x; i < npw; i += NT) acc[0] += q[i].x * aq[i].x + q[i].y * aq[i].y;
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) acc[0] += q[i].x * aq[i].x + q[i].y * aq[i].y;
   block_sum<double, 1>(acc, sm);
-  const double a = acc[0];
+  if (threadIdx.x == 0) part[blockIdx.y * kMsSplit + blockIdx.x] = acc[0];
+}
+
+// alpha_j from the partials; w into Q[s][j+1]; part2[slot][blk] = the slice's |w|^2
+__global__ void __launch_bounds__(NT)
+k_ms_upd(z64* __restrict__ Q, const z64* __restrict__ AQ, long ldq, int npw, int j, const int* __restrict__ act,
+         const double* __restrict__ part, double* __restrict__ part2, double* __restrict__ alpha,
+         const double* __restrict__ beta, int kcap) {
+  __shared__ double sm[NT / 64];
+  const int slot = blockIdx.y, s = act[slot];
+  double a = 0.0;
+  for (int b = 0; b < kMsSplit; ++b) a += part[slot * kMsSplit + b];
   const double bp = j > 0 ? beta[(long)s * kcap + j - 1] : 0.0;
-  acc[0] = 0.0;
-  for (int i = threadIdx.x; i < npw; i += NT) {
+  int i0, i1;
+  ms_slice(npw, i0, i1);
+  const z64* q = Q + (long)s * ldq + (long)j * npw;
+  const z64* aq = AQ + (long)s * ldq + (long)j * npw;
+  const z64* qp = j > 0 ? q - npw : nullptr;
+  z64* w = Q + (long)s * ldq + (long)(j + 1) * npw;
+  double acc[1] = {0.0};
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) {
     z64 v = aq[i] - a * q[i];
     if (qp) v = v - bp * qp[i];
     w[i] = v;
     acc[0] += norm2(v);
   }
   block_sum<double, 1>(acc, sm);
-  const double b = sqrt(acc[0]);
-  const double inv = b > 0.0 ? 1.0 / b : 0.0;
-  for (int i = threadIdx.x; i < npw; i += NT) w[i] = inv * w[i];
   if (threadIdx.x == 0) {
-    alpha[(long)s * kcap + j] = a;
-    beta[(long)s * kcap + j] = b;
+    part2[slot * kMsSplit + blockIdx.x] = acc[0];
+    if (blockIdx.x == 0) alpha[(long)s * kcap + j] = a;
   }
+}
+
+// beta_j = |w| from the partials; Q[s][j+1] = w / beta_j
+__global__ void __launch_bounds__(NT)
+k_ms_norm(z64* __restrict__ Q, long ldq, int npw, int j, const int* __restrict__ act,
+          const double* __restrict__ part2, double* __restrict__ beta, int kcap) {
+  const int slot = blockIdx.y, s = act[slot];
+  double b2 = 0.0;
+  for (int b = 0; b < kMsSplit; ++b) b2 += part2[slot * kMsSplit + b];
+  const double bn = sqrt(b2);
+  const double inv = bn > 0.0 ? 1.0 / bn : 0.0;
+  int i0, i1;
+  ms_slice(npw, i0, i1);
+  z64* w = Q + (long)s * ldq + (long)(j + 1) * npw;
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) w[i] = inv * w[i];
+  if (threadIdx.x == 0 && blockIdx.x == 0) beta[(long)s * kcap + j] = bn;
 }
 
 // X[s][t] = Q[s] y and the true residual r = b_s - (A - tau_t) X[s][t] =
@@ -1414,10 +1454,17 @@ void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, lo
   k_ms_init<<<nsys, NT, 0, s>>>(B, ldb, bidx, npw, Q, ldq, nrm);
 }
 
+int ms_step_scratch(int na) { return 2 * na * kMsSplit; }
+
 void launch_ms_step(z64* Q, const z64* AQ, long ldq, int npw, int j, const int* act, int na, double* alpha,
-                    double* beta, int kcap, hipStream_t s) {
+                    double* beta, int kcap, double* scratch, hipStream_t s) {
   if (na <= 0) return;
-  k_ms_step<<<na, NT, 0, s>>>(Q, AQ, ldq, npw, j, act, alpha, beta, kcap);
+  const dim3 grid(kMsSplit, na);
+  double* part = scratch;
+  double* part2 = scratch + (size_t)na * kMsSplit;
+  k_ms_dot<<<grid, NT, 0, s>>>(Q, AQ, ldq, npw, j, act, part);
+  k_ms_upd<<<grid, NT, 0, s>>>(Q, AQ, ldq, npw, j, act, part, part2, alpha, beta, kcap);
+  k_ms_norm<<<grid, NT, 0, s>>>(Q, ldq, npw, j, act, part2, beta, kcap);
 }
 
 int ms_res_tiles(int npw) { return (npw + 15) / 16; }

@@ -170,8 +170,10 @@ void launch_model_div(const z64* B, int npw, const double* kin, const double* ep
                       int nz, z64* F, hipStream_t s);
 void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, long ldq, double* nrm, int nsys,
                     hipStream_t s);
+// scratch needs ms_step_scratch(na) doubles
+int ms_step_scratch(int na);
 void launch_ms_step(z64* Q, const z64* AQ, long ldq, int npw, int j, const int* act, int na, double* alpha,
-                    double* beta, int kcap, hipStream_t s);
+                    double* beta, int kcap, double* scratch, hipStream_t s);
 // X[s][t] = Q[s] y and res[s * ntp + t] = |b - AQ[s] y + tau_t X[s][t]|^2 with
 // y = Y[s][.][t], b = B[bidx[s]]; part needs nsys * ntp * ms_res_tiles(npw)
 // entries (rows t >= ntau of res are zero)

@@ -833,6 +833,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     const long ldq = (long)(kcap + 1) * npw;
     z64* Q = c->buf<z64>("ms.Q", (size_t)n * ldq);
     z64* AQ = c->buf<z64>("ms.AQ", (size_t)n * ldq);   // A q_j as applied, for the true residuals
+    double* mscratch = c->buf<double>("ms.scr", ms_step_scratch(n));
     double* alpha = c->buf<double>("ms.al", (size_t)n * kcap);
     double* beta = c->buf<double>("ms.be", (size_t)n * kcap);
     double* nrm = c->buf<double>("ms.nrm", n);
@@ -871,7 +872,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
       for (int t = 0; t < steps; ++t, ++j) {
         apply_op<double>(c, K_CGLIN, Q + (size_t)j * npw, AQ + (size_t)j * npw, nullptr, Tb, ldq, d_sh,
                          nullptr, d_act, na);
-        launch_ms_step(Q, AQ, ldq, npw, j, d_act, na, alpha, beta, kcap, c->stream);
+        launch_ms_step(Q, AQ, ldq, npw, j, d_act, na, alpha, beta, kcap, mscratch, c->stream);
       }
       c->check_launch();
       HIPCHK(hipMemcpyAsync(ha.data(), alpha, ha.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
