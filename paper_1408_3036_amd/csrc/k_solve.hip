@@ -1442,6 +1442,22 @@ k_model_div(const z64* __restrict__ B, int npw, const double* __restrict__ kin, 
 }
 }  // namespace
 
+namespace {
+__global__ void __launch_bounds__(256) k_sqrt_inv(const double* __restrict__ bb, double* __restrict__ r,
+                                                  double* __restrict__ ir, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double v = sqrt(bb[i]);
+  r[i] = v;
+  ir[i] = v > 0.0 ? 1.0 / v : 0.0;
+}
+}  // namespace
+
+void launch_sqrt_inv(const double* bb, double* r, double* ir, int n, hipStream_t s) {
+  if (n <= 0) return;
+  k_sqrt_inv<<<(n + 255) / 256, 256, 0, s>>>(bb, r, ir, n);
+}
+
 void launch_model_div(const z64* B, int npw, const double* kin, const double* eps, int nv, int nb, const z64* zl,
                       int nz, z64* F, hipStream_t s) {
   if (nb <= 0 || nz <= 0) return;

@@ -164,6 +164,8 @@ void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act
 namespace lgw {
 // Multi-shift Lanczos: Q rows of system s at Q + s * ldq (k vectors of npw);
 // alpha/beta [nsys][kcap]; Y [nsys][ntau][kcap]
+// r = sqrt(bb), ir = 1 / r (0 where bb = 0)
+void launch_sqrt_inv(const double* bb, double* r, double* ir, int n, hipStream_t s);
 // model operator (H -> T): F[k][p] = B[p] / (kin - e_{p mod nv} - z_k) + B[p] / (kin - e_{p mod nv} + z_k),
 // terms with a vanishing denominator dropped
 void launch_model_div(const z64* B, int npw, const double* kin, const double* eps, int nv, int nb, const z64* zl,

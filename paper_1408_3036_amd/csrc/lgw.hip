@@ -602,15 +602,12 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
   std::vector<int> all(nsys);
   for (int s = 0; s < nsys; ++s) all[s] = s;
   h2d_async(c, d_act, all.data(), nsys * sizeof(int));
-  // |b|^2 per system
+  // |b|^2 per system (|B - 0|^2 with a zero AX), read back with the first true
+  // residuals: the host needs it only to form relative residuals
   std::vector<double> h_bb(nsys), h_res(nsys);
-  {
-    // res = |B - 0|^2 computed with a zero AX
-    HIPCHK(hipMemsetAsync(AX, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
-    launch_resid<double>(B, npw, d_bidx, AX, npw, nullptr, 0, bb, npw, d_act, nsys, c->stream);
-    HIPCHK(hipMemcpyAsync(h_bb.data(), bb, nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
-  }
+  bool have_bb = false;
+  HIPCHK(hipMemsetAsync(AX, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
+  launch_resid<double>(B, npw, d_bidx, AX, npw, nullptr, 0, bb, npw, d_act, nsys, c->stream);
   // true residual R = B - A X over the listed systems; returns rel. residuals
   auto true_resid = [&](const std::vector<int>& lst) {
     if (lst.empty()) return;
@@ -622,7 +619,9 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
     apply_op<double>(c, kind, X, AX, tmp, Tb, npw, d_shift, d_w2, d_act, (int)lst.size());
     launch_resid<double>(B, npw, d_bidx, AX, npw, R, npw, res, npw, d_act, (int)lst.size(), c->stream);
     HIPCHK(hipMemcpyAsync(h_res.data(), res, nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (!have_bb) HIPCHK(hipMemcpyAsync(h_bb.data(), bb, nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     c->sync();
+    have_bb = true;
     for (int s : lst) out.rel[s] = h_bb[s] > 0 ? std::sqrt(h_res[s] / h_bb[s]) : 0.0;
   };
 
@@ -690,10 +689,9 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
     // mixed precision: X = 0, R = B
     HIPCHK(hipMemsetAsync(X, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
     launch_rows_out(B, npw, R, npw, d_act /*identity rows*/, d_bidx, nullptr, npw, nsys, c->stream);
-    for (int s = 0; s < nsys; ++s) {
-      h_res[s] = h_bb[s];
-      out.rel[s] = h_bb[s] > 0 ? 1.0 : 0.0;
-    }
+    // every system enters the first sweep (a zero right-hand side gets zero
+    // scalings and converges at initialisation)
+    for (int s = 0; s < nsys; ++s) out.rel[s] = 1.0;
     std::vector<cplx<float>> sh32(nsys);
     std::vector<float> w32(nsys);
     for (int s = 0; s < nsys; ++s) {
@@ -714,13 +712,19 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
         if (out.rel[s] > tol && out.flags[s] == 0) bad.push_back(s);
       if (bad.empty()) break;
       for (int s : bad) {
-        h_rs[s] = std::sqrt(h_res[s]);
-        h_irs[s] = h_rs[s] > 0 ? 1.0 / h_rs[s] : 0.0;
         out.sweeps[s] += 1;
         prev[s] = out.rel[s];
       }
-      h2d_async(c, rs, h_rs.data(), nsys * sizeof(double));
-      h2d_async(c, irs, h_irs.data(), nsys * sizeof(double));
+      if (sweep == 0) {
+        launch_sqrt_inv(bb, rs, irs, nsys, c->stream);   // |b| and 1/|b| from the device's |b|^2
+      } else {
+        for (int s : bad) {
+          h_rs[s] = std::sqrt(h_res[s]);
+          h_irs[s] = h_rs[s] > 0 ? 1.0 / h_rs[s] : 0.0;
+        }
+        h2d_async(c, rs, h_rs.data(), nsys * sizeof(double));
+        h2d_async(c, irs, h_irs.data(), nsys * sizeof(double));
+      }
       h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
       launch_scale_cvt(R, npw, R32, npw, irs, d_act, npw, (int)bad.size(), c->stream);
       if (b.pre) launch_scale_diag<float>(R32, npw, d_act, R32, npw, d_act, b.pre, npw, (int)bad.size(), c->stream);
@@ -1196,7 +1200,6 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
       h2d_async(c, d_idx, all.data(), all.size() * sizeof(int));
       launch_rows_out(Xs, npw, F, npw, d_idx, d_idx + np, kind == K_SQMR ? d_idx + 2 * np : nullptr, npw, np,
                       c->stream);
-      c->sync();
       for (int i = 0; i < n; ++i) {
         c->st_iters.push_back(so.iters[i]);
         c->st_flags.push_back(so.flags[i]);
