@@ -194,10 +194,11 @@ lgw_status lgw_chi0_apply_vjp(lgw_ctx* ctx, int n_rhs, const lgw_c128* dV, int n
                               double* g_Vloc);
 
 /* lgw_lanczos followed by lgw_project on its vectors, with the projection
- * overlapped: every 8 finished Lanczos vectors are projected at all
- * frequencies by one of two worker threads, each on its own stream and twin of
- * the context (created on the first call and kept with it), while the
- * recursion continues.  The products
+ * overlapped: finished Lanczos vectors are projected at all frequencies in
+ * chunks (8 vectors, 16 with opts.multishift; towards the end of the
+ * recursion the chunks taper to a quarter of that) by one of two worker
+ * threads, each on its own stream and twin of the context (created on the
+ * first call and kept with it), while the recursion continues.  The products
  * (eps(0) - 1) q_j of the recursion serve z = 0.  Outputs as lgw_lanczos
  * (alpha, beta [k], Q [k][N^3] or NULL, k_done) and lgw_project (E
  * [n_z][k][k]; with k_done < k only the leading k_done x k_done block of each
