@@ -283,3 +283,34 @@ def test_silane48_model_operator_against_oracle():
     for k, z in enumerate(zs):
         for j in range(4):
             assert rel(dn[k, j], md.chi0(z, x[j])) < 1e-12
+
+
+def test_large72_recycling_and_model():
+    """72^3 box, 16 valence bands, 38,401 plane waves: the recycled static block
+    equals the Lanczos tridiagonal (16 per-band bases, two projector band
+    groups), and the model operator matches the oracle on two columns."""
+    from oracle.model import Model
+    w = make_workload(3)
+    b = Basis(w.L, w.N, w.ecut)
+    q0 = torch.from_numpy(random_potentials(w.N, 1, 78)[0])
+    lg = _lgw(w, tol=1e-12, precond=True, imag_form="shifted")
+    try:
+        a, be, _, E, kd = lg.lanczos_recycle(q0, 4, [0.0, 0.5], want_Q=False)
+    finally:
+        lg.close()
+    assert kd == 4
+    T = olz.tridiag(a.cpu().numpy(), be.cpu().numpy())
+    E = E.cpu().numpy()
+    assert rel(E[0], T) < 1e-9
+    assert np.all(np.linalg.eigvalsh(0.5 * (E[1] + E[1].conj().T)) > -1e-12)   # eps(i w) - 1 >= 0
+    md = Model(b, w.psi, w.eps)
+    lm = _lgw(w, model=True)
+    try:
+        x = random_potentials(w.N, 2, 79)
+        zs = [0.0, 0.9j]
+        dn = lm.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+    finally:
+        lm.close()
+    for k, z in enumerate(zs):
+        for j in range(2):
+            assert rel(dn[k, j], md.chi0(z, x[j])) < 1e-12
