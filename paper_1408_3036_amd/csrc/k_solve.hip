@@ -75,6 +75,34 @@ k_proj(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, cplx<T>* __
 }
 
 // ---------------------------------------------------------------- CG
+// Projector partial sums left for the next operator application (ProjFeed):
+// acc[2u], acc[2u+1] += conj(Phi_{v0+u}[i]) (pre[i] y) for the bands
+// v0 + u < nv of one group of eight
+template <typename T>
+__device__ __forceinline__ void feed_acc(const ProjFeed<T>& f, int v0, int i, cplx<T> y, T (&acc)[16]) {
+  if (f.pre) y = f.pre[i] * y;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    if (v0 + u < f.nv) {
+      const cplx<T> ph = f.Phi[(long)(v0 + u) * f.ldphi + i];
+      acc[2 * u] += ph.x * y.x + ph.y * y.y;
+      acc[2 * u + 1] += ph.x * y.y - ph.y * y.x;
+    }
+  }
+}
+// the group's block sums (every thread holds them) to slice k of system sys
+template <typename T>
+__device__ __forceinline__ void feed_store(const ProjFeed<T>& f, int v0, int k, int sys, const T (&acc)[16]) {
+  if (threadIdx.x != 0) return;
+  cplx<T>* P = f.part + ((long)k * f.ntot + sys) * f.nv;
+  for (int u = 0; u < 8 && v0 + u < f.nv; ++u) P[v0 + u] = cplx<T>{acc[2 * u], acc[2 * u + 1]};
+}
+template <typename T>
+__device__ __forceinline__ void feed_zero(T (&acc)[16]) {
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = T(0);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_cg_init(SolveVecs<T> v, const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx,
@@ -99,6 +127,25 @@ k_cg_init(SolveVecs<T> v, const cplx<T>* __restrict__ b, long ldb, const int* __
     v.theta[sys] = T(-1);
     if (!keep_x) { v.bb[sys] = acc[0]; v.iters[sys] = 0; }
     v.flag[sys] = acc[0] == T(0) ? FLAG_CONV : 0;
+  }
+}
+
+// the projector sums of the first direction p = b, by slice: grid (nsplit, nsys)
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_feed_init(ProjFeed<T> f, const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx, int npw,
+            const int* __restrict__ act) {
+  __shared__ T sm[16 * (NT / 64)];
+  const int sys = sys_of(act, blockIdx.y);
+  const cplx<T>* bs = b + (long)(bidx ? bidx[sys] : sys) * ldb;
+  const int chunk = (npw + f.nsplit - 1) / f.nsplit;
+  const int i0 = blockIdx.x * chunk, i1 = min(npw, i0 + chunk);
+  T fa[16];
+  for (int v0 = 0; v0 < f.nv; v0 += 8) {
+    feed_zero(fa);
+    for (int i = i0 + threadIdx.x; i < i1; i += NT) feed_acc(f, v0, i, bs[i], fa);
+    block_sum<T, 16>(fa, sm);
+    feed_store(f, v0, blockIdx.x, sys, fa);
   }
 }
 
@@ -461,9 +508,10 @@ void launch_proj(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, lo
 
 template <typename T>
 void launch_cg_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw, int nsys,
-                    bool keep_x, const int* act, hipStream_t s) {
+                    bool keep_x, const int* act, hipStream_t s, const ProjFeed<T>& f) {
   if (nsys <= 0) return;
   k_cg_init<T><<<nsys, NT, 0, s>>>(v, b, ldb, bidx, npw, keep_x ? 1 : 0, act);
+  if (f.part && f.nv > 0) k_feed_init<T><<<dim3(f.nsplit, nsys), NT, 0, s>>>(f, b, ldb, bidx, npw, act);
 }
 
 template <typename T>
@@ -576,7 +624,7 @@ void launch_real_zxy_to_xyz(int N, const double* in, double* out, hipStream_t s)
   template void launch_proj<T>(const cplx<T>*, long, int, int, cplx<T>*, long, const int*, int,         \
                                hipStream_t);                                                           \
   template void launch_cg_init<T>(const SolveVecs<T>&, const cplx<T>*, long, const int*, int, int, bool,\
-                                  const int*, hipStream_t);                                                        \
+                                  const int*, hipStream_t, const ProjFeed<T>&);                                    \
   template void launch_cg_step<T>(const SolveVecs<T>&, int, T, const int*, int, hipStream_t);          \
   template void launch_sqmr_init<T>(const SolveVecs<T>&, const cplx<T>*, long, const int*, int, int,    \
                                     bool, const int*, hipStream_t);                                                \
@@ -841,7 +889,7 @@ k_proj_dots(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, const 
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, const cplx<T>* X, cplx<T>* Y,
-              long ldy, const int* __restrict__ act, int nsys, int ks, const cplx<T>* __restrict__ part,
+              long ldy, const int* __restrict__ act, int nsys, int ks, const cplx<T>* __restrict__ part, int ptot,
               const T* __restrict__ dpre, const T* __restrict__ dpost) {
   __shared__ cplx<T> C[16][kMaxBands];
   __shared__ cplx<T> red[256];
@@ -859,8 +907,10 @@ k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, cons
     cplx<T> a0{0, 0}, a1{0, 0};
     if (e < E) {
       const int s = e / nv, v = e - s * nv;
-      const cplx<T>* pp = part + (long)(tile + s) * nv + v;
-      const long step = (long)nsys * nv;
+      // partial rows by active slot, or by system (ptot systems per slice)
+      const int prow = ptot ? sys_of(act, tile + s) : tile + s;
+      const cplx<T>* pp = part + (long)prow * nv + v;
+      const long step = (long)(ptot ? ptot : nsys) * nv;
       int k = sub;
       for (; k + tpe < ks; k += 2 * tpe) {
         a0 = a0 + pp[(long)k * step];
@@ -941,8 +991,21 @@ void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, const cpl
     default: k_proj_dots<T, 4><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, X, ldy, act, nsys, kchunk, part, dpre); break;
   }
   k_proj_update<T><<<dim3((npw + 255) / 256, tiles), 256, 0, s>>>(Phi, ldphi, nv, npw, X, Y, ldy, act, nsys, ks,
-                                                                   part, dpre, dpost);
+                                                                   part, 0, dpre, dpost);
 }
+
+template <typename T>
+void launch_proj_fed(const ProjFeed<T>& f, int npw, const cplx<T>* X, cplx<T>* Y, long ldy, const int* act,
+                     int nsys, const T* dpost, hipStream_t s) {
+  if (nsys <= 0 || f.nv <= 0) return;
+  const int tiles = (nsys + 15) / 16;
+  k_proj_update<T><<<dim3((npw + 255) / 256, tiles), 256, 0, s>>>(f.Phi, f.ldphi, f.nv, npw, X, Y, ldy, act, nsys,
+                                                                   f.nsplit, f.part, f.ntot, f.pre, dpost);
+}
+template void launch_proj_fed<double>(const ProjFeed<double>&, int, const z64*, z64*, long, const int*, int,
+                                      const double*, hipStream_t);
+template void launch_proj_fed<float>(const ProjFeed<float>&, int, const z32*, z32*, long, const int*, int,
+                                     const float*, hipStream_t);
 
 template <typename T>
 void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy, const int* act,
@@ -1201,7 +1264,9 @@ k_cg_split2(SolveVecs<T> v, int npw, const int* __restrict__ act, int nsplit, co
 // norm in theta and updates the iteration count and the convergence flag
 template <typename T>
 __global__ void __launch_bounds__(NT)
-k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int nsplit, const T* __restrict__ part2) {
+k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int nsplit, const T* __restrict__ part2,
+            ProjFeed<T> f) {
+  __shared__ T sm[16 * (NT / 64)];
   const int sys = sys_of(act, blockIdx.y);
   if (v.flag[sys]) return;
   T rrn = T(0);
@@ -1211,7 +1276,41 @@ k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int ns
   slice_of<T>(npw, nsplit, i0, i1);
   cplx<T>* p = v.p + (long)sys * v.ld;
   const cplx<T>* r = v.r + (long)sys * v.ld;
-  for (int i = i0 + threadIdx.x; i < i1; i += NT) p[i] = r[i] + beta * p[i];
+  T fa[16];
+  feed_zero(fa);
+  if (f.part) {
+    // the band values and the scaling are loaded before the store to p (the
+    // compiler may not move loads across it), so each step waits once
+    for (int i = i0 + threadIdx.x; i < i1; i += NT) {
+      const cplx<T> ri = r[i], pi = p[i];
+      cplx<T> ph[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ph[u] = u < f.nv ? f.Phi[(long)u * f.ldphi + i] : cplx<T>{0, 0};
+      const T sc = f.pre ? f.pre[i] : T(1);
+      const cplx<T> pn = ri + beta * pi;
+      p[i] = pn;
+      const cplx<T> y = sc * pn;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        fa[2 * u] += ph[u].x * y.x + ph[u].y * y.y;
+        fa[2 * u + 1] += ph[u].x * y.y - ph[u].y * y.x;
+      }
+    }
+  } else {
+    for (int i = i0 + threadIdx.x; i < i1; i += NT) p[i] = r[i] + beta * p[i];
+  }
+  if (f.part) {
+    // the slice's projector sums of the new direction (each thread re-reads
+    // only what it wrote)
+    block_sum<T, 16>(fa, sm);
+    feed_store(f, 0, blockIdx.x, sys, fa);
+    for (int v0 = 8; v0 < f.nv; v0 += 8) {
+      feed_zero(fa);
+      for (int i = i0 + threadIdx.x; i < i1; i += NT) feed_acc(f, v0, i, p[i], fa);
+      block_sum<T, 16>(fa, sm);
+      feed_store(f, v0, blockIdx.x, sys, fa);
+    }
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     v.theta[sys] = rrn;
     v.iters[sys] += 1;
@@ -1223,18 +1322,18 @@ k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int ns
 
 template <typename T>
 void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
-                          hipStream_t s) {
+                          hipStream_t s, const ProjFeed<T>& f) {
   if (nsys <= 0) return;
   const dim3 grid(nsplit, nsys);
   k_cg_split1<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part);
   k_cg_split2<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part, part + (long)nsys * nsplit);
-  k_cg_split3<T><<<grid, NT, 0, s>>>(v, npw, tol2, act, nsplit, part + (long)nsys * nsplit);
+  k_cg_split3<T><<<grid, NT, 0, s>>>(v, npw, tol2, act, nsplit, part + (long)nsys * nsplit, f);
 }
 
 template void launch_cg_step_split<double>(const SolveVecs<double>&, int, double, const int*, int, int, double*,
-                                           hipStream_t);
+                                           hipStream_t, const ProjFeed<double>&);
 template void launch_cg_step_split<float>(const SolveVecs<float>&, int, float, const int*, int, int, float*,
-                                          hipStream_t);
+                                          hipStream_t, const ProjFeed<float>&);
 }  // namespace lgw
 
 // ====================================================================

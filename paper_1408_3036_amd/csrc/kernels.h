@@ -74,9 +74,24 @@ struct SolveVecs {
   int* flag;
   int* iters;
 };
+// Projector partial sums that the CG kernels of a small batch leave for the
+// next operator application, which then skips the projector's dot products:
+// part[k][sys][v] = sum over slice k of conj(Phi_v) (pre .* p_sys), with the
+// slices of the split CG kernels (the initialisation writes slice 0 with the
+// whole sum and zeroes the others).  part == null: no partial sums.
+template <typename T>
+struct ProjFeed {
+  const cplx<T>* Phi = nullptr;   // [nv][ldphi]
+  long ldphi = 0;
+  int nv = 0;
+  const T* pre = nullptr;         // scaling applied before the projection, or null
+  cplx<T>* part = nullptr;        // [nsplit][ntot][nv]
+  int ntot = 0;                   // systems of the batch (stride of part)
+  int nsplit = 1;
+};
 template <typename T>
 void launch_cg_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw,
-                    int nsys, bool keep_x, const int* act, hipStream_t s);
+                    int nsys, bool keep_x, const int* act, hipStream_t s, const ProjFeed<T>& f = {});
 template <typename T>
 void launch_cg_step(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, hipStream_t s);
 template <typename T>
@@ -139,6 +154,11 @@ void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* 
 template <typename T>
 void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, const cplx<T>* X, cplx<T>* Y, long ldy,
                       const int* act, int nsys, cplx<T>* part, const T* dpre, const T* dpost, hipStream_t s);
+// The same projection from partial sums already in f.part (ProjFeed): only
+// the reduction over the f.nsplit slices and the update run
+template <typename T>
+void launch_proj_fed(const ProjFeed<T>& f, int npw, const cplx<T>* X, cplx<T>* Y, long ldy, const int* act,
+                     int nsys, const T* dpost, hipStream_t s);
 }  // namespace lgw
 
 namespace lgw {
@@ -158,7 +178,7 @@ namespace lgw {
 // needs 2 * nsys * nsplit entries
 template <typename T>
 void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
-                          hipStream_t s);
+                          hipStream_t s, const ProjFeed<T>& f = {});
 }  // namespace lgw
 
 namespace lgw {

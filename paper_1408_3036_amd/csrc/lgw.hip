@@ -328,6 +328,13 @@ template <class T>
 void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
   proj<T>(c, Y, Y, ldy, act, nsys);
 }
+// Y = P (f.pre .* X) from the partial sums the CG kernels left in f.part
+template <class T>
+void proj_fed(lgw_ctx* c, const ProjFeed<T>& f, const cplx<T>* X, cplx<T>* Y, long ldy, const int* act, int nsys) {
+  hipEvent_t t0 = c->begin(nsys);
+  launch_proj_fed<T>(f, c->npw, X, Y, ldy, act, nsys, nullptr, c->stream);
+  c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_PROJ, 2.0 * sizeof(T) * ((2.0 * nsys + c->nv) * c->npw));
+}
 
 // Y = A X for the projected operator of the given kind (X is in range(P_c)).
 // With a preconditioner scaling S (pre != null): Y = S P A P S X, the product
@@ -338,10 +345,12 @@ void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
 template <class T>
 void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, cplx<T>* Tb, long ld,
               const cplx<T>* shift, const T* w2, const int* act, int nsys, const T* pre = nullptr,
-              cplx<T>* ptmp = nullptr) {
+              cplx<T>* ptmp = nullptr, const ProjFeed<T>* fed = nullptr) {
   const bool fold = pre && sizeof(T) == 4;
   if (pre) {
-    proj<T>(c, X, ptmp, ld, act, nsys, pre, nullptr);   // ptmp = P S X
+    // ptmp = P S X (the dot products already summed by slice when fed)
+    if (fed) proj_fed<T>(c, *fed, X, ptmp, ld, act, nsys);
+    else proj<T>(c, X, ptmp, ld, act, nsys, pre, nullptr);
     X = ptmp;
   }
   const T* dout = fold ? pre : nullptr;
@@ -370,6 +379,7 @@ struct Batch {
   T* split_part = nullptr;
   const T* pre = nullptr;      // preconditioner scaling or null
   cplx<T>* ptmp = nullptr;
+  cplx<T>* fpart = nullptr;    // CG with a preconditioner: projector partial sums (ProjFeed)
   std::vector<int> h_iters, h_flags;
   Batch() = default;
   Batch(const Batch&) = delete;
@@ -377,7 +387,7 @@ struct Batch {
   Batch(Batch&& o) noexcept { *this = std::move(o); }
   Batch& operator=(Batch&& o) noexcept {
     kind = o.kind; nsys = o.nsys; ld = o.ld; v = o.v; tmp = o.tmp; Tb = o.Tb; shift = o.shift; w2 = o.w2;
-    act = o.act; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp;
+    act = o.act; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp; fpart = o.fpart;
     h_iters = std::move(o.h_iters); h_flags = std::move(o.h_flags);
     return *this;
   }
@@ -413,6 +423,8 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   b.act = c->buf<int>(t + ".act", nsys);
   b.nsplit = std::max(1, std::min(64, c->npw / 1024));
   b.split_part = c->buf<T>(t + ".split", (size_t)2 * std::min(nsys, lgw_ctx::kTimedMin) * b.nsplit);
+  b.fpart = b.pre && kind != K_SQMR && c->nv > 0 ? c->buf<cplx<T>>(t + ".fpart", (size_t)b.nsplit * nsys * c->nv)
+                                                 : nullptr;
   {
     size_t cap = 0;
     for (int n = 1; n <= nsys; n += (n < 64 ? 1 : 16)) cap = std::max(cap, (size_t)proj_ksplit<T>(c->npw, n) * n);
@@ -441,10 +453,25 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   if (act.empty()) return;
   const int npw = c->npw;
   h2d_async(c, b.act, act.data(), act.size() * sizeof(int));
+  // Small preconditioned CG batches take the projector's dot products of the
+  // next direction from the CG kernels (initialisation and direction update),
+  // so each operator application starts with the projector's update alone.
+  // Decided once per run: the split kernels then serve every chunk.
+  ProjFeed<T> feed;
+  const bool fed = b.fpart && (int)act.size() <= lgw_ctx::kTimedMin;
+  if (fed) {
+    feed.Phi = phi_of<T>(c);
+    feed.ldphi = c->npw;
+    feed.nv = c->nv;
+    feed.pre = b.pre;
+    feed.part = b.fpart;
+    feed.ntot = b.nsys;
+    feed.nsplit = b.nsplit;
+  }
   if (b.kind == K_SQMR)
     launch_sqmr_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream);
   else
-    launch_cg_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream);
+    launch_cg_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream, feed);
   c->check_launch();
   const int check = std::max(1, c->opts.check_every);
   const int maxit = std::max(1, c->opts.max_iter);
@@ -498,7 +525,8 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     const int na = (int)act.size();
     auto iterate = [&](int n_it) {
       for (int k = 0; k < n_it; ++k) {
-        apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na, b.pre, b.ptmp);
+        apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na, b.pre, b.ptmp,
+                    fed ? &feed : nullptr);
         hipEvent_t t0 = c->begin(na);
         if (b.kind == K_SQMR) {
           launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
@@ -506,7 +534,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
           c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
         } else if (na <= lgw_ctx::kTimedMin) {
           // small batch: spread each system over several workgroups
-          launch_cg_step_split<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, c->stream);
+          launch_cg_step_split<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, c->stream, feed);
         } else {
           launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
           // reads p, Ap (twice), x, r (twice), p; writes x, r, p
@@ -528,7 +556,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
           (uintptr_t)b.v.Ap, (uintptr_t)b.v.d, (uintptr_t)b.v.rr, (uintptr_t)b.v.bb, (uintptr_t)b.v.theta,
           (uintptr_t)b.v.rho, (uintptr_t)b.v.flag, (uintptr_t)b.v.iters, (uintptr_t)b.tmp, (uintptr_t)b.Tb,
           (uintptr_t)b.shift, (uintptr_t)b.w2, (uintptr_t)b.act, (uintptr_t)b.split_part, (uintptr_t)b.pre,
-          (uintptr_t)b.ptmp};
+          (uintptr_t)b.ptmp, (uintptr_t)b.fpart, (uintptr_t)fed};
       auto f = c->graphs.find(key);
       if (f != c->graphs.end()) {
         gx = f->second;
