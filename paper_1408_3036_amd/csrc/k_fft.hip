@@ -24,13 +24,18 @@ template <int N>
 __device__ __forceinline__ int pruned(int t, int h) { return t <= h ? t : t + N - 2 * h - 1; }
 
 // ------------------------------------------------------------------ zinv
+// With partial projector sums (f.part != null) X is the direction D, and the
+// projected input f.pre .* D - sum_v Phi_v C_v is formed in the gather and
+// also stored to Xout.
 template <typename T, int N>
 __global__ void __launch_bounds__(256)
 k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, long ldx,
-       cplx<T>* __restrict__ Tb, long ldt, T scale, const int* __restrict__ act) {
+       cplx<T>* __restrict__ Tb, long ldt, T scale, const int* __restrict__ act, ProjFeed<T> f,
+       cplx<T>* __restrict__ Xout) {
   constexpr int LDZ = skew(N) + 1;
   __shared__ cplx<T> buf[kZCols * LDZ];
   __shared__ cplx<T> tws[N];
+  __shared__ cplx<T> Cs[kMaxBands];
   const int sys = sys_of(act, blockIdx.y);
   const int c0 = blockIdx.x * kZCols;
   const int nc = min(kZCols, g.ncols - c0);
@@ -45,7 +50,16 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
   }
   if (threadIdx.x == 0) cs[nc] = c0 + nc < g.ncols ? g.col_start[c0 + nc] : g.npw;
   for (int i = threadIdx.x; i < kZCols * LDZ; i += 256) buf[i] = cplx<T>{0, 0};
+  if (f.part) {
+    // this system's projector coefficients: the sum of its slices
+    for (int v = threadIdx.x; v < f.nv; v += 256) {
+      cplx<T> a{0, 0};
+      for (int k = 0; k < f.nsplit; ++k) a = a + f.part[((long)k * f.ntot + sys) * f.nv + v];
+      Cs[v] = a;
+    }
+  }
   __syncthreads();
+  cplx<T>* Xo = f.part ? Xout + (long)sys * ldx : nullptr;
   // the block's columns are one contiguous run of the sphere vector
   for (int gi = cs[0] + threadIdx.x; gi < cs[nc]; gi += 256) {
     int lo = 0, hi = nc;
@@ -54,7 +68,13 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
       if (cs[mid] <= gi) lo = mid; else hi = mid;
     }
     const int mz = gi - cs[lo] - ch[lo];
-    buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)] = Xs[gi];
+    cplx<T> xv = Xs[gi];
+    if (Xo) {
+      if (f.pre) xv = f.pre[gi] * xv;
+      for (int v = 0; v < f.nv; ++v) xv = xv - Cs[v] * f.Phi[(long)v * f.ldphi + gi];
+      Xo[gi] = xv;
+    }
+    buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)] = xv;
   }
   __syncthreads();
   fft_lds<T, N, +1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + skew(e); });
@@ -292,7 +312,16 @@ void launch_zinv(const Geom& g, const cplx<T>* tw, const cplx<T>* X, long ldx, c
                  T scale, const int* act, int nsys, hipStream_t s) {
   if (nsys <= 0) return;
   dim3 grid((g.ncols + kZCols - 1) / kZCols, nsys);
-  LGW_DISPATCH_N(g.N, (k_zinv<T, NN_><<<grid, 256, 0, s>>>(g, tw, X, ldx, Tb, ldt, scale, act)));
+  LGW_DISPATCH_N(g.N, (k_zinv<T, NN_><<<grid, 256, 0, s>>>(g, tw, X, ldx, Tb, ldt, scale, act, ProjFeed<T>{},
+                                                          nullptr)));
+}
+
+template <typename T>
+void launch_zinv_fed(const Geom& g, const cplx<T>* tw, const ProjFeed<T>& f, const cplx<T>* D, cplx<T>* Xout,
+                     long ldx, cplx<T>* Tb, long ldt, const int* act, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  dim3 grid((g.ncols + kZCols - 1) / kZCols, nsys);
+  LGW_DISPATCH_N(g.N, (k_zinv<T, NN_><<<grid, 256, 0, s>>>(g, tw, D, ldx, Tb, ldt, T(1), act, f, Xout)));
 }
 
 template <typename T>
@@ -353,6 +382,8 @@ void launch_zfull_mul(int N, const cplx<T>* tw, cplx<T>* G, long ldg, const T* m
 #define LGW_INST(T)                                                                                   \
   template void launch_zinv<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, cplx<T>*, long, T,  \
                                const int*, int, hipStream_t);                                         \
+  template void launch_zinv_fed<T>(const Geom&, const cplx<T>*, const ProjFeed<T>&, const cplx<T>*,    \
+                                   cplx<T>*, long, cplx<T>*, long, const int*, int, hipStream_t);     \
   template void launch_plane_hv<T>(const Geom&, const cplx<T>*, cplx<T>*, long, const T*, const int*, \
                                    int, hipStream_t);                                                 \
   template void launch_zfwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, T, const cplx<T>*,  \

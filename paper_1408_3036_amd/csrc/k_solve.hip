@@ -889,7 +889,7 @@ k_proj_dots(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, const 
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, const cplx<T>* X, cplx<T>* Y,
-              long ldy, const int* __restrict__ act, int nsys, int ks, const cplx<T>* __restrict__ part, int ptot,
+              long ldy, const int* __restrict__ act, int nsys, int ks, const cplx<T>* __restrict__ part,
               const T* __restrict__ dpre, const T* __restrict__ dpost) {
   __shared__ cplx<T> C[16][kMaxBands];
   __shared__ cplx<T> red[256];
@@ -907,10 +907,8 @@ k_proj_update(const cplx<T>* __restrict__ Phi, long ldphi, int nv, int npw, cons
     cplx<T> a0{0, 0}, a1{0, 0};
     if (e < E) {
       const int s = e / nv, v = e - s * nv;
-      // partial rows by active slot, or by system (ptot systems per slice)
-      const int prow = ptot ? sys_of(act, tile + s) : tile + s;
-      const cplx<T>* pp = part + (long)prow * nv + v;
-      const long step = (long)(ptot ? ptot : nsys) * nv;
+      const cplx<T>* pp = part + (long)(tile + s) * nv + v;
+      const long step = (long)nsys * nv;
       int k = sub;
       for (; k + tpe < ks; k += 2 * tpe) {
         a0 = a0 + pp[(long)k * step];
@@ -991,21 +989,9 @@ void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, const cpl
     default: k_proj_dots<T, 4><<<grid, 64, 0, s>>>(Phi, ldphi, nv, npw, X, ldy, act, nsys, kchunk, part, dpre); break;
   }
   k_proj_update<T><<<dim3((npw + 255) / 256, tiles), 256, 0, s>>>(Phi, ldphi, nv, npw, X, Y, ldy, act, nsys, ks,
-                                                                   part, 0, dpre, dpost);
+                                                                   part, dpre, dpost);
 }
 
-template <typename T>
-void launch_proj_fed(const ProjFeed<T>& f, int npw, const cplx<T>* X, cplx<T>* Y, long ldy, const int* act,
-                     int nsys, const T* dpost, hipStream_t s) {
-  if (nsys <= 0 || f.nv <= 0) return;
-  const int tiles = (nsys + 15) / 16;
-  k_proj_update<T><<<dim3((npw + 255) / 256, tiles), 256, 0, s>>>(f.Phi, f.ldphi, f.nv, npw, X, Y, ldy, act, nsys,
-                                                                   f.nsplit, f.part, f.ntot, f.pre, dpost);
-}
-template void launch_proj_fed<double>(const ProjFeed<double>&, int, const z64*, z64*, long, const int*, int,
-                                      const double*, hipStream_t);
-template void launch_proj_fed<float>(const ProjFeed<float>&, int, const z32*, z32*, long, const int*, int,
-                                     const float*, hipStream_t);
 
 template <typename T>
 void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, long ldy, const int* act,

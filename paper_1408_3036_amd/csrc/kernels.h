@@ -9,6 +9,23 @@ namespace lgw {
 
 constexpr int kMaxBands = 32;   // bands handled by the projector kernels
 
+// Projector partial sums that the CG kernels of a small batch leave for the
+// next operator application, which then skips the projector's dot products
+// and forms the projected input in its first transform (launch_zinv_fed):
+// part[k][sys][v] = sum over slice k of conj(Phi_v) (pre .* p_sys), with the
+// slices of the split CG kernels (the initialisation writes slice 0 with the
+// whole sum and zeroes the others).  part == null: no partial sums.
+template <typename T>
+struct ProjFeed {
+  const cplx<T>* Phi = nullptr;   // [nv][ldphi]
+  long ldphi = 0;
+  int nv = 0;
+  const T* pre = nullptr;         // scaling applied before the projection, or null
+  cplx<T>* part = nullptr;        // [nsplit][ntot][nv]
+  int ntot = 0;                   // systems of the batch (stride of part)
+  int nsplit = 1;
+};
+
 bool grid_supported(int N);
 
 // ---- transforms (T = double or float) -----------------------------------
@@ -16,6 +33,13 @@ bool grid_supported(int N);
 template <typename T>
 void launch_zinv(const Geom& g, const cplx<T>* tw, const cplx<T>* X, long ldx,
                  cplx<T>* Tb, long ldt, T scale, const int* act, int nsys, hipStream_t s);
+// the same pass (scale 1) on the projected input X = P (f.pre .* D), formed on
+// the fly from the direction D and the partial sums in f.part (ProjFeed):
+// X = f.pre .* D - sum_v Phi_v C_v with C_v the sum of the slices; X is also
+// written to Xout (the same layout as D, ld ldx)
+template <typename T>
+void launch_zinv_fed(const Geom& g, const cplx<T>* tw, const ProjFeed<T>& f, const cplx<T>* D, cplx<T>* Xout,
+                     long ldx, cplx<T>* Tb, long ldt, const int* act, int nsys, hipStream_t s);
 // middle pass of H: Tb <- FFT_xy(Vt[z] * IFFT_xy(Tb)) on every z plane (unscaled)
 template <typename T>
 void launch_plane_hv(const Geom& g, const cplx<T>* tw, cplx<T>* Tb, long ldt, const T* Vt,
@@ -73,21 +97,6 @@ struct SolveVecs {
   cplx<T>* rho;   // SQMR rho
   int* flag;
   int* iters;
-};
-// Projector partial sums that the CG kernels of a small batch leave for the
-// next operator application, which then skips the projector's dot products:
-// part[k][sys][v] = sum over slice k of conj(Phi_v) (pre .* p_sys), with the
-// slices of the split CG kernels (the initialisation writes slice 0 with the
-// whole sum and zeroes the others).  part == null: no partial sums.
-template <typename T>
-struct ProjFeed {
-  const cplx<T>* Phi = nullptr;   // [nv][ldphi]
-  long ldphi = 0;
-  int nv = 0;
-  const T* pre = nullptr;         // scaling applied before the projection, or null
-  cplx<T>* part = nullptr;        // [nsplit][ntot][nv]
-  int ntot = 0;                   // systems of the batch (stride of part)
-  int nsplit = 1;
 };
 template <typename T>
 void launch_cg_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw,
@@ -154,11 +163,6 @@ void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* 
 template <typename T>
 void launch_proj_mfma(const cplx<T>* Phi, long ldphi, int nv, int npw, const cplx<T>* X, cplx<T>* Y, long ldy,
                       const int* act, int nsys, cplx<T>* part, const T* dpre, const T* dpost, hipStream_t s);
-// The same projection from partial sums already in f.part (ProjFeed): only
-// the reduction over the f.nsplit slices and the update run
-template <typename T>
-void launch_proj_fed(const ProjFeed<T>& f, int npw, const cplx<T>* X, cplx<T>* Y, long ldy, const int* act,
-                     int nsys, const T* dpost, hipStream_t s);
 }  // namespace lgw
 
 namespace lgw {

@@ -290,16 +290,21 @@ void upload(lgw_ctx* c, DevBuf& b, const std::vector<T>& h) {
   h2d(c, b.p, h.data(), h.size() * sizeof(T));
 }
 
-// y = (H - shift) x [+ ecoef E] for nsys systems (device per-system arrays)
+// y = (H - shift) x [+ ecoef E] for nsys systems (device per-system arrays).
+// With fed: x = P (fed->pre .* D) is formed by the first transform from the
+// direction D and the CG kernels' partial sums, and stored to X.
 template <class T>
 void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const cplx<T>* shift,
             const cplx<T>* E, long lde, const T* ecoef, cplx<T>* Tb, const int* act, int nsys,
-            const T* dout = nullptr) {
+            const T* dout = nullptr, const ProjFeed<T>* fed = nullptr, const cplx<T>* D = nullptr) {
   const long ldt = (long)c->N * c->ncols;
   const double e = 2.0 * sizeof(T);   // bytes of one complex value
   const double cols = (double)nsys * c->N * c->ncols, sph = (double)nsys * c->npw;
   hipEvent_t t0 = c->begin(nsys);
-  launch_zinv<T>(c->geom, tw_of<T>(c), X, ldx, Tb, ldt, T(1), act, nsys, c->stream);
+  if (fed)
+    launch_zinv_fed<T>(c->geom, tw_of<T>(c), *fed, D, const_cast<cplx<T>*>(X), ldx, Tb, ldt, act, nsys, c->stream);
+  else
+    launch_zinv<T>(c->geom, tw_of<T>(c), X, ldx, Tb, ldt, T(1), act, nsys, c->stream);
   const int pk = sizeof(T) == 4 ? LGW_K_FP32 : 0;
   c->end(t0, pk + LGW_K_ZINV, e * (sph + cols));
   hipEvent_t t1 = c->begin(nsys);
@@ -328,13 +333,7 @@ template <class T>
 void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
   proj<T>(c, Y, Y, ldy, act, nsys);
 }
-// Y = P (f.pre .* X) from the partial sums the CG kernels left in f.part
-template <class T>
-void proj_fed(lgw_ctx* c, const ProjFeed<T>& f, const cplx<T>* X, cplx<T>* Y, long ldy, const int* act, int nsys) {
-  hipEvent_t t0 = c->begin(nsys);
-  launch_proj_fed<T>(f, c->npw, X, Y, ldy, act, nsys, nullptr, c->stream);
-  c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_PROJ, 2.0 * sizeof(T) * ((2.0 * nsys + c->nv) * c->npw));
-}
+
 
 // Y = A X for the projected operator of the given kind (X is in range(P_c)).
 // With a preconditioner scaling S (pre != null): Y = S P A P S X, the product
@@ -347,19 +346,21 @@ void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, 
               const cplx<T>* shift, const T* w2, const int* act, int nsys, const T* pre = nullptr,
               cplx<T>* ptmp = nullptr, const ProjFeed<T>* fed = nullptr) {
   const bool fold = pre && sizeof(T) == 4;
+  const cplx<T>* D = nullptr;
   if (pre) {
-    // ptmp = P S X (the dot products already summed by slice when fed)
-    if (fed) proj_fed<T>(c, *fed, X, ptmp, ld, act, nsys);
+    // ptmp = P S X; fed: formed by the first transform from the CG kernels' sums
+    if (fed) D = X;
     else proj<T>(c, X, ptmp, ld, act, nsys, pre, nullptr);
     X = ptmp;
   }
+  if (!D) fed = nullptr;
   const T* dout = fold ? pre : nullptr;
   if (kind == K_CGSQ) {
-    happly<T>(c, X, ld, tmp, ld, shift, nullptr, 0, nullptr, Tb, act, nsys);
+    happly<T>(c, X, ld, tmp, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, nullptr, fed, D);
     proj<T>(c, tmp, ld, act, nsys);
     happly<T>(c, tmp, ld, Y, ld, shift, X, ld, w2, Tb, act, nsys, dout);
   } else {
-    happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, dout);
+    happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, dout, fed, D);
   }
   if (!fold) proj<T>(c, Y, Y, ld, act, nsys, nullptr, pre);   // Y = S P Y (S = 1 without preconditioner)
 }
