@@ -85,12 +85,23 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
 }
 
 // ------------------------------------------------------------------ zfwd
+// sum over the 256 threads of a column workgroup (the total in every thread)
+template <typename T>
+__device__ __forceinline__ T zblock_sum(T v, T* sm) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sm[0] + sm[1]) + (sm[2] + sm[3]);
+}
+
 template <typename T, int N>
 __global__ void __launch_bounds__(256)
 k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, long ldt, T scale,
        const cplx<T>* __restrict__ X, long ldx, const cplx<T>* __restrict__ shift,
        const cplx<T>* __restrict__ E, long lde, const T* __restrict__ ecoef,
-       cplx<T>* __restrict__ Y, long ldy, const int* __restrict__ act, const T* __restrict__ dout) {
+       cplx<T>* __restrict__ Y, long ldy, const int* __restrict__ act, const T* __restrict__ dout,
+       CgDot<T> cd) {
   constexpr int LDZ = skew(N) + 1;
   __shared__ cplx<T> buf[kZCols * LDZ];
   __shared__ cplx<T> tws[N];
@@ -117,6 +128,8 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
   cplx<T>* Ys = Y + (long)sys * ldy;
   const cplx<T> sh = shift ? shift[sys] : cplx<T>{0, 0};
   const T ec = ecoef ? ecoef[sys] : T(0);
+  const cplx<T>* Ps = cd.part ? cd.p + (long)sys * cd.ldp : nullptr;
+  T pap = T(0);
   for (int i = cs[0] + threadIdx.x; i < cs[nc]; i += 256) {
     int lo = 0, hi = nc;
     while (hi - lo > 1) {
@@ -124,6 +137,7 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
       if (cs[mid] <= i) lo = mid; else hi = mid;
     }
     const int mz = i - cs[lo] - ch[lo];
+    const cplx<T> pv = Ps ? Ps[i] : cplx<T>{0, 0};
     cplx<T> v = scale * buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)];
     if (Xs) {
       const cplx<T> xv = Xs[i];
@@ -133,6 +147,21 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
     if (Es) v = v + ec * Es[i];
     if (dout) v = dout[i] * v;
     Ys[i] = v;
+    pap += pv.x * v.x + pv.y * v.y;
+  }
+  if (cd.part) {
+    __shared__ T smd[4];
+    const T tot = zblock_sum(pap, smd);
+    if (threadIdx.x == 0) {
+      cd.part[(long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+      if (blockIdx.x == 0) {
+        const T th = cd.theta[sys];
+        if (th >= T(0)) {
+          cd.rr[sys] = th;
+          cd.theta[sys] = T(-1);
+        }
+      }
+    }
   }
 }
 
@@ -336,12 +365,14 @@ template <typename T>
 void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, T scale,
                  const cplx<T>* X, long ldx, const cplx<T>* shift, const cplx<T>* E, long lde,
                  const T* ecoef, cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s,
-                 const T* dout) {
+                 const T* dout, const CgDot<T>& cd) {
   if (nsys <= 0) return;
-  dim3 grid((g.ncols + kZCols - 1) / kZCols, nsys);
+  dim3 grid(zcol_blocks(g), nsys);
   LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E, lde,
-                                                        ecoef, Y, ldy, act, dout)));
+                                                        ecoef, Y, ldy, act, dout, cd)));
 }
+
+int zcol_blocks(const Geom& g) { return (g.ncols + kZCols - 1) / kZCols; }
 
 template <typename T>
 void launch_plane_pair_fwd(const Geom& g, const cplx<T>* tw, const cplx<T>* U, int nv, const cplx<T>* X,
@@ -388,7 +419,7 @@ void launch_zfull_mul(int N, const cplx<T>* tw, cplx<T>* G, long ldg, const T* m
                                    int, hipStream_t);                                                 \
   template void launch_zfwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, T, const cplx<T>*,  \
                                long, const cplx<T>*, const cplx<T>*, long, const T*, cplx<T>*, long,  \
-                               const int*, int, hipStream_t, const T*);                               \
+                               const int*, int, hipStream_t, const T*, const CgDot<T>&);              \
   template void launch_plane_pair_fwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, int,            \
                                          const cplx<T>*, long, int, cplx<T>*, long, hipStream_t);     \
   template void launch_plane_acc<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, const cplx<T>*, \

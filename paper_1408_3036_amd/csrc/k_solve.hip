@@ -1218,12 +1218,12 @@ k_cg_split1(SolveVecs<T> v, int npw, const int* __restrict__ act, int nsplit, T*
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_cg_split2(SolveVecs<T> v, int npw, const int* __restrict__ act, int nsplit, const T* __restrict__ part,
-            T* __restrict__ part2) {
+            int npart, T* __restrict__ part2) {
   __shared__ T sm[NT / 64];
   const int sys = sys_of(act, blockIdx.y);
   if (v.flag[sys]) return;
   T pAp = T(0);
-  for (int k = 0; k < nsplit; ++k) pAp += part[(long)blockIdx.y * nsplit + k];
+  for (int k = 0; k < npart; ++k) pAp += part[(long)blockIdx.y * npart + k];
   if (!(pAp > T(0))) {
     if (blockIdx.x == 0 && threadIdx.x == 0) v.flag[sys] = FLAG_BREAK;
     return;
@@ -1308,18 +1308,22 @@ k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int ns
 
 template <typename T>
 void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
-                          hipStream_t s, const ProjFeed<T>& f) {
+                          hipStream_t s, const ProjFeed<T>& f, const T* dots, int ndots) {
   if (nsys <= 0) return;
   const dim3 grid(nsplit, nsys);
-  k_cg_split1<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part);
-  k_cg_split2<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part, part + (long)nsys * nsplit);
+  if (dots) {
+    k_cg_split2<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, dots, ndots, part + (long)nsys * nsplit);
+  } else {
+    k_cg_split1<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part);
+    k_cg_split2<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part, nsplit, part + (long)nsys * nsplit);
+  }
   k_cg_split3<T><<<grid, NT, 0, s>>>(v, npw, tol2, act, nsplit, part + (long)nsys * nsplit, f);
 }
 
 template void launch_cg_step_split<double>(const SolveVecs<double>&, int, double, const int*, int, int, double*,
-                                           hipStream_t, const ProjFeed<double>&);
+                                           hipStream_t, const ProjFeed<double>&, const double*, int);
 template void launch_cg_step_split<float>(const SolveVecs<float>&, int, float, const int*, int, int, float*,
-                                          hipStream_t, const ProjFeed<float>&);
+                                          hipStream_t, const ProjFeed<float>&, const float*, int);
 }  // namespace lgw
 
 // ====================================================================

@@ -28,6 +28,20 @@ struct ProjFeed {
 
 bool grid_supported(int N);
 
+// CG step work done by the last transform of an operator application whose
+// store is the final A p (single precision, scaling folded into the store):
+// per column workgroup k of active slot j, part[j * nblk + k] = the block's
+// Re p^H (A p); workgroup 0 also commits the norm parked in theta to rr
+// (theta >= 0), as the split CG's first phase would.  part == null: off.
+template <typename T>
+struct CgDot {
+  const cplx<T>* p = nullptr;   // directions, ld ldp
+  long ldp = 0;
+  T* part = nullptr;            // [nslots][nblk], nblk = zcol_blocks(g)
+  T* rr = nullptr;
+  T* theta = nullptr;
+};
+
 // ---- transforms (T = double or float) -----------------------------------
 // sphere -> columns: Tb[z][c] = scale * IFFT_z(X column c)
 template <typename T>
@@ -50,7 +64,10 @@ void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, 
                  const cplx<T>* X, long ldx, const cplx<T>* shift,
                  const cplx<T>* E, long lde, const T* ecoef,
                  cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s,
-                 const T* dout = nullptr);   // optional per-plane-wave scaling of Y
+                 const T* dout = nullptr,     // optional per-plane-wave scaling of Y
+                 const CgDot<T>& cd = {});     // optional CG dot products (CgDot)
+// column workgroups of the column passes (one run of the sphere vector each)
+int zcol_blocks(const Geom& g);
 // Tb[j*nv+v][z][c] = FFT_xy(U[v][z] * X[j][z]) at the column positions (unscaled)
 template <typename T>
 void launch_plane_pair_fwd(const Geom& g, const cplx<T>* tw, const cplx<T>* U, int nv,
@@ -180,9 +197,11 @@ void launch_conj(const z64* in, z64* out, long n, hipStream_t s);
 namespace lgw {
 // CG update spread over nsplit workgroups per system (small batches); part
 // needs 2 * nsys * nsplit entries
+// With dots != null the first phase is skipped: p^H A p is the sum of the
+// ndots partials per active slot in dots (CgDot, left by the transform).
 template <typename T>
 void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
-                          hipStream_t s, const ProjFeed<T>& f = {});
+                          hipStream_t s, const ProjFeed<T>& f = {}, const T* dots = nullptr, int ndots = 0);
 }  // namespace lgw
 
 namespace lgw {

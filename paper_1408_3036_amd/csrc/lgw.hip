@@ -296,7 +296,8 @@ void upload(lgw_ctx* c, DevBuf& b, const std::vector<T>& h) {
 template <class T>
 void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const cplx<T>* shift,
             const cplx<T>* E, long lde, const T* ecoef, cplx<T>* Tb, const int* act, int nsys,
-            const T* dout = nullptr, const ProjFeed<T>* fed = nullptr, const cplx<T>* D = nullptr) {
+            const T* dout = nullptr, const ProjFeed<T>* fed = nullptr, const cplx<T>* D = nullptr,
+            const CgDot<T>* cd = nullptr) {
   const long ldt = (long)c->N * c->ncols;
   const double e = 2.0 * sizeof(T);   // bytes of one complex value
   const double cols = (double)nsys * c->N * c->ncols, sph = (double)nsys * c->npw;
@@ -312,7 +313,7 @@ void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const 
   c->end(t1, pk + LGW_K_PLANE_HV, e * 2.0 * cols + sizeof(T) * (double)c->n3);
   hipEvent_t t2 = c->begin(nsys);
   launch_zfwd<T>(c->geom, tw_of<T>(c), Tb, ldt, T(1.0 / (double)c->n3), X, ldx, shift, E, lde, ecoef, Y, ldy,
-                 act, nsys, c->stream, dout);
+                 act, nsys, c->stream, dout, cd ? *cd : CgDot<T>{});
   c->end(t2, pk + LGW_K_ZFWD, e * (cols + (E ? 3.0 : 2.0) * sph));
   c->tot_h += nsys;
 }
@@ -344,7 +345,7 @@ void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
 template <class T>
 void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, cplx<T>* Tb, long ld,
               const cplx<T>* shift, const T* w2, const int* act, int nsys, const T* pre = nullptr,
-              cplx<T>* ptmp = nullptr, const ProjFeed<T>* fed = nullptr) {
+              cplx<T>* ptmp = nullptr, const ProjFeed<T>* fed = nullptr, const CgDot<T>* cd = nullptr) {
   const bool fold = pre && sizeof(T) == 4;
   const cplx<T>* D = nullptr;
   if (pre) {
@@ -354,13 +355,14 @@ void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, 
     X = ptmp;
   }
   if (!D) fed = nullptr;
+  if (!fold) cd = nullptr;   // the last transform stores the final A X only when S is folded into it
   const T* dout = fold ? pre : nullptr;
   if (kind == K_CGSQ) {
     happly<T>(c, X, ld, tmp, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, nullptr, fed, D);
     proj<T>(c, tmp, ld, act, nsys);
-    happly<T>(c, tmp, ld, Y, ld, shift, X, ld, w2, Tb, act, nsys, dout);
+    happly<T>(c, tmp, ld, Y, ld, shift, X, ld, w2, Tb, act, nsys, dout, nullptr, nullptr, cd);
   } else {
-    happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, dout, fed, D);
+    happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, dout, fed, D, cd);
   }
   if (!fold) proj<T>(c, Y, Y, ld, act, nsys, nullptr, pre);   // Y = S P Y (S = 1 without preconditioner)
 }
@@ -381,6 +383,7 @@ struct Batch {
   const T* pre = nullptr;      // preconditioner scaling or null
   cplx<T>* ptmp = nullptr;
   cplx<T>* fpart = nullptr;    // CG with a preconditioner: projector partial sums (ProjFeed)
+  T* dot_part = nullptr;       // single-precision CG with a preconditioner: p^H A p partials (CgDot)
   std::vector<int> h_iters, h_flags;
   Batch() = default;
   Batch(const Batch&) = delete;
@@ -388,7 +391,7 @@ struct Batch {
   Batch(Batch&& o) noexcept { *this = std::move(o); }
   Batch& operator=(Batch&& o) noexcept {
     kind = o.kind; nsys = o.nsys; ld = o.ld; v = o.v; tmp = o.tmp; Tb = o.Tb; shift = o.shift; w2 = o.w2;
-    act = o.act; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp; fpart = o.fpart;
+    act = o.act; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp; fpart = o.fpart; dot_part = o.dot_part;
     h_iters = std::move(o.h_iters); h_flags = std::move(o.h_flags);
     return *this;
   }
@@ -426,6 +429,9 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   b.split_part = c->buf<T>(t + ".split", (size_t)2 * std::min(nsys, lgw_ctx::kTimedMin) * b.nsplit);
   b.fpart = b.pre && kind != K_SQMR && c->nv > 0 ? c->buf<cplx<T>>(t + ".fpart", (size_t)b.nsplit * nsys * c->nv)
                                                  : nullptr;
+  b.dot_part = b.fpart && sizeof(T) == 4
+                   ? c->buf<T>(t + ".dots", (size_t)std::min(nsys, lgw_ctx::kTimedMin) * zcol_blocks(c->geom))
+                   : nullptr;
   {
     size_t cap = 0;
     for (int n = 1; n <= nsys; n += (n < 64 ? 1 : 16)) cap = std::max(cap, (size_t)proj_ksplit<T>(c->npw, n) * n);
@@ -469,6 +475,18 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     feed.ntot = b.nsys;
     feed.nsplit = b.nsplit;
   }
+  // ... and, in single precision (the scaling folded into the transform's
+  // store), p^H A p from that transform: the split CG's first phase is skipped
+  CgDot<T> cdot;
+  const bool tdots = fed && b.dot_part;
+  if (tdots) {
+    cdot.p = b.v.p;
+    cdot.ldp = b.ld;
+    cdot.part = b.dot_part;
+    cdot.rr = b.v.rr;
+    cdot.theta = b.v.theta;
+  }
+  const int nblk = zcol_blocks(c->geom);
   if (b.kind == K_SQMR)
     launch_sqmr_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream);
   else
@@ -527,7 +545,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     auto iterate = [&](int n_it) {
       for (int k = 0; k < n_it; ++k) {
         apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na, b.pre, b.ptmp,
-                    fed ? &feed : nullptr);
+                    fed ? &feed : nullptr, tdots ? &cdot : nullptr);
         hipEvent_t t0 = c->begin(na);
         if (b.kind == K_SQMR) {
           launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
@@ -535,7 +553,8 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
           c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
         } else if (na <= lgw_ctx::kTimedMin) {
           // small batch: spread each system over several workgroups
-          launch_cg_step_split<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, c->stream, feed);
+          launch_cg_step_split<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, c->stream, feed,
+                                  tdots ? b.dot_part : nullptr, nblk);
         } else {
           launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
           // reads p, Ap (twice), x, r (twice), p; writes x, r, p
@@ -557,7 +576,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
           (uintptr_t)b.v.Ap, (uintptr_t)b.v.d, (uintptr_t)b.v.rr, (uintptr_t)b.v.bb, (uintptr_t)b.v.theta,
           (uintptr_t)b.v.rho, (uintptr_t)b.v.flag, (uintptr_t)b.v.iters, (uintptr_t)b.tmp, (uintptr_t)b.Tb,
           (uintptr_t)b.shift, (uintptr_t)b.w2, (uintptr_t)b.act, (uintptr_t)b.split_part, (uintptr_t)b.pre,
-          (uintptr_t)b.ptmp, (uintptr_t)b.fpart, (uintptr_t)fed};
+          (uintptr_t)b.ptmp, (uintptr_t)b.fpart, (uintptr_t)fed, (uintptr_t)b.dot_part, (uintptr_t)tdots};
       auto f = c->graphs.find(key);
       if (f != c->graphs.end()) {
         gx = f->second;
