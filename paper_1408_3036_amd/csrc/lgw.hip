@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <string>
@@ -142,6 +143,24 @@ struct lgw_ctx {
     }
     return pinb;
   }
+  // pinned host buffer for device->host readbacks (readback): a copy into
+  // pageable memory waits for its own completion, so several of them in a row
+  // cost a host round trip each; into pinned memory they queue behind one wait
+  char* rdb = nullptr;
+  size_t rdb_n = 0;
+  char* readback_buf(size_t bytes) {
+    if (bytes > rdb_n) {
+      if (rdb) {
+        HIPCHK(hipStreamSynchronize(stream));
+        (void)hipHostFree(rdb);
+        rdb = nullptr;
+        rdb_n = 0;
+      }
+      HIPCHK(hipHostMalloc((void**)&rdb, bytes, hipHostMallocDefault));
+      rdb_n = bytes;
+    }
+    return rdb;
+  }
   // instantiated graphs of small-batch Krylov chunks, kept across solves and
   // keyed by every pointer and size their capture bakes in; all are dropped
   // before any workspace buffer is reallocated
@@ -224,6 +243,7 @@ struct lgw_ctx {
     drop_graphs();
     if (pin) (void)hipHostFree(pin);
     if (pinb) (void)hipHostFree(pinb);
+    if (rdb) (void)hipHostFree(rdb);
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     for (const Timed& t : pending) {
       (void)hipEventDestroy(t.a);
@@ -282,6 +302,30 @@ void h2d_async(lgw_ctx* c, void* dst, const void* src, size_t bytes) {
   std::memcpy(c->pin + c->pin_off, src, bytes);
   HIPCHK(hipMemcpyAsync(dst, c->pin + c->pin_off, bytes, hipMemcpyHostToDevice, c->stream));
   c->pin_off += n;
+}
+
+// Device arrays to host memory after the work queued on the context stream:
+// the copies go through the pinned readback buffer and share one wait.
+struct Rd {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+void readback(lgw_ctx* c, std::initializer_list<Rd> parts) {
+  size_t tot = 0;
+  for (const Rd& r : parts) tot += (r.bytes + 255) & ~size_t(255);
+  char* h = c->readback_buf(std::max<size_t>(tot, 256));
+  size_t off = 0;
+  for (const Rd& r : parts) {
+    if (r.bytes) HIPCHK(hipMemcpyAsync(h + off, r.src, r.bytes, hipMemcpyDeviceToHost, c->stream));
+    off += (r.bytes + 255) & ~size_t(255);
+  }
+  c->sync();
+  off = 0;
+  for (const Rd& r : parts) {
+    if (r.bytes) std::memcpy(r.dst, h + off, r.bytes);
+    off += (r.bytes + 255) & ~size_t(255);
+  }
 }
 
 template <class T>
@@ -510,10 +554,9 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     // kernels skip flagged systems, so the first chunk runs without a poll
     // (initialisation flags only zero right-hand sides).
     if (it > 0) {
-      HIPCHK(hipMemcpyAsync(flags.data(), b.v.flag, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipMemcpyAsync(iters.data(), b.v.iters, b.nsys * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      if (stall > 0) HIPCHK(hipMemcpyAsync(est.data(), b.v.rr, b.nsys * sizeof(T), hipMemcpyDeviceToHost, c->stream));
-      c->sync();
+      readback(c, {{flags.data(), b.v.flag, b.nsys * sizeof(int)},
+                   {iters.data(), b.v.iters, b.nsys * sizeof(int)},
+                   {est.data(), b.v.rr, stall > 0 ? b.nsys * sizeof(T) : 0}});
       std::vector<int> next, stalled;
       for (int s : act) {
         if (flags[s]) continue;
@@ -666,9 +709,8 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
     proj<double>(c, X, npw, d_act, (int)lst.size());
     apply_op<double>(c, kind, X, AX, tmp, Tb, npw, d_shift, d_w2, d_act, (int)lst.size());
     launch_resid<double>(B, npw, d_bidx, AX, npw, R, npw, res, npw, d_act, (int)lst.size(), c->stream);
-    HIPCHK(hipMemcpyAsync(h_res.data(), res, nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    if (!have_bb) HIPCHK(hipMemcpyAsync(h_bb.data(), bb, nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
+    readback(c, {{h_res.data(), res, nsys * sizeof(double)},
+                 {h_bb.data(), bb, have_bb ? 0 : nsys * sizeof(double)}});
     have_bb = true;
     for (int s : lst) out.rel[s] = h_bb[s] > 0 ? std::sqrt(h_res[s] / h_bb[s]) : 0.0;
   };
@@ -927,9 +969,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
         launch_ms_step(Q, AQ, ldq, npw, j, d_act, na, alpha, beta, kcap, mscratch, c->stream);
       }
       c->check_launch();
-      HIPCHK(hipMemcpyAsync(ha.data(), alpha, ha.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(hipMemcpyAsync(hb.data(), beta, hb.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      c->sync();
+      readback(c, {{ha.data(), alpha, ha.size() * sizeof(double)}, {hb.data(), beta, hb.size() * sizeof(double)}});
       std::vector<int> next;
       for (int s : act) {
         const double* al = ha.data() + (size_t)s * kcap;
@@ -1598,9 +1638,7 @@ lgw_status lanczos_core(lgw_ctx* c, int k, z64* Qd, z64* W0, double* d_alpha, do
     }
     launch_norm(wbuf, n3, d_beta + j, part, c->stream);
     double hb[2];
-    HIPCHK(hipMemcpyAsync(&hb[0], d_alpha + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(&hb[1], d_beta + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
+    readback(c, {{&hb[0], d_alpha + j, sizeof(double)}, {&hb[1], d_beta + j, sizeof(double)}});
     amax = std::max(amax, std::abs(hb[0]));
     done = j + 1;
     if (hb[1] < 1e-14 * amax) break;
@@ -1758,9 +1796,7 @@ lgw_status lanczos_reverse(lgw_ctx* c, int m, const z64* Qd, const z64* W0, cons
                            const double* d_beta, z64* Qb, double* gV, SolveTally& tally) {
   const long n3 = c->n3;
   std::vector<double> al(m), be(m);
-  HIPCHK(hipMemcpyAsync(al.data(), d_alpha, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(be.data(), d_beta, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  c->sync();
+  readback(c, {{al.data(), d_alpha, m * sizeof(double)}, {be.data(), d_beta, m * sizeof(double)}});
   std::vector<double> bb(m, 0.0);                     // dL/d beta_j
   z64* w1 = c->buf<z64>("lr.w1", n3);
   z64* w2 = c->buf<z64>("lr.w2", n3);
@@ -2012,9 +2048,7 @@ void recycle_E(lgw_ctx* c, int m, const z64* Bk, const z64* Fk, int n_w, const d
                         c->stream);   // [l][a] = <g_a, b_l>
   }
   std::vector<z64> hh((size_t)nv * n2 * n2), hb((size_t)nv * n2 * m);
-  HIPCHK(hipMemcpyAsync(hh.data(), Hh, hh.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(hb.data(), Bg, hb.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
-  c->sync();
+  readback(c, {{hh.data(), Hh, hh.size() * sizeof(z64)}, {hb.data(), Bg, hb.size() * sizeof(z64)}});
   // per band: h = W diag(e) W^H, B' = W^H (gamma^H b), and its part of E
   std::vector<std::vector<z64>> Ev(nv);
   const double pref = 4.0 / c->dV;
@@ -2304,10 +2338,7 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
       cp->check_launch();
       std::vector<z64> h_ov(n_v * n_v), h_gn(n_v);
       std::vector<double> h_rn(n_v);
-      HIPCHK(hipMemcpyAsync(h_ov.data(), ov, h_ov.size() * sizeof(z64), hipMemcpyDeviceToHost, cp->stream));
-      HIPCHK(hipMemcpyAsync(h_gn.data(), gn, n_v * sizeof(z64), hipMemcpyDeviceToHost, cp->stream));
-      HIPCHK(hipMemcpyAsync(h_rn.data(), rn, n_v * sizeof(double), hipMemcpyDeviceToHost, cp->stream));
-      cp->sync();
+      readback(cp, {{h_ov.data(), ov, h_ov.size() * sizeof(z64)}, {h_gn.data(), gn, n_v * sizeof(z64)}, {h_rn.data(), rn, n_v * sizeof(double)}});
       for (int a = 0; a < n_v; ++a) {
         for (int b = 0; b < n_v; ++b) {
           const z64 x = h_ov[(size_t)b * n_v + a];
