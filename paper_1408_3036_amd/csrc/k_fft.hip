@@ -51,12 +51,19 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
   if (threadIdx.x == 0) cs[nc] = c0 + nc < g.ncols ? g.col_start[c0 + nc] : g.npw;
   for (int i = threadIdx.x; i < kZCols * LDZ; i += 256) buf[i] = cplx<T>{0, 0};
   if (f.part) {
-    // this system's projector coefficients: the sum of its slices
-    for (int v = threadIdx.x; v < f.nv; v += 256) {
-      cplx<T> a{0, 0};
-      for (int k = 0; k < f.nsplit; ++k) a = a + f.part[((long)k * f.ntot + sys) * f.nv + v];
-      Cs[v] = a;
+    // this system's projector coefficients, the sum of its slices: eight
+    // lanes per band (kMaxBands * 8 = 256 threads), then a shuffle tree
+    static_assert(kMaxBands * 8 == 256, "eight lanes per band over the workgroup");
+    const int v = threadIdx.x >> 3, l = threadIdx.x & 7;
+    cplx<T> a{0, 0};
+    if (v < f.nv)
+      for (int k = l; k < f.nsplit; k += 8) a = a + f.part[((long)k * f.ntot + sys) * f.nv + v];
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) {
+      a.x += __shfl_xor(a.x, o, 64);
+      a.y += __shfl_xor(a.y, o, 64);
     }
+    if (l == 0 && v < f.nv) Cs[v] = a;
   }
   __syncthreads();
   cplx<T>* Xo = f.part ? Xout + (long)sys * ldx : nullptr;

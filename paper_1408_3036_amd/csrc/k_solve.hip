@@ -90,12 +90,39 @@ __device__ __forceinline__ void feed_acc(const ProjFeed<T>& f, int v0, int i, cp
     }
   }
 }
-// the group's block sums (every thread holds them) to slice k of system sys
+// Workgroup sums of the 16 values of a group, stored to slice k of system
+// sys.  Within a wave the values are halved at each exchange (each lane keeps
+// one half and adds its partner's copy of it: 8 + 4 + 2 + 1 shuffles leave one
+// value per lane, summed over 16 lanes; two more finish the wave); the waves'
+// totals meet in LDS.  Fixed order, so every call sums alike.
 template <typename T>
-__device__ __forceinline__ void feed_store(const ProjFeed<T>& f, int v0, int k, int sys, const T (&acc)[16]) {
-  if (threadIdx.x != 0) return;
-  cplx<T>* P = f.part + ((long)k * f.ntot + sys) * f.nv;
-  for (int u = 0; u < 8 && v0 + u < f.nv; ++u) P[v0 + u] = cplx<T>{acc[2 * u], acc[2 * u + 1]};
+__device__ __forceinline__ void feed_store(const ProjFeed<T>& f, int v0, int k, int sys, T (&acc)[16], T* sm) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int base = 0;
+#pragma unroll
+  for (int o = 32, h = 8; h >= 1; o >>= 1, h >>= 1) {
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int j = 0; j < h; ++j) {
+      const T send = up ? acc[j] : acc[j + h];
+      const T keep = up ? acc[j + h] : acc[j];
+      acc[j] = keep + __shfl_xor(send, o, 64);
+    }
+    base += up ? h : 0;
+  }
+  acc[0] += __shfl_xor(acc[0], 2, 64);
+  acc[0] += __shfl_xor(acc[0], 1, 64);
+  if ((lane & 3) == 0) sm[w * 16 + base] = acc[0];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 16 && v0 + t / 2 < f.nv) {
+    T tot = T(0);
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) tot += sm[i * 16 + t];
+    T* P = reinterpret_cast<T*>(f.part + ((long)k * f.ntot + sys) * f.nv + v0);
+    P[t] = tot;
+  }
+  __syncthreads();
 }
 template <typename T>
 __device__ __forceinline__ void feed_zero(T (&acc)[16]) {
@@ -144,8 +171,7 @@ k_feed_init(ProjFeed<T> f, const cplx<T>* __restrict__ b, long ldb, const int* _
   for (int v0 = 0; v0 < f.nv; v0 += 8) {
     feed_zero(fa);
     for (int i = i0 + threadIdx.x; i < i1; i += NT) feed_acc(f, v0, i, bs[i], fa);
-    block_sum<T, 16>(fa, sm);
-    feed_store(f, v0, blockIdx.x, sys, fa);
+    feed_store(f, v0, blockIdx.x, sys, fa, sm);
   }
 }
 
@@ -1288,13 +1314,11 @@ k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int ns
   if (f.part) {
     // the slice's projector sums of the new direction (each thread re-reads
     // only what it wrote)
-    block_sum<T, 16>(fa, sm);
-    feed_store(f, 0, blockIdx.x, sys, fa);
+    feed_store(f, 0, blockIdx.x, sys, fa, sm);
     for (int v0 = 8; v0 < f.nv; v0 += 8) {
       feed_zero(fa);
       for (int i = i0 + threadIdx.x; i < i1; i += NT) feed_acc(f, v0, i, p[i], fa);
-      block_sum<T, 16>(fa, sm);
-      feed_store(f, v0, blockIdx.x, sys, fa);
+      feed_store(f, v0, blockIdx.x, sys, fa, sm);
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
