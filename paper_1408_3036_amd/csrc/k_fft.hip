@@ -27,7 +27,9 @@ __device__ __forceinline__ int pruned(int t, int h) { return t <= h ? t : t + N 
 // With partial projector sums (f.part != null) X is the direction D, and the
 // projected input f.pre .* D - sum_v Phi_v C_v is formed in the gather and
 // also stored to Xout.
-template <typename T, int N>
+// FED selects the variant at compile time, so that the plain pass keeps its
+// registers.
+template <typename T, int N, bool FED>
 __global__ void __launch_bounds__(256)
 k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, long ldx,
        cplx<T>* __restrict__ Tb, long ldt, T scale, const int* __restrict__ act, ProjFeed<T> f,
@@ -50,7 +52,7 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
   }
   if (threadIdx.x == 0) cs[nc] = c0 + nc < g.ncols ? g.col_start[c0 + nc] : g.npw;
   for (int i = threadIdx.x; i < kZCols * LDZ; i += 256) buf[i] = cplx<T>{0, 0};
-  if (f.part) {
+  if constexpr (FED) {
     // this system's projector coefficients, the sum of its slices: eight
     // lanes per band (kMaxBands * 8 = 256 threads), then a shuffle tree
     static_assert(kMaxBands * 8 == 256, "eight lanes per band over the workgroup");
@@ -63,10 +65,22 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
       a.x += __shfl_xor(a.x, o, 64);
       a.y += __shfl_xor(a.y, o, 64);
     }
-    if (l == 0 && v < f.nv) Cs[v] = a;
+    if (l == 0 && v < f.nv) {
+      // with the direction update, part holds the residual's sums:
+      // C(p) = C(r) + beta C(p_old)
+      if (f.r && f.theta[sys] >= T(0)) a = a + (f.theta[sys] / f.rr[sys]) * f.Cp[(long)sys * f.nv + v];
+      Cs[v] = a;
+      if (f.r && blockIdx.x == 0) f.Cn[(long)sys * f.nv + v] = a;
+    }
+  }
+  // direction update: p = r + beta p while a new norm is parked in theta
+  bool upd = false;
+  T beta = T(0);
+  if constexpr (FED) {
+    upd = f.r && f.theta[sys] >= T(0);
+    if (upd) beta = f.theta[sys] / f.rr[sys];
   }
   __syncthreads();
-  cplx<T>* Xo = f.part ? Xout + (long)sys * ldx : nullptr;
   // the block's columns are one contiguous run of the sphere vector
   for (int gi = cs[0] + threadIdx.x; gi < cs[nc]; gi += 256) {
     int lo = 0, hi = nc;
@@ -75,11 +89,29 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
       if (cs[mid] <= gi) lo = mid; else hi = mid;
     }
     const int mz = gi - cs[lo] - ch[lo];
-    cplx<T> xv = Xs[gi];
-    if (Xo) {
-      if (f.pre) xv = f.pre[gi] * xv;
-      for (int v = 0; v < f.nv; ++v) xv = xv - Cs[v] * f.Phi[(long)v * f.ldphi + gi];
-      Xo[gi] = xv;
+    cplx<T> xv;
+    if constexpr (FED) {
+      // the loads of a point come before its stores (the compiler may not
+      // move them across the store to p)
+      cplx<T> ph[8];
+      const T sc = f.pre ? f.pre[gi] : T(1);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ph[u] = u < f.nv ? f.Phi[(long)u * f.ldphi + gi] : cplx<T>{0, 0};
+      if (upd) {
+        const long o = (long)sys * ldx + gi;
+        xv = f.r[o] + beta * f.p[o];
+        f.p[o] = xv;
+      } else {
+        xv = Xs[gi];
+      }
+      xv = sc * xv;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (u < f.nv) xv = xv - Cs[u] * ph[u];
+      for (int v = 8; v < f.nv; ++v) xv = xv - Cs[v] * f.Phi[(long)v * f.ldphi + gi];
+      Xout[(long)sys * ldx + gi] = xv;
+    } else {
+      xv = Xs[gi];
     }
     buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)] = xv;
   }
@@ -102,7 +134,7 @@ __device__ __forceinline__ T zblock_sum(T v, T* sm) {
   return (sm[0] + sm[1]) + (sm[2] + sm[3]);
 }
 
-template <typename T, int N>
+template <typename T, int N, bool DOT>
 __global__ void __launch_bounds__(256)
 k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, long ldt, T scale,
        const cplx<T>* __restrict__ X, long ldx, const cplx<T>* __restrict__ shift,
@@ -135,7 +167,7 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
   cplx<T>* Ys = Y + (long)sys * ldy;
   const cplx<T> sh = shift ? shift[sys] : cplx<T>{0, 0};
   const T ec = ecoef ? ecoef[sys] : T(0);
-  const cplx<T>* Ps = cd.part ? cd.p + (long)sys * cd.ldp : nullptr;
+  const cplx<T>* Ps = DOT ? cd.p + (long)sys * cd.ldp : nullptr;
   T pap = T(0);
   for (int i = cs[0] + threadIdx.x; i < cs[nc]; i += 256) {
     int lo = 0, hi = nc;
@@ -144,7 +176,8 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
       if (cs[mid] <= i) lo = mid; else hi = mid;
     }
     const int mz = i - cs[lo] - ch[lo];
-    const cplx<T> pv = Ps ? Ps[i] : cplx<T>{0, 0};
+    cplx<T> pv{0, 0};
+    if constexpr (DOT) pv = Ps[i];
     cplx<T> v = scale * buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)];
     if (Xs) {
       const cplx<T> xv = Xs[i];
@@ -154,9 +187,9 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
     if (Es) v = v + ec * Es[i];
     if (dout) v = dout[i] * v;
     Ys[i] = v;
-    pap += pv.x * v.x + pv.y * v.y;
+    if constexpr (DOT) pap += pv.x * v.x + pv.y * v.y;
   }
-  if (cd.part) {
+  if constexpr (DOT) {
     __shared__ T smd[4];
     const T tot = zblock_sum(pap, smd);
     if (threadIdx.x == 0) {
@@ -169,6 +202,8 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
         }
       }
     }
+    if (cd.Cn && blockIdx.x == 0 && threadIdx.x < cd.nv)
+      cd.Cp[(long)sys * cd.nv + threadIdx.x] = cd.Cn[(long)sys * cd.nv + threadIdx.x];
   }
 }
 
@@ -348,8 +383,8 @@ void launch_zinv(const Geom& g, const cplx<T>* tw, const cplx<T>* X, long ldx, c
                  T scale, const int* act, int nsys, hipStream_t s) {
   if (nsys <= 0) return;
   dim3 grid((g.ncols + kZCols - 1) / kZCols, nsys);
-  LGW_DISPATCH_N(g.N, (k_zinv<T, NN_><<<grid, 256, 0, s>>>(g, tw, X, ldx, Tb, ldt, scale, act, ProjFeed<T>{},
-                                                          nullptr)));
+  LGW_DISPATCH_N(g.N, (k_zinv<T, NN_, false><<<grid, 256, 0, s>>>(g, tw, X, ldx, Tb, ldt, scale, act,
+                                                                 ProjFeed<T>{}, nullptr)));
 }
 
 template <typename T>
@@ -357,7 +392,7 @@ void launch_zinv_fed(const Geom& g, const cplx<T>* tw, const ProjFeed<T>& f, con
                      long ldx, cplx<T>* Tb, long ldt, const int* act, int nsys, hipStream_t s) {
   if (nsys <= 0) return;
   dim3 grid((g.ncols + kZCols - 1) / kZCols, nsys);
-  LGW_DISPATCH_N(g.N, (k_zinv<T, NN_><<<grid, 256, 0, s>>>(g, tw, D, ldx, Tb, ldt, T(1), act, f, Xout)));
+  LGW_DISPATCH_N(g.N, (k_zinv<T, NN_, true><<<grid, 256, 0, s>>>(g, tw, D, ldx, Tb, ldt, T(1), act, f, Xout)));
 }
 
 template <typename T>
@@ -375,8 +410,13 @@ void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, 
                  const T* dout, const CgDot<T>& cd) {
   if (nsys <= 0) return;
   dim3 grid(zcol_blocks(g), nsys);
-  LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E, lde,
-                                                        ecoef, Y, ldy, act, dout, cd)));
+  if (cd.part) {
+    LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_, true><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E, lde,
+                                                                 ecoef, Y, ldy, act, dout, cd)));
+  } else {
+    LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_, false><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E,
+                                                                  lde, ecoef, Y, ldy, act, dout, cd)));
+  }
 }
 
 int zcol_blocks(const Geom& g) { return (g.ncols + kZCols - 1) / kZCols; }

@@ -150,6 +150,7 @@ k_cg_init(SolveVecs<T> v, const cplx<T>* __restrict__ b, long ldb, const int* __
   }
   block_sum<T, 1>(acc, sm);
   if (threadIdx.x == 0) {
+    if (v.cnt) v.cnt[blockIdx.x] = 0;
     v.rr[sys] = acc[0];
     v.theta[sys] = T(-1);
     if (!keep_x) { v.bb[sys] = acc[0]; v.iters[sys] = 0; }
@@ -1328,6 +1329,84 @@ k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int ns
   }
 }
 
+// The x/r phase of a single-precision CG step whose direction update and
+// p^H A p are done by the transforms (launch_cg_step_fed).  The slice sums of
+// conj(Phi_v) (pre .* r_new) are left for the next projection; the norm goes
+// through a ticket: each workgroup stores its slice norm, the last of the
+// system to take a ticket (all have read rr and the flag by then) sums them
+// in a fixed order, parks the norm in theta, counts the step, sets the flag
+// and returns the counter to zero.
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_cg_split2f(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int nsplit, const T* __restrict__ dots,
+             int ndots, T* __restrict__ part2, ProjFeed<T> f) {
+  __shared__ T sm[16 * (NT / 64)];
+  const int slot = blockIdx.y;
+  const int sys = sys_of(act, slot);
+  if (v.flag[sys]) return;
+  T pAp = T(0);
+  for (int k = 0; k < ndots; ++k) pAp += dots[(long)slot * ndots + k];
+  if (!(pAp > T(0))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) v.flag[sys] = FLAG_BREAK;
+    return;
+  }
+  const T alpha = v.rr[sys] / pAp;
+  int i0, i1;
+  slice_of<T>(npw, nsplit, i0, i1);
+  const long off = (long)sys * v.ld;
+  cplx<T>* x = v.x + off;
+  cplx<T>* r = v.r + off;
+  const cplx<T>* p = v.p + off;
+  const cplx<T>* Ap = v.Ap + off;
+  T acc[1] = {T(0)};
+  T fa[16];
+  feed_zero(fa);
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) {
+    // every load of the step before its stores
+    const cplx<T> pi = p[i], ai = Ap[i], ri = r[i], xi = x[i];
+    cplx<T> ph[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ph[u] = u < f.nv ? f.Phi[(long)u * f.ldphi + i] : cplx<T>{0, 0};
+    const T sc = f.pre ? f.pre[i] : T(1);
+    x[i] = xi + alpha * pi;
+    const cplx<T> rn = ri - alpha * ai;
+    r[i] = rn;
+    acc[0] += norm2(rn);
+    const cplx<T> y = sc * rn;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      fa[2 * u] += ph[u].x * y.x + ph[u].y * y.y;
+      fa[2 * u + 1] += ph[u].x * y.y - ph[u].y * y.x;
+    }
+  }
+  block_sum<T, 1>(acc, sm);
+  feed_store(f, 0, blockIdx.x, sys, fa, sm);
+  for (int v0 = 8; v0 < f.nv; v0 += 8) {
+    feed_zero(fa);
+    for (int i = i0 + threadIdx.x; i < i1; i += NT) feed_acc(f, v0, i, r[i], fa);
+    feed_store(f, v0, blockIdx.x, sys, fa, sm);
+  }
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    part2[(long)slot * nsplit + blockIdx.x] = acc[0];
+    const int ticket = __hip_atomic_fetch_add(v.cnt + slot, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = ticket == nsplit - 1;
+  }
+  __syncthreads();
+  if (!last || threadIdx.x >= 64) return;
+  // the last workgroup's first wave: the slice norms loaded side by side, then
+  // a fixed shuffle tree (nsplit <= 64)
+  T e = threadIdx.x < nsplit
+            ? __hip_atomic_load(part2 + (long)slot * nsplit + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+            : T(0);
+  const T rrn = wave_sum(e);
+  if (threadIdx.x != 0) return;
+  v.cnt[slot] = 0;
+  v.theta[sys] = rrn;
+  v.iters[sys] += 1;
+  if (rrn <= tol2 * v.bb[sys]) v.flag[sys] = FLAG_CONV;
+}
+
 }  // namespace
 
 template <typename T>
@@ -1343,6 +1422,17 @@ void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act
   }
   k_cg_split3<T><<<grid, NT, 0, s>>>(v, npw, tol2, act, nsplit, part + (long)nsys * nsplit, f);
 }
+
+template <typename T>
+void launch_cg_step_fed(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
+                        const T* dots, int ndots, const ProjFeed<T>& f, hipStream_t s) {
+  if (nsys <= 0) return;
+  k_cg_split2f<T><<<dim3(nsplit, nsys), NT, 0, s>>>(v, npw, tol2, act, nsplit, dots, ndots, part, f);
+}
+template void launch_cg_step_fed<double>(const SolveVecs<double>&, int, double, const int*, int, int, double*,
+                                         const double*, int, const ProjFeed<double>&, hipStream_t);
+template void launch_cg_step_fed<float>(const SolveVecs<float>&, int, float, const int*, int, int, float*,
+                                        const float*, int, const ProjFeed<float>&, hipStream_t);
 
 template void launch_cg_step_split<double>(const SolveVecs<double>&, int, double, const int*, int, int, double*,
                                            hipStream_t, const ProjFeed<double>&, const double*, int);

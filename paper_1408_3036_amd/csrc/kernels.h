@@ -24,6 +24,17 @@ struct ProjFeed {
   cplx<T>* part = nullptr;        // [nsplit][ntot][nv]
   int ntot = 0;                   // systems of the batch (stride of part)
   int nsplit = 1;
+  // Direction update in the first transform (single-precision CG, see
+  // launch_cg_step_fed): with r != null, part holds the slice sums of the
+  // residual r, and while theta[sys] >= 0 the transform first sets
+  // p = r + beta p (beta = theta / rr) and uses C = sum(part) + beta Cp;
+  // its workgroup 0 leaves C in Cn (the last transform moves it to Cp).
+  const cplx<T>* r = nullptr;
+  cplx<T>* p = nullptr;           // the directions, updated in place
+  const T* rr = nullptr;
+  const T* theta = nullptr;
+  const cplx<T>* Cp = nullptr;    // [ntot][nv] coefficients of the current p
+  cplx<T>* Cn = nullptr;          // [ntot][nv] those of the new p
 };
 
 bool grid_supported(int N);
@@ -40,6 +51,11 @@ struct CgDot {
   T* part = nullptr;            // [nslots][nblk], nblk = zcol_blocks(g)
   T* rr = nullptr;
   T* theta = nullptr;
+  // direction update in the first transform (ProjFeed::r): workgroup 0 also
+  // moves the new direction's projector coefficients Cn to Cp
+  cplx<T>* Cp = nullptr;
+  const cplx<T>* Cn = nullptr;
+  int nv = 0;
 };
 
 // ---- transforms (T = double or float) -----------------------------------
@@ -114,6 +130,7 @@ struct SolveVecs {
   cplx<T>* rho;   // SQMR rho
   int* flag;
   int* iters;
+  int* cnt;       // ticket counters per active slot (launch_cg_step_fed), or null
 };
 template <typename T>
 void launch_cg_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw,
@@ -202,6 +219,14 @@ namespace lgw {
 template <typename T>
 void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
                           hipStream_t s, const ProjFeed<T>& f = {}, const T* dots = nullptr, int ndots = 0);
+// The rest of a single-precision CG step when the transforms do the direction
+// update (ProjFeed::r) and p^H A p (CgDot): x += alpha p, r -= alpha A p, the
+// slice sums of the new r for the next projection, and, by the last workgroup
+// of each system to finish (an atomic ticket on v.cnt), the new norm parked in
+// theta, the count and the convergence flag.  part needs nsys * nsplit entries.
+template <typename T>
+void launch_cg_step_fed(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
+                        const T* dots, int ndots, const ProjFeed<T>& f, hipStream_t s);
 }  // namespace lgw
 
 namespace lgw {

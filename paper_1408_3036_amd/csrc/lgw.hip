@@ -428,6 +428,8 @@ struct Batch {
   cplx<T>* ptmp = nullptr;
   cplx<T>* fpart = nullptr;    // CG with a preconditioner: projector partial sums (ProjFeed)
   T* dot_part = nullptr;       // single-precision CG with a preconditioner: p^H A p partials (CgDot)
+  cplx<T>* cp = nullptr;       // ... and the projector coefficients of the current and the next direction
+  cplx<T>* cn = nullptr;
   std::vector<int> h_iters, h_flags;
   Batch() = default;
   Batch(const Batch&) = delete;
@@ -435,7 +437,7 @@ struct Batch {
   Batch(Batch&& o) noexcept { *this = std::move(o); }
   Batch& operator=(Batch&& o) noexcept {
     kind = o.kind; nsys = o.nsys; ld = o.ld; v = o.v; tmp = o.tmp; Tb = o.Tb; shift = o.shift; w2 = o.w2;
-    act = o.act; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp; fpart = o.fpart; dot_part = o.dot_part;
+    act = o.act; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp; fpart = o.fpart; dot_part = o.dot_part; cp = o.cp; cn = o.cn;
     h_iters = std::move(o.h_iters); h_flags = std::move(o.h_flags);
     return *this;
   }
@@ -476,6 +478,11 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   b.dot_part = b.fpart && sizeof(T) == 4
                    ? c->buf<T>(t + ".dots", (size_t)std::min(nsys, lgw_ctx::kTimedMin) * zcol_blocks(c->geom))
                    : nullptr;
+  if (b.dot_part) {
+    b.cp = c->buf<cplx<T>>(t + ".cp", (size_t)nsys * c->nv);
+    b.cn = c->buf<cplx<T>>(t + ".cn", (size_t)nsys * c->nv);
+    b.v.cnt = c->buf<int>(t + ".cnt", nsys);
+  }
   {
     size_t cap = 0;
     for (int n = 1; n <= nsys; n += (n < 64 ? 1 : 16)) cap = std::max(cap, (size_t)proj_ksplit<T>(c->npw, n) * n);
@@ -520,15 +527,25 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     feed.nsplit = b.nsplit;
   }
   // ... and, in single precision (the scaling folded into the transform's
-  // store), p^H A p from that transform: the split CG's first phase is skipped
+  // store), the first transform also updates the direction and the last one
+  // leaves p^H A p: a step is the operator application plus one x/r launch
   CgDot<T> cdot;
   const bool tdots = fed && b.dot_part;
   if (tdots) {
+    feed.r = b.v.r;
+    feed.p = b.v.p;
+    feed.rr = b.v.rr;
+    feed.theta = b.v.theta;
+    feed.Cp = b.cp;
+    feed.Cn = b.cn;
     cdot.p = b.v.p;
     cdot.ldp = b.ld;
     cdot.part = b.dot_part;
     cdot.rr = b.v.rr;
     cdot.theta = b.v.theta;
+    cdot.Cp = b.cp;
+    cdot.Cn = b.cn;
+    cdot.nv = c->nv;
   }
   const int nblk = zcol_blocks(c->geom);
   if (b.kind == K_SQMR)
@@ -596,8 +613,11 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
           c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
         } else if (na <= lgw_ctx::kTimedMin) {
           // small batch: spread each system over several workgroups
-          launch_cg_step_split<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, c->stream, feed,
-                                  tdots ? b.dot_part : nullptr, nblk);
+          if (tdots)
+            launch_cg_step_fed<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, b.dot_part, nblk, feed,
+                                  c->stream);
+          else
+            launch_cg_step_split<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, c->stream, feed);
         } else {
           launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
           // reads p, Ap (twice), x, r (twice), p; writes x, r, p
@@ -619,7 +639,8 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
           (uintptr_t)b.v.Ap, (uintptr_t)b.v.d, (uintptr_t)b.v.rr, (uintptr_t)b.v.bb, (uintptr_t)b.v.theta,
           (uintptr_t)b.v.rho, (uintptr_t)b.v.flag, (uintptr_t)b.v.iters, (uintptr_t)b.tmp, (uintptr_t)b.Tb,
           (uintptr_t)b.shift, (uintptr_t)b.w2, (uintptr_t)b.act, (uintptr_t)b.split_part, (uintptr_t)b.pre,
-          (uintptr_t)b.ptmp, (uintptr_t)b.fpart, (uintptr_t)fed, (uintptr_t)b.dot_part, (uintptr_t)tdots};
+          (uintptr_t)b.ptmp, (uintptr_t)b.fpart, (uintptr_t)fed, (uintptr_t)b.dot_part, (uintptr_t)tdots,
+          (uintptr_t)b.cp, (uintptr_t)b.cn, (uintptr_t)b.v.cnt};
       auto f = c->graphs.find(key);
       if (f != c->graphs.end()) {
         gx = f->second;
