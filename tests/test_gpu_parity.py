@@ -368,6 +368,36 @@ def test_preconditioned_shifted_forms_match_oracle(sysc1, precision):
         assert st_fast["total_happly"] < 0.8 * st_plain["total_happly"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_preconditioned_squared_form_matches_oracle(sysc1, precision):
+    """The kinetic preconditioner with the paper's squared equation on the
+    imaginary axis (Sec. III.A): small batches, so the CG steps hand the
+    projector's partial sums to the transforms (in single precision the first
+    transform of the squared operator also updates the direction and the second
+    one's store carries p^H A p)."""
+    from paper_1408_3036_amd import Lgw
+    w, b, s, _ = sysc1
+    zs = [0.0, 0.05j, 0.3j, 2.0j]
+    x = random_potentials(w.N, 2, 61)
+    ref = np.array([s.chi0(z, x) for z in zs])
+    gate = 1e-10 if precision == "fp64" else 1e-6
+    lp = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps,
+             precision=precision, precond=True, imag_form="squared",
+             tol=1e-13 if precision == "fp64" else 1e-10)
+    try:
+        dn = lp.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+        st = lp.stats()
+    finally:
+        lp.close()
+    print(f"{precision} squared+precond: sweeps {sorted(set(st['refine_sweeps'].tolist()))} "
+          f"iters {st['iters'].min()}..{st['iters'].max()}")
+    assert np.all(st["flags"] == 1), st
+    for k in range(len(zs)):
+        err = colwise_rel(dn[k], ref[k])
+        print(f"  z={zs[k]}: {err:.2e}")
+        assert err < gate, (zs[k], err)
+
+
 def test_preconditioned_lanczos_and_vjp(sysc1):
     from paper_1408_3036_amd import Lgw
     w, b, s, lg = sysc1
