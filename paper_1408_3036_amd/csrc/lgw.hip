@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <thread>
 #include <exception>
 #include <functional>
@@ -170,9 +171,10 @@ struct lgw_ctx {
   z64* keep_b = nullptr;
   z64* keep_f = nullptr;
   int keep_n = 0, keep_cap = 0;
-  // iterations the last small-batch solve of each (kind, precision) took: the
-  // next one runs that many before its first convergence poll
-  std::map<std::pair<int, int>, int> it_hint;
+  // iterations the last small-batch solve of each (kind, precision, pass of
+  // the refinement) took: the next one runs that many before its first
+  // convergence poll
+  std::map<std::tuple<int, int, int>, int> it_hint;
   void drop_graphs() {
     if (graphs.empty()) return;
     if (stream) (void)hipStreamSynchronize(stream);
@@ -506,7 +508,7 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
 // inner tolerance for nearly resonant real-axis systems.
 template <class T>
 void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* bidx_dev, bool keep_x, double tol,
-               const std::vector<int>& start, int stall = 0) {
+               const std::vector<int>& start, int stall = 0, int pass = 0) {
   std::vector<int> act(start);
   if (act.empty()) return;
   const int npw = c->npw;
@@ -560,7 +562,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   // solves of a recursion need similar counts), then polls come every two
   // iterations for a while, since a poll costs less than a few wasted ones.
   const bool small = c->opts.use_graph && (int)act.size() <= lgw_ctx::kTimedMin && !c->time_all;
-  int& hint = c->it_hint[{b.kind, (int)sizeof(T)}];
+  int& hint = c->it_hint[{b.kind, (int)sizeof(T), std::min(pass, 3)}];
   std::vector<int> flags(b.nsys), iters(b.nsys);
   std::vector<T> est(b.nsys);
   std::vector<double> best(b.nsys, 0.0);
@@ -782,7 +784,7 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       // restart from x with the true residual: b.v.x already holds X (or y)
       h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
       if (pre) launch_scale_diag<double>(R, npw, d_act, R, npw, d_act, pre, npw, (int)bad.size(), c->stream);
-      run_batch<double>(c, b, R, npw, nullptr, true, itol, bad, stall);
+      run_batch<double>(c, b, R, npw, nullptr, true, itol, bad, stall, 1 + restart);
       h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
       x_out(d_act, (int)bad.size());
       lst = bad;
@@ -842,7 +844,7 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       // FP32 SQMR stops on a 32-iteration stagnation window like the FP64 one
       // (an iterate pushed past its attainable accuracy spoils the correction);
       // CG keeps a longer window for slowly converging imaginary-axis systems
-      run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad, kind == K_SQMR ? 32 : 96);
+      run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad, kind == K_SQMR ? 32 : 96, sweep);
       h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
       if (b.pre) launch_scale_diag<float>(b.v.x, npw, d_act, b.v.x, npw, d_act, b.pre, npw, (int)bad.size(), c->stream);
       launch_cvt_32_64_axpy(b.v.x, X, rs, d_act, npw, npw, (int)bad.size(), c->stream);
