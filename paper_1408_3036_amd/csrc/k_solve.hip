@@ -150,7 +150,6 @@ k_cg_init(SolveVecs<T> v, const cplx<T>* __restrict__ b, long ldb, const int* __
   }
   block_sum<T, 1>(acc, sm);
   if (threadIdx.x == 0) {
-    if (v.cnt) v.cnt[blockIdx.x] = 0;
     v.rr[sys] = acc[0];
     v.theta[sys] = T(-1);
     if (!keep_x) { v.bb[sys] = acc[0]; v.iters[sys] = 0; }
@@ -158,22 +157,76 @@ k_cg_init(SolveVecs<T> v, const cplx<T>* __restrict__ b, long ldb, const int* __
   }
 }
 
-// the projector sums of the first direction p = b, by slice: grid (nsplit, nsys)
+// Initialisation of a small preconditioned CG batch over the split grid
+// (nsplit, nsys): x = 0 (unless kept), r = p = b on each slice, the slice sums
+// conj(Phi_v) (pre .* b) for the first projection, and |b|^2 through the
+// ticket (the last workgroup of a system sums the slice norms in one wave and
+// writes rr, theta, bb, the count and the flag; the counters are zero
+// between launches).
 template <typename T>
 __global__ void __launch_bounds__(NT)
-k_feed_init(ProjFeed<T> f, const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx, int npw,
-            const int* __restrict__ act) {
+k_cg_init_fed(SolveVecs<T> v, const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx, int npw,
+              int keep_x, const int* __restrict__ act, T* __restrict__ npart, ProjFeed<T> f) {
   __shared__ T sm[16 * (NT / 64)];
-  const int sys = sys_of(act, blockIdx.y);
+  __shared__ int last;
+  const int slot = blockIdx.y;
+  const int sys = sys_of(act, slot);
+  const int nsplit = f.nsplit;
   const cplx<T>* bs = b + (long)(bidx ? bidx[sys] : sys) * ldb;
-  const int chunk = (npw + f.nsplit - 1) / f.nsplit;
+  const int chunk = (npw + nsplit - 1) / nsplit;
   const int i0 = blockIdx.x * chunk, i1 = min(npw, i0 + chunk);
+  const long off = (long)sys * v.ld;
+  cplx<T>* x = v.x + off;
+  cplx<T>* r = v.r + off;
+  cplx<T>* p = v.p + off;
+  T acc[1] = {T(0)};
   T fa[16];
-  for (int v0 = 0; v0 < f.nv; v0 += 8) {
+  feed_zero(fa);
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) {
+    const cplx<T> bi = bs[i];
+    cplx<T> ph[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ph[u] = u < f.nv ? f.Phi[(long)u * f.ldphi + i] : cplx<T>{0, 0};
+    const T sc = f.pre ? f.pre[i] : T(1);
+    if (!keep_x) x[i] = cplx<T>{0, 0};
+    r[i] = bi;
+    p[i] = bi;
+    acc[0] += norm2(bi);
+    const cplx<T> y = sc * bi;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      fa[2 * u] += ph[u].x * y.x + ph[u].y * y.y;
+      fa[2 * u + 1] += ph[u].x * y.y - ph[u].y * y.x;
+    }
+  }
+  block_sum<T, 1>(acc, sm);
+  feed_store(f, 0, blockIdx.x, sys, fa, sm);
+  for (int v0 = 8; v0 < f.nv; v0 += 8) {
     feed_zero(fa);
     for (int i = i0 + threadIdx.x; i < i1; i += NT) feed_acc(f, v0, i, bs[i], fa);
     feed_store(f, v0, blockIdx.x, sys, fa, sm);
   }
+  if (threadIdx.x == 0) {
+    npart[(long)slot * nsplit + blockIdx.x] = acc[0];
+    const int ticket = __hip_atomic_fetch_add(v.cnt + slot, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = ticket == nsplit - 1;
+  }
+  __syncthreads();
+  if (!last || threadIdx.x >= 64) return;
+  const T e = threadIdx.x < nsplit
+                  ? __hip_atomic_load(npart + (long)slot * nsplit + threadIdx.x, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT)
+                  : T(0);
+  const T bb = wave_sum(e);
+  if (threadIdx.x != 0) return;
+  v.cnt[slot] = 0;
+  v.rr[sys] = bb;
+  v.theta[sys] = T(-1);
+  if (!keep_x) {
+    v.bb[sys] = bb;
+    v.iters[sys] = 0;
+  }
+  v.flag[sys] = bb == T(0) ? FLAG_CONV : 0;
 }
 
 template <typename T>
@@ -535,10 +588,12 @@ void launch_proj(const cplx<T>* Phi, long ldphi, int nv, int npw, cplx<T>* Y, lo
 
 template <typename T>
 void launch_cg_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw, int nsys,
-                    bool keep_x, const int* act, hipStream_t s, const ProjFeed<T>& f) {
+                    bool keep_x, const int* act, hipStream_t s, const ProjFeed<T>& f, T* npart) {
   if (nsys <= 0) return;
-  k_cg_init<T><<<nsys, NT, 0, s>>>(v, b, ldb, bidx, npw, keep_x ? 1 : 0, act);
-  if (f.part && f.nv > 0) k_feed_init<T><<<dim3(f.nsplit, nsys), NT, 0, s>>>(f, b, ldb, bidx, npw, act);
+  if (f.part)
+    k_cg_init_fed<T><<<dim3(f.nsplit, nsys), NT, 0, s>>>(v, b, ldb, bidx, npw, keep_x ? 1 : 0, act, npart, f);
+  else
+    k_cg_init<T><<<nsys, NT, 0, s>>>(v, b, ldb, bidx, npw, keep_x ? 1 : 0, act);
 }
 
 template <typename T>
@@ -651,7 +706,7 @@ void launch_real_zxy_to_xyz(int N, const double* in, double* out, hipStream_t s)
   template void launch_proj<T>(const cplx<T>*, long, int, int, cplx<T>*, long, const int*, int,         \
                                hipStream_t);                                                           \
   template void launch_cg_init<T>(const SolveVecs<T>&, const cplx<T>*, long, const int*, int, int, bool,\
-                                  const int*, hipStream_t, const ProjFeed<T>&);                                    \
+                                  const int*, hipStream_t, const ProjFeed<T>&, T*);                                \
   template void launch_cg_step<T>(const SolveVecs<T>&, int, T, const int*, int, hipStream_t);          \
   template void launch_sqmr_init<T>(const SolveVecs<T>&, const cplx<T>*, long, const int*, int, int,    \
                                     bool, const int*, hipStream_t);                                                \

@@ -130,11 +130,15 @@ struct SolveVecs {
   cplx<T>* rho;   // SQMR rho
   int* flag;
   int* iters;
-  int* cnt;       // ticket counters per active slot (launch_cg_step_fed), or null
+  int* cnt;       // ticket counters per active slot, zero between launches (fed CG kernels), or null
 };
+// With f.part: the split-grid initialisation of a small preconditioned batch,
+// which also leaves the first projection's slice sums and needs v.cnt (zero)
+// and npart (nsys * f.nsplit entries)
 template <typename T>
 void launch_cg_init(const SolveVecs<T>& v, const cplx<T>* b, long ldb, const int* bidx, int npw,
-                    int nsys, bool keep_x, const int* act, hipStream_t s, const ProjFeed<T>& f = {});
+                    int nsys, bool keep_x, const int* act, hipStream_t s, const ProjFeed<T>& f = {},
+                    T* npart = nullptr);
 template <typename T>
 void launch_cg_step(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, hipStream_t s);
 template <typename T>

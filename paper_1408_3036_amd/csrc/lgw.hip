@@ -483,7 +483,12 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   if (b.dot_part) {
     b.cp = c->buf<cplx<T>>(t + ".cp", (size_t)nsys * c->nv);
     b.cn = c->buf<cplx<T>>(t + ".cn", (size_t)nsys * c->nv);
+  }
+  if (b.fpart) {
+    // ticket counters of the fed CG kernels: zero here, and every ticketed
+    // launch leaves them zero
     b.v.cnt = c->buf<int>(t + ".cnt", nsys);
+    HIPCHK(hipMemsetAsync(b.v.cnt, 0, nsys * sizeof(int), c->stream));
   }
   {
     size_t cap = 0;
@@ -553,7 +558,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   if (b.kind == K_SQMR)
     launch_sqmr_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream);
   else
-    launch_cg_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream, feed);
+    launch_cg_init<T>(b.v, B, ldb, bidx_dev, npw, (int)act.size(), keep_x, b.act, c->stream, feed, b.split_part);
   c->check_launch();
   const int check = std::max(1, c->opts.check_every);
   const int maxit = std::max(1, c->opts.max_iter);
