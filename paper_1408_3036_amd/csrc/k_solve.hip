@@ -420,6 +420,30 @@ k_resid(const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx,
   if (threadIdx.x == 0) res[sys] = acc[0];
 }
 
+// the same over ns workgroups per system (grid (ns, nsys)): res[sys][blk] are
+// the slice norms, summed by the caller
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_resid_split(const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx,
+              const cplx<T>* __restrict__ AX, long lda, cplx<T>* __restrict__ R, long ldr,
+              double* __restrict__ res, int npw, const int* __restrict__ act) {
+  __shared__ double sm[NT / 64];
+  const int sys = sys_of(act, blockIdx.y);
+  const int chunk = (npw + gridDim.x - 1) / gridDim.x;
+  const int i0 = blockIdx.x * chunk, i1 = min(npw, i0 + chunk);
+  const cplx<T>* bs = b + (long)(bidx ? bidx[sys] : sys) * ldb;
+  const cplx<T>* as = AX + (long)sys * lda;
+  cplx<T>* rs = R ? R + (long)sys * ldr : nullptr;
+  double acc[1] = {0.0};
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) {
+    const cplx<T> ri = bs[i] - as[i];
+    if (rs) rs[i] = ri;
+    acc[0] += (double)norm2(ri);
+  }
+  block_sum<double, 1>(acc, sm);
+  if (threadIdx.x == 0) res[(long)sys * gridDim.x + blockIdx.x] = acc[0];
+}
+
 // ---------------------------------------------------------------- BLAS-1
 constexpr int kDotBlocks = 64;
 
@@ -621,6 +645,15 @@ void launch_resid(const cplx<T>* b, long ldb, const int* bidx, const cplx<T>* AX
   if (nsys <= 0) return;
   k_resid<T><<<nsys, NT, 0, s>>>(b, ldb, bidx, AX, lda, R, ldr, res, npw, act);
 }
+
+template <typename T>
+void launch_resid_split(const cplx<T>* b, long ldb, const int* bidx, const cplx<T>* AX, long lda, cplx<T>* R,
+                        long ldr, double* res, int ns, int npw, const int* act, int nsys, hipStream_t s) {
+  if (nsys <= 0) return;
+  k_resid_split<T><<<dim3(ns, nsys), NT, 0, s>>>(b, ldb, bidx, AX, lda, R, ldr, res, npw, act);
+}
+template void launch_resid_split<double>(const z64*, long, const int*, const z64*, long, z64*, long, double*, int,
+                                         int, const int*, int, hipStream_t);
 
 void launch_dots(const z64* A, long lda, int m, const z64* w, long n, z64* h, z64* partial, hipStream_t s) {
   if (m <= 0) return;

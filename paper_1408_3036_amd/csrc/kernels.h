@@ -152,6 +152,11 @@ template <typename T>
 void launch_resid(const cplx<T>* b, long ldb, const int* bidx, const cplx<T>* AX, long lda,
                   cplx<T>* R, long ldr, double* res, int npw, const int* act, int nsys,
                   hipStream_t s);
+// the same over ns workgroups per system: res[sys * ns + k] is the norm of
+// slice k (the caller sums them)
+template <typename T>
+void launch_resid_split(const cplx<T>* b, long ldb, const int* bidx, const cplx<T>* AX, long lda, cplx<T>* R,
+                        long ldr, double* res, int ns, int npw, const int* act, int nsys, hipStream_t s);
 
 // ---- BLAS-1 style helpers on long vectors --------------------------------
 // out[i*m + j]... generic dot products: h[i] = sum_e conj(A[i][e]) w[e], i < m

@@ -709,7 +709,6 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
   z64* AX = c->buf<z64>("sv.AX", (size_t)nsys * npw);
   z64* tmp = c->buf<z64>("sv.tmp", kind == K_CGSQ ? (size_t)nsys * npw : 1);
   z64* Tb = c->buf<z64>("sv.Tb", (size_t)nsys * c->N * c->ncols);
-  double* res = c->buf<double>("sv.res", nsys);
   double* bb = c->buf<double>("sv.bb", nsys);
   z64* d_shift = c->buf<z64>("sv.shift", nsys);
   double* d_w2 = c->buf<double>("sv.w2", nsys);
@@ -725,6 +724,9 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
   // residuals: the host needs it only to form relative residuals
   std::vector<double> h_bb(nsys), h_res(nsys);
   bool have_bb = false;
+  const int rsn = std::max(1, std::min(64, npw / 1024));
+  double* resp = c->buf<double>("sv.resp", (size_t)nsys * rsn);
+  std::vector<double> h_resp((size_t)nsys * rsn);
   HIPCHK(hipMemsetAsync(AX, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
   launch_resid<double>(B, npw, d_bidx, AX, npw, nullptr, 0, bb, npw, d_act, nsys, c->stream);
   // true residual R = B - A X over the listed systems; returns rel. residuals
@@ -736,10 +738,16 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
     // projected residual below cannot see
     proj<double>(c, X, npw, d_act, (int)lst.size());
     apply_op<double>(c, kind, X, AX, tmp, Tb, npw, d_shift, d_w2, d_act, (int)lst.size());
-    launch_resid<double>(B, npw, d_bidx, AX, npw, R, npw, res, npw, d_act, (int)lst.size(), c->stream);
-    readback(c, {{h_res.data(), res, nsys * sizeof(double)},
+    // slice norms over several workgroups per system, summed here in order
+    launch_resid_split<double>(B, npw, d_bidx, AX, npw, R, npw, resp, rsn, npw, d_act, (int)lst.size(), c->stream);
+    readback(c, {{h_resp.data(), resp, h_resp.size() * sizeof(double)},
                  {h_bb.data(), bb, have_bb ? 0 : nsys * sizeof(double)}});
     have_bb = true;
+    for (int s : lst) {
+      double t = 0.0;
+      for (int k = 0; k < rsn; ++k) t += h_resp[(size_t)s * rsn + k];
+      h_res[s] = t;
+    }
     for (int s : lst) out.rel[s] = h_bb[s] > 0 ? std::sqrt(h_res[s] / h_bb[s]) : 0.0;
   };
 
