@@ -39,11 +39,13 @@ struct ProjFeed {
 
 bool grid_supported(int N);
 
-// CG step work done by the last transform of an operator application whose
-// store is the final A p (single precision, scaling folded into the store):
-// per column workgroup k of active slot j, part[j * nblk + k] = the block's
-// Re p^H (A p); workgroup 0 also commits the norm parked in theta to rr
-// (theta >= 0), as the split CG's first phase would.  part == null: off.
+// CG step work done by the last transform of an operator application: per
+// column workgroup k of active slot j, part[j * nblk + k] = the block's
+// Re p^H y of its store y with the given vectors p (the directions where the
+// store is the final A p, the projected input P S p where an outer projection
+// follows: p^H S P y = (P S p)^H y); workgroup 0 also commits the norm parked
+// in theta to rr (theta >= 0), as the split CG's first phase would.
+// part == null: off.
 template <typename T>
 struct CgDot {
   const cplx<T>* p = nullptr;   // directions, ld ldp

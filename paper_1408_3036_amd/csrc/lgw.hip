@@ -401,7 +401,6 @@ void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, 
     X = ptmp;
   }
   if (!D) fed = nullptr;
-  if (!fold) cd = nullptr;   // the last transform stores the final A X only when S is folded into it
   const T* dout = fold ? pre : nullptr;
   if (kind == K_CGSQ) {
     happly<T>(c, X, ld, tmp, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, nullptr, fed, D);
@@ -477,7 +476,7 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   b.split_part = c->buf<T>(t + ".split", (size_t)2 * std::min(nsys, lgw_ctx::kTimedMin) * b.nsplit);
   b.fpart = b.pre && kind != K_SQMR && c->nv > 0 ? c->buf<cplx<T>>(t + ".fpart", (size_t)b.nsplit * nsys * c->nv)
                                                  : nullptr;
-  b.dot_part = b.fpart && sizeof(T) == 4
+  b.dot_part = b.fpart
                    ? c->buf<T>(t + ".dots", (size_t)std::min(nsys, lgw_ctx::kTimedMin) * zcol_blocks(c->geom))
                    : nullptr;
   if (b.dot_part) {
@@ -533,9 +532,11 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     feed.ntot = b.nsys;
     feed.nsplit = b.nsplit;
   }
-  // ... and, in single precision (the scaling folded into the transform's
-  // store), the first transform also updates the direction and the last one
-  // leaves p^H A p: a step is the operator application plus one x/r launch
+  // ... and the first transform also updates the direction while the last
+  // one leaves p^H A p, so a step is the operator application plus one x/r
+  // launch.  In single precision that transform stores A p itself (S folded
+  // in); in double precision the outer projection follows it, and
+  // p^H S P Y = (P S p)^H Y takes the projected input it was given instead.
   CgDot<T> cdot;
   const bool tdots = fed && b.dot_part;
   if (tdots) {
@@ -545,7 +546,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     feed.theta = b.v.theta;
     feed.Cp = b.cp;
     feed.Cn = b.cn;
-    cdot.p = b.v.p;
+    cdot.p = sizeof(T) == 4 ? b.v.p : b.ptmp;
     cdot.ldp = b.ld;
     cdot.part = b.dot_part;
     cdot.rr = b.v.rr;
