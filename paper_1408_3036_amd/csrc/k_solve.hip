@@ -1333,12 +1333,12 @@ k_cg_split1(SolveVecs<T> v, int npw, const int* __restrict__ act, int nsplit, T*
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_cg_split2(SolveVecs<T> v, int npw, const int* __restrict__ act, int nsplit, const T* __restrict__ part,
-            int npart, T* __restrict__ part2) {
+            T* __restrict__ part2) {
   __shared__ T sm[NT / 64];
   const int sys = sys_of(act, blockIdx.y);
   if (v.flag[sys]) return;
   T pAp = T(0);
-  for (int k = 0; k < npart; ++k) pAp += part[(long)blockIdx.y * npart + k];
+  for (int k = 0; k < nsplit; ++k) pAp += part[(long)blockIdx.y * nsplit + k];
   if (!(pAp > T(0))) {
     if (blockIdx.x == 0 && threadIdx.x == 0) v.flag[sys] = FLAG_BREAK;
     return;
@@ -1365,9 +1365,7 @@ k_cg_split2(SolveVecs<T> v, int npw, const int* __restrict__ act, int nsplit, co
 // norm in theta and updates the iteration count and the convergence flag
 template <typename T>
 __global__ void __launch_bounds__(NT)
-k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int nsplit, const T* __restrict__ part2,
-            ProjFeed<T> f) {
-  __shared__ T sm[16 * (NT / 64)];
+k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int nsplit, const T* __restrict__ part2) {
   const int sys = sys_of(act, blockIdx.y);
   if (v.flag[sys]) return;
   T rrn = T(0);
@@ -1377,39 +1375,7 @@ k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int ns
   slice_of<T>(npw, nsplit, i0, i1);
   cplx<T>* p = v.p + (long)sys * v.ld;
   const cplx<T>* r = v.r + (long)sys * v.ld;
-  T fa[16];
-  feed_zero(fa);
-  if (f.part) {
-    // the band values and the scaling are loaded before the store to p (the
-    // compiler may not move loads across it), so each step waits once
-    for (int i = i0 + threadIdx.x; i < i1; i += NT) {
-      const cplx<T> ri = r[i], pi = p[i];
-      cplx<T> ph[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) ph[u] = u < f.nv ? f.Phi[(long)u * f.ldphi + i] : cplx<T>{0, 0};
-      const T sc = f.pre ? f.pre[i] : T(1);
-      const cplx<T> pn = ri + beta * pi;
-      p[i] = pn;
-      const cplx<T> y = sc * pn;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        fa[2 * u] += ph[u].x * y.x + ph[u].y * y.y;
-        fa[2 * u + 1] += ph[u].x * y.y - ph[u].y * y.x;
-      }
-    }
-  } else {
-    for (int i = i0 + threadIdx.x; i < i1; i += NT) p[i] = r[i] + beta * p[i];
-  }
-  if (f.part) {
-    // the slice's projector sums of the new direction (each thread re-reads
-    // only what it wrote)
-    feed_store(f, 0, blockIdx.x, sys, fa, sm);
-    for (int v0 = 8; v0 < f.nv; v0 += 8) {
-      feed_zero(fa);
-      for (int i = i0 + threadIdx.x; i < i1; i += NT) feed_acc(f, v0, i, p[i], fa);
-      feed_store(f, v0, blockIdx.x, sys, fa, sm);
-    }
-  }
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) p[i] = r[i] + beta * p[i];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     v.theta[sys] = rrn;
     v.iters[sys] += 1;
@@ -1499,16 +1465,12 @@ k_cg_split2f(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int n
 
 template <typename T>
 void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
-                          hipStream_t s, const ProjFeed<T>& f, const T* dots, int ndots) {
+                          hipStream_t s) {
   if (nsys <= 0) return;
   const dim3 grid(nsplit, nsys);
-  if (dots) {
-    k_cg_split2<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, dots, ndots, part + (long)nsys * nsplit);
-  } else {
-    k_cg_split1<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part);
-    k_cg_split2<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part, nsplit, part + (long)nsys * nsplit);
-  }
-  k_cg_split3<T><<<grid, NT, 0, s>>>(v, npw, tol2, act, nsplit, part + (long)nsys * nsplit, f);
+  k_cg_split1<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part);
+  k_cg_split2<T><<<grid, NT, 0, s>>>(v, npw, act, nsplit, part, part + (long)nsys * nsplit);
+  k_cg_split3<T><<<grid, NT, 0, s>>>(v, npw, tol2, act, nsplit, part + (long)nsys * nsplit);
 }
 
 template <typename T>
@@ -1523,9 +1485,9 @@ template void launch_cg_step_fed<float>(const SolveVecs<float>&, int, float, con
                                         const float*, int, const ProjFeed<float>&, hipStream_t);
 
 template void launch_cg_step_split<double>(const SolveVecs<double>&, int, double, const int*, int, int, double*,
-                                           hipStream_t, const ProjFeed<double>&, const double*, int);
+                                           hipStream_t);
 template void launch_cg_step_split<float>(const SolveVecs<float>&, int, float, const int*, int, int, float*,
-                                          hipStream_t, const ProjFeed<float>&, const float*, int);
+                                          hipStream_t);
 }  // namespace lgw
 
 // ====================================================================

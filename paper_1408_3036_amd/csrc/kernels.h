@@ -24,8 +24,8 @@ struct ProjFeed {
   cplx<T>* part = nullptr;        // [nsplit][ntot][nv]
   int ntot = 0;                   // systems of the batch (stride of part)
   int nsplit = 1;
-  // Direction update in the first transform (single-precision CG, see
-  // launch_cg_step_fed): with r != null, part holds the slice sums of the
+  // Direction update in the first transform (small preconditioned CG
+  // batches, see launch_cg_step_fed): with r != null, part holds the slice sums of the
   // residual r, and while theta[sys] >= 0 the transform first sets
   // p = r + beta p (beta = theta / rr) and uses C = sum(part) + beta Cp;
   // its workgroup 0 leaves C in Cn (the last transform moves it to Cp).
@@ -225,12 +225,10 @@ void launch_conj(const z64* in, z64* out, long n, hipStream_t s);
 namespace lgw {
 // CG update spread over nsplit workgroups per system (small batches); part
 // needs 2 * nsys * nsplit entries
-// With dots != null the first phase is skipped: p^H A p is the sum of the
-// ndots partials per active slot in dots (CgDot, left by the transform).
 template <typename T>
 void launch_cg_step_split(const SolveVecs<T>& v, int npw, T tol2, const int* act, int nsys, int nsplit, T* part,
-                          hipStream_t s, const ProjFeed<T>& f = {}, const T* dots = nullptr, int ndots = 0);
-// The rest of a single-precision CG step when the transforms do the direction
+                          hipStream_t s);
+// The rest of a preconditioned small-batch CG step when the transforms do the direction
 // update (ProjFeed::r) and p^H A p (CgDot): x += alpha p, r -= alpha A p, the
 // slice sums of the new r for the next projection, and, by the last workgroup
 // of each system to finish (an atomic ticket on v.cnt), the new norm parked in

@@ -428,7 +428,7 @@ struct Batch {
   const T* pre = nullptr;      // preconditioner scaling or null
   cplx<T>* ptmp = nullptr;
   cplx<T>* fpart = nullptr;    // CG with a preconditioner: projector partial sums (ProjFeed)
-  T* dot_part = nullptr;       // single-precision CG with a preconditioner: p^H A p partials (CgDot)
+  T* dot_part = nullptr;       // CG with a preconditioner: p^H A p partials of the last transform (CgDot)
   cplx<T>* cp = nullptr;       // ... and the projector coefficients of the current and the next direction
   cplx<T>* cn = nullptr;
   std::vector<int> h_iters, h_flags;
@@ -476,14 +476,10 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   b.split_part = c->buf<T>(t + ".split", (size_t)2 * std::min(nsys, lgw_ctx::kTimedMin) * b.nsplit);
   b.fpart = b.pre && kind != K_SQMR && c->nv > 0 ? c->buf<cplx<T>>(t + ".fpart", (size_t)b.nsplit * nsys * c->nv)
                                                  : nullptr;
-  b.dot_part = b.fpart
-                   ? c->buf<T>(t + ".dots", (size_t)std::min(nsys, lgw_ctx::kTimedMin) * zcol_blocks(c->geom))
-                   : nullptr;
-  if (b.dot_part) {
+  if (b.fpart) {
+    b.dot_part = c->buf<T>(t + ".dots", (size_t)std::min(nsys, lgw_ctx::kTimedMin) * zcol_blocks(c->geom));
     b.cp = c->buf<cplx<T>>(t + ".cp", (size_t)nsys * c->nv);
     b.cn = c->buf<cplx<T>>(t + ".cn", (size_t)nsys * c->nv);
-  }
-  if (b.fpart) {
     // ticket counters of the fed CG kernels: zero here, and every ticketed
     // launch leaves them zero
     b.v.cnt = c->buf<int>(t + ".cnt", nsys);
@@ -517,11 +513,16 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   if (act.empty()) return;
   const int npw = c->npw;
   h2d_async(c, b.act, act.data(), act.size() * sizeof(int));
-  // Small preconditioned CG batches take the projector's dot products of the
-  // next direction from the CG kernels (initialisation and direction update),
-  // so each operator application starts with the projector's update alone.
-  // Decided once per run: the split kernels then serve every chunk.
+  // Small preconditioned CG batches: the CG kernels leave the projector's
+  // slice sums of the residual (of b at the initialisation), the first
+  // transform updates the direction and forms P S p from them (coefficients
+  // by C(p) = C(r) + beta C(p_old)), and the last one leaves p^H A p, so a
+  // step is the operator application plus one x/r launch.  In single
+  // precision that transform stores A p itself (S folded in); in double
+  // precision the outer projection follows it, and p^H S P Y = (P S p)^H Y
+  // takes the projected input it was given instead.  Decided once per run.
   ProjFeed<T> feed;
+  CgDot<T> cdot;
   const bool fed = b.fpart && (int)act.size() <= lgw_ctx::kTimedMin;
   if (fed) {
     feed.Phi = phi_of<T>(c);
@@ -531,15 +532,6 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     feed.part = b.fpart;
     feed.ntot = b.nsys;
     feed.nsplit = b.nsplit;
-  }
-  // ... and the first transform also updates the direction while the last
-  // one leaves p^H A p, so a step is the operator application plus one x/r
-  // launch.  In single precision that transform stores A p itself (S folded
-  // in); in double precision the outer projection follows it, and
-  // p^H S P Y = (P S p)^H Y takes the projected input it was given instead.
-  CgDot<T> cdot;
-  const bool tdots = fed && b.dot_part;
-  if (tdots) {
     feed.r = b.v.r;
     feed.p = b.v.p;
     feed.rr = b.v.rr;
@@ -613,7 +605,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     auto iterate = [&](int n_it) {
       for (int k = 0; k < n_it; ++k) {
         apply_op<T>(c, b.kind, b.v.p, b.v.Ap, b.tmp, b.Tb, b.ld, b.shift, b.w2, b.act, na, b.pre, b.ptmp,
-                    fed ? &feed : nullptr, tdots ? &cdot : nullptr);
+                    fed ? &feed : nullptr, fed ? &cdot : nullptr);
         hipEvent_t t0 = c->begin(na);
         if (b.kind == K_SQMR) {
           launch_sqmr_step<T>(b.v, npw, T(tol), b.act, na, c->stream);
@@ -621,11 +613,11 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
           c->end(t0, (sizeof(T) == 4 ? LGW_K_FP32 : 0) + LGW_K_SQMR, 2.0 * sizeof(T) * 11.0 * na * npw);
         } else if (na <= lgw_ctx::kTimedMin) {
           // small batch: spread each system over several workgroups
-          if (tdots)
+          if (fed)
             launch_cg_step_fed<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, b.dot_part, nblk, feed,
                                   c->stream);
           else
-            launch_cg_step_split<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, c->stream, feed);
+            launch_cg_step_split<T>(b.v, npw, T(tol * tol), b.act, na, b.nsplit, b.split_part, c->stream);
         } else {
           launch_cg_step<T>(b.v, npw, T(tol * tol), b.act, na, c->stream);
           // reads p, Ap (twice), x, r (twice), p; writes x, r, p
@@ -647,7 +639,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
           (uintptr_t)b.v.Ap, (uintptr_t)b.v.d, (uintptr_t)b.v.rr, (uintptr_t)b.v.bb, (uintptr_t)b.v.theta,
           (uintptr_t)b.v.rho, (uintptr_t)b.v.flag, (uintptr_t)b.v.iters, (uintptr_t)b.tmp, (uintptr_t)b.Tb,
           (uintptr_t)b.shift, (uintptr_t)b.w2, (uintptr_t)b.act, (uintptr_t)b.split_part, (uintptr_t)b.pre,
-          (uintptr_t)b.ptmp, (uintptr_t)b.fpart, (uintptr_t)fed, (uintptr_t)b.dot_part, (uintptr_t)tdots,
+          (uintptr_t)b.ptmp, (uintptr_t)b.fpart, (uintptr_t)fed, (uintptr_t)b.dot_part,
           (uintptr_t)b.cp, (uintptr_t)b.cn, (uintptr_t)b.v.cnt};
       auto f = c->graphs.find(key);
       if (f != c->graphs.end()) {
