@@ -1383,8 +1383,8 @@ k_cg_split3(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int ns
   }
 }
 
-// The x/r phase of a single-precision CG step whose direction update and
-// p^H A p are done by the transforms (launch_cg_step_fed).  The slice sums of
+// The x/r phase of a small preconditioned CG batch's step whose direction
+// update and p^H A p are done by the transforms (launch_cg_step_fed).  The slice sums of
 // conj(Phi_v) (pre .* r_new) are left for the next projection; the norm goes
 // through a ticket: each workgroup stores its slice norm, the last of the
 // system to take a ticket (all have read rr and the flag by then) sums them

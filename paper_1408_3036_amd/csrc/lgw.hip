@@ -381,13 +381,14 @@ void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
   proj<T>(c, Y, Y, ldy, act, nsys);
 }
 
-
 // Y = A X for the projected operator of the given kind (X is in range(P_c)).
-// With a preconditioner scaling S (pre != null): Y = S P A P S X, the product
-// S X staged in ptmp.  In single precision the outer P is left out and S is
+// With a preconditioner scaling S (pre != null): Y = S P A P S X, with P S X
+// staged in ptmp (formed by the first transform from the CG kernels' partial
+// sums when fed).  In single precision the outer P is left out and S is
 // applied by the transform's store: A maps range(P) into itself up to the
 // valence orbitals' eigen-residual (1e-13 relative at the workloads), far
 // below FP32 rounding, and the FP64 refinement projects every correction.
+// cd: the last transform also leaves p^H A p (CgDot).
 template <class T>
 void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, cplx<T>* Tb, long ld,
               const cplx<T>* shift, const T* w2, const int* act, int nsys, const T* pre = nullptr,
