@@ -95,21 +95,28 @@ __device__ __forceinline__ void feed_acc(const ProjFeed<T>& f, int v0, int i, cp
 // one half and adds its partner's copy of it: 8 + 4 + 2 + 1 shuffles leave one
 // value per lane, summed over 16 lanes; two more finish the wave); the waves'
 // totals meet in LDS.  Fixed order, so every call sums alike.
+// one halving exchange at lane distance 4H: lanes keep H values
+// (compile-time H, so that every index into acc is static)
+template <typename T, int H>
+__device__ __forceinline__ void feed_halve(T (&acc)[16], int lane, int& base) {
+  constexpr int O = 4 * H;
+  const bool up = (lane & O) != 0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const T send = up ? acc[j] : acc[j + H];
+    const T keep = up ? acc[j + H] : acc[j];
+    acc[j] = keep + __shfl_xor(send, O, 64);
+  }
+  base += up ? H : 0;
+}
 template <typename T>
 __device__ __forceinline__ void feed_store(const ProjFeed<T>& f, int v0, int k, int sys, T (&acc)[16], T* sm) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int base = 0;
-#pragma unroll
-  for (int o = 32, h = 8; h >= 1; o >>= 1, h >>= 1) {
-    const bool up = (lane & o) != 0;
-#pragma unroll
-    for (int j = 0; j < h; ++j) {
-      const T send = up ? acc[j] : acc[j + h];
-      const T keep = up ? acc[j + h] : acc[j];
-      acc[j] = keep + __shfl_xor(send, o, 64);
-    }
-    base += up ? h : 0;
-  }
+  feed_halve<T, 8>(acc, lane, base);
+  feed_halve<T, 4>(acc, lane, base);
+  feed_halve<T, 2>(acc, lane, base);
+  feed_halve<T, 1>(acc, lane, base);
   acc[0] += __shfl_xor(acc[0], 2, 64);
   acc[0] += __shfl_xor(acc[0], 1, 64);
   if ((lane & 3) == 0) sm[w * 16 + base] = acc[0];
