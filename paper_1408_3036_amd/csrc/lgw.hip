@@ -338,18 +338,18 @@ void upload(lgw_ctx* c, DevBuf& b, const std::vector<T>& h) {
 
 // y = (H - shift) x [+ ecoef E] for nsys systems (device per-system arrays).
 // With fed: x = P (fed->pre .* D) is formed by the first transform from the
-// direction D and the CG kernels' partial sums, and stored to X.
+// direction D and the CG kernels' partial sums, and stored to Xw (X == Xw).
 template <class T>
 void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const cplx<T>* shift,
             const cplx<T>* E, long lde, const T* ecoef, cplx<T>* Tb, const int* act, int nsys,
             const T* dout = nullptr, const ProjFeed<T>* fed = nullptr, const cplx<T>* D = nullptr,
-            const CgDot<T>* cd = nullptr) {
+            cplx<T>* Xw = nullptr, const CgDot<T>* cd = nullptr) {
   const long ldt = (long)c->N * c->ncols;
   const double e = 2.0 * sizeof(T);   // bytes of one complex value
   const double cols = (double)nsys * c->N * c->ncols, sph = (double)nsys * c->npw;
   hipEvent_t t0 = c->begin(nsys);
   if (fed)
-    launch_zinv_fed<T>(c->geom, tw_of<T>(c), *fed, D, const_cast<cplx<T>*>(X), ldx, Tb, ldt, act, nsys, c->stream);
+    launch_zinv_fed<T>(c->geom, tw_of<T>(c), *fed, D, Xw, ldx, Tb, ldt, act, nsys, c->stream);
   else
     launch_zinv<T>(c->geom, tw_of<T>(c), X, ldx, Tb, ldt, T(1), act, nsys, c->stream);
   const int pk = sizeof(T) == 4 ? LGW_K_FP32 : 0;
@@ -404,11 +404,11 @@ void apply_op(lgw_ctx* c, int kind, const cplx<T>* X, cplx<T>* Y, cplx<T>* tmp, 
   if (!D) fed = nullptr;
   const T* dout = fold ? pre : nullptr;
   if (kind == K_CGSQ) {
-    happly<T>(c, X, ld, tmp, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, nullptr, fed, D);
+    happly<T>(c, X, ld, tmp, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, nullptr, fed, D, ptmp);
     proj<T>(c, tmp, ld, act, nsys);
-    happly<T>(c, tmp, ld, Y, ld, shift, X, ld, w2, Tb, act, nsys, dout, nullptr, nullptr, cd);
+    happly<T>(c, tmp, ld, Y, ld, shift, X, ld, w2, Tb, act, nsys, dout, nullptr, nullptr, nullptr, cd);
   } else {
-    happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, dout, fed, D, cd);
+    happly<T>(c, X, ld, Y, ld, shift, nullptr, 0, nullptr, Tb, act, nsys, dout, fed, D, ptmp, cd);
   }
   if (!fold) proj<T>(c, Y, Y, ld, act, nsys, nullptr, pre);   // Y = S P Y (S = 1 without preconditioner)
 }
