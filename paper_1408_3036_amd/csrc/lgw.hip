@@ -558,8 +558,8 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   const int maxit = std::max(1, c->opts.max_iter);
   // Small, launch-bound batches replay their chunks as HIP graphs; their first
   // chunk is as long as the last solve of the same kind took (consecutive
-  // solves of a recursion need similar counts), then polls come every two
-  // iterations for a while, since a poll costs less than a few wasted ones.
+  // solves of a recursion need similar counts), then a poll follows every
+  // iteration for a while, since a poll costs less than a wasted iteration.
   const bool small = c->opts.use_graph && (int)act.size() <= lgw_ctx::kTimedMin && !c->time_all;
   int& hint = c->it_hint[{b.kind, (int)sizeof(T), std::min(pass, 3)}];
   std::vector<int> flags(b.nsys), iters(b.nsys);
@@ -600,7 +600,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     int chunk = std::min(check, maxit - it);
     if (small && hint > 0) {
       if (it == 0) chunk = std::min(hint, maxit);
-      else if (it < hint + check) chunk = std::min(2, maxit - it);
+      else if (it < hint + check) chunk = std::min(1, maxit - it);
     }
     const int na = (int)act.size();
     auto iterate = [&](int n_it) {
