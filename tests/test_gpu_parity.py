@@ -269,6 +269,41 @@ def _oracle_lanczos_loss(b, V, n_v, q0, k, zs):
     return olz.logdet_loss(lambda z, v: s.M(z, v), q0, k, zs)
 
 
+def test_lanczos_breaks_down_on_an_invariant_subspace():
+    """Degenerate case of the recursion (Sec. IV): with V_loc = 0 and one
+    valence plane wave, eps(0) - 1 is diagonal in plane waves, so a seed of two
+    plane waves spans an invariant subspace.  The band solves are exact (two
+    kinetic eigenvalues in each right-hand side), the recursion stops after two
+    steps, and the Ritz values are the closed-form eigenvalues of the free box
+    (the same case the oracle is pinned on)."""
+    from paper_1408_3036_amd import Lgw
+    from oracle import lindhard
+    L, N, ecut = 10.0, 16, 6.0
+    omega = L ** 3
+    r = L * np.stack(np.meshgrid(*[np.arange(N)] * 3, indexing="ij"), -1).reshape(-1, 3) / N
+
+    def pw(q):
+        return np.exp(1j * (2 * np.pi / L) * r @ np.asarray(q, float))
+    psi = (pw((0, 0, 0)) / np.sqrt(omega))[None, :]
+    lg = Lgw(L, N, ecut, torch.zeros((N, N, N), dtype=torch.float64), torch.from_numpy(psi), np.zeros(1),
+             tol=1e-13)
+    q1, q2 = (1, 0, 0), (0, 2, 1)
+    try:
+        a, be, Q, kd = lg.lanczos(torch.from_numpy(pw(q1) + 0.5 * pw(q2)), 6)
+    finally:
+        lg.close()
+    assert kd == 2
+    a, be = a.cpu().numpy(), be.cpu().numpy()
+    th = np.sort(np.linalg.eigvalsh(olz.tridiag(a, be)))
+    ref = []
+    for q in (q1, q2):
+        k = 2 * np.pi / L * np.linalg.norm(q)
+        v = 4 * np.pi * (1 - np.cos(k * L / 2)) / k ** 2
+        ref.append(-v * lindhard.eigenvalue(L, N, ecut, 1, q, 0.0).real)
+    print(f"breakdown: kd {kd}, beta {be}, Ritz {th}, closed form {np.sort(ref)}")
+    assert np.allclose(th, np.sort(ref), rtol=1e-10)
+
+
 def test_lanczos_loss_and_gradient(sysc1):
     w, b, s, lg = sysc1
     q0 = random_potentials(w.N, 1, 50)[0]
