@@ -229,7 +229,7 @@ lgw_status lgw_lanczos_recycle(lgw_ctx* ctx, const lgw_c128* q0, int k, int n_w,
 /* Loss of the Lanczos-projected dielectric matrix and its gradient:
  *   L = sum_z log det(I + E(z)),  E(z) = Q^H (eps(z) - 1) Q,
  * with Q the k Lanczos vectors of eps(0) - 1 from q0 (as lgw_lanczos: the
- * static basis of Sec. V reused for every frequency as in Sec. VI), so that
+ * static basis of Sec. IV reused for every frequency as in Sec. VI), so that
  * sum_k log(1 + theta_k(z)) over the eigenvalues of E(z).  Every z must be
  * i*w with w >= 0 (E Hermitian, I + E positive definite); otherwise EINVAL.
  *   loss   [1]   (follows opts.mem)

@@ -73,7 +73,7 @@ def logdet_loss(apply_Mz, q0: np.ndarray, k: int, z_list) -> float:
     """Scalar summary of the frequency-dependent dielectric matrix in the static
     basis: L = sum_z log det(I + E(z)) = sum_z sum_i log(1 + theta_i(z)), with
     E(z) = Q^H (eps(z) - 1) Q over the k Lanczos vectors of eps(0) - 1 from q0
-    (Sec. V basis, reused at every imaginary frequency as in Sec. VI).  E(z)
+    (Sec. IV basis, reused at every imaginary frequency as in Sec. VI).  E(z)
     is Hermitian on the imaginary axis and eps - 1 is positive semidefinite
     there, so I + E(z) is positive definite."""
     _, _, Q, _ = lanczos(lambda x: apply_Mz(0.0, x), q0, k)

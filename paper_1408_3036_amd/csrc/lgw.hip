@@ -1640,7 +1640,7 @@ lgw_status lanczos_start(lgw_ctx* c, const lgw_c128* q0, z64* Q) {
   return LGW_OK;
 }
 
-// Lanczos with full reorthogonalisation on eps(0) - 1 (Sec. V): from q_0 in
+// Lanczos with full reorthogonalisation on eps(0) - 1 (Sec. IV): from q_0 in
 // Q[0], for j < k: w = M q_j, alpha_j = Re <q_j, w>, w -= alpha_j q_j +
 // beta_{j-1} q_{j-1}, then classical Gram-Schmidt against q_0..q_j twice,
 // beta_j = |w|, q_{j+1} = w / beta_j.  Stops early when beta_j < 1e-14

@@ -264,7 +264,11 @@ def test_silane48_recycling_against_direct_projection():
     print(f"silane-48 recycling: lanczos+recycle {t_rec:.3f}s (lanczos alone {t_lz:.3f}s); "
           f"rel. deviation from direct projection: max {max(errs):.2e} "
           f"(w=0 {errs[0]:.1e}, w={ws[5]:.3f} {errs[5]:.1e}, w={ws[-1]:.2f} {errs[-1]:.1e})")
-    assert max(errs) < 0.1
+    # the recycled E(i w) is an approximation away from w = 0 (Sec. VI); its
+    # deviation from the direct projection measured 1.1e-3 at most at this
+    # workload, bounded here with a small margin
+    assert max(errs) < 2e-3
+    assert errs[0] < 1e-8
 
 
 def test_silane48_model_operator_against_oracle():
