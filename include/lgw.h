@@ -248,6 +248,27 @@ lgw_status lgw_lanczos_loss_vjp(lgw_ctx* ctx, const lgw_c128* q0, int k, int n_z
  *   x, y [n][npw] in the library's sphere order (lgw_sphere). */
 lgw_status lgw_hpsi(lgw_ctx* ctx, int n, lgw_c128 shift, const lgw_c128* x, lgw_c128* y);
 
+/* lgw_hpsi without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same y = (H - shift) x with the same kernels and
+ * precision as lgw_hpsi, its intermediates in a fixed 64 MiB device array of
+ * the library (one per device, held until the process ends) instead of the
+ * context's workspace.  No hipMalloc, hipFree or other allocating call is
+ * made.
+ *   x, y  device pointers [n][npw] (sphere order of lgw_sphere); the context
+ *         must use LGW_MEM_DEVICE, else LGW_EINVAL.
+ *   n     vectors.  Scratch needed, in 256-byte aligned parts: FP64
+ *         16 n + 16 n N ncols bytes; mixed precision 8 n + 8 n N ncols +
+ *         2 * 8 n npw bytes.  Above 64 MiB the call returns LGW_EINVAL,
+ *         launches nothing, and lgw_last_error states the largest n (at
+ *         silane size, 48^3 and 641 columns: 136 vectors in FP64).
+ * Asynchronous: the kernels are queued on the context's stream and y is
+ * complete when that stream reaches them; the call does not synchronise.
+ * Every call on one device shares that device's array (nothing in it needs to
+ * start at zero; the call writes everything it reads): calls that overlap on
+ * one device, from any context or stream, race on it. */
+lgw_status lgw_hpsi_noalloc(lgw_ctx* ctx, int n, lgw_c128 shift, const lgw_c128* x, lgw_c128* y);
+
 /* y = v^1/2 x on grid vectors [n][N^3] (truncated Coulomb square root). */
 lgw_status lgw_vhalf(lgw_ctx* ctx, int n, const lgw_c128* x, lgw_c128* y);
 

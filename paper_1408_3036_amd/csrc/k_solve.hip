@@ -549,6 +549,18 @@ k_cvt_64_32(const z64* __restrict__ in, z32* __restrict__ out, long n) {
     out[e] = cvt<float>(in[e]);
 }
 
+__global__ void __launch_bounds__(NT)
+k_cvt_32_64(const z32* __restrict__ in, z64* __restrict__ out, long n) {
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT)
+    out[e] = cvt<double>(in[e]);
+}
+
+template <class T>
+__global__ void __launch_bounds__(NT)
+k_fill(cplx<T>* __restrict__ p, cplx<T> v, long n) {
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) p[e] = v;
+}
+
 // x[sys] += scale[sys] * e[sys] (e in single precision)
 __global__ void __launch_bounds__(NT)
 k_cvt_32_64_axpy(const z32* __restrict__ e, z64* __restrict__ x, const double* __restrict__ scale,
@@ -707,6 +719,19 @@ void launch_finite_check(const double* x, long n, int* flag, hipStream_t s) {
 void launch_cvt_64_32(const z64* in, z32* out, long n, hipStream_t s) {
   k_cvt_64_32<<<blocks_for(n), NT, 0, s>>>(in, out, n);
 }
+
+void launch_cvt_32_64(const z32* in, z64* out, long n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cvt_32_64<<<blocks_for(n), NT, 0, s>>>(in, out, n);
+}
+
+template <class T>
+void launch_fill(cplx<T>* p, cplx<T> v, long n, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<T><<<blocks_for(n), NT, 0, s>>>(p, v, n);
+}
+template void launch_fill<double>(z64*, z64, long, hipStream_t);
+template void launch_fill<float>(z32*, z32, long, hipStream_t);
 
 void launch_cvt_32_64_axpy(const z32* e, z64* x, const double* scale, const int* act, long ld, int npw,
                            int nsys, hipStream_t s) {

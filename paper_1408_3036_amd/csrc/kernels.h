@@ -179,6 +179,10 @@ void launch_add(z64* y, const z64* a, const z64* b, long n, hipStream_t s);
 void launch_finite_check(const double* x, long n, int* flag, hipStream_t s);
 // mixed precision conversions
 void launch_cvt_64_32(const z64* in, z32* out, long n, hipStream_t s);
+void launch_cvt_32_64(const z32* in, z64* out, long n, hipStream_t s);
+// p[0..n) = v (a fill kernel: no memset node, so it can sit in a captured graph)
+template <class T>
+void launch_fill(cplx<T>* p, cplx<T> v, long n, hipStream_t s);
 void launch_cvt_32_64_axpy(const z32* e, z64* x, const double* scale, const int* sys_of_vec,
                            long ld, int npw, int nsys, hipStream_t s);
 

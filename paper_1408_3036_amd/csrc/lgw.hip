@@ -40,6 +40,17 @@
 
 using namespace lgw;
 
+// ---- device scratch of the no-allocation entry point (lgw_hpsi_noalloc) ----
+// The column intermediates of an H application (and, in single precision, the
+// converted operands) live in this fixed array instead of workspace the
+// library allocates.  Every device the library runs on holds its own copy
+// until the process ends.  Host code reaches it only through the address that
+// hipGetSymbolAddress returned on that device: the array's name is a host-side
+// stand-in, not a device address.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+
 namespace {
 
 struct Fail {
@@ -105,6 +116,7 @@ struct lgw_ctx {
   std::vector<double> st_res;
   long long tot_iters = 0, tot_h = 0;
   std::string err;
+  std::string scratch_err;   // why this device has no scratch address (lgw_hpsi_noalloc)
   bool ones_ready = false;
   // opt-in per-kernel timing with HIP events on the context stream
   bool prof = false;
@@ -1578,6 +1590,32 @@ lgw_status set_err(lgw_ctx* c, lgw_status st, const std::string& m) {
 
 thread_local std::string g_setup_err;
 
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;   // device -> address of its copy of scratch
+
+// Called by lgw_setup with the context's device current; once per device.
+hipError_t scratch_init(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr.count(dev)) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) g_scratch_ptr[dev] = static_cast<char*>(p);
+  return e;
+}
+
+char* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
+// bytes of scratch lgw_hpsi_noalloc needs for n vectors (256-byte aligned parts)
+size_t hpsi_noalloc_bytes(int precision, long n, long npw, long ldt) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  if (precision == LGW_FP64) return al(n * sizeof(z64)) + al(n * ldt * sizeof(z64));
+  return al(n * sizeof(z32)) + al(n * ldt * sizeof(z32)) + 2 * al(n * npw * sizeof(z32));
+}
+
 // Solve statistics gathered over several internal chi0 calls.
 struct SolveTally {
   std::vector<int> it, fl, sw;
@@ -2227,6 +2265,12 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
   try {
     c->opts = o;
     HIPCHK(hipGetDevice(&c->device));
+    {
+      // the no-allocation entry point's scratch on this device (once per device)
+      const hipError_t se = scratch_init(c->device);
+      if (se != hipSuccess)
+        c->scratch_err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(se);
+    }
     if (o.stream) c->stream = (hipStream_t)o.stream;
     else {
       HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
@@ -3223,6 +3267,62 @@ lgw_status lgw_hpsi(lgw_ctx* c, int n, lgw_c128 shift, const lgw_c128* x, lgw_c1
     c->check_launch();
     c->sync();
     finish_out(c, y, dy, bytes);
+    return LGW_OK;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_hpsi_noalloc(lgw_ctx* c, int n, lgw_c128 shift, const lgw_c128* x, lgw_c128* y) {
+  if (!c) return LGW_EINVAL;
+  if (n < 0 || (n > 0 && (!x || !y))) return set_err(c, LGW_EINVAL, "invalid arguments");
+  if (c->opts.mem != LGW_MEM_DEVICE)
+    return set_err(c, LGW_EINVAL, "lgw_hpsi_noalloc needs a device-memory context (opts.mem = LGW_MEM_DEVICE)");
+  if (n == 0) return LGW_OK;
+  const long npw = c->npw, ldt = (long)c->N * c->ncols;
+  const size_t need = hpsi_noalloc_bytes(c->opts.precision, n, npw, ldt);
+  if (need > kScratchBytes) {
+    long nmax = 0;
+    while (hpsi_noalloc_bytes(c->opts.precision, nmax + 1, npw, ldt) <= kScratchBytes) ++nmax;
+    return set_err(c, LGW_EINVAL, "lgw_hpsi_noalloc: " + std::to_string(n) + " vectors need " +
+                                      std::to_string(need) + " bytes of scratch; the fixed scratch holds " +
+                                      std::to_string(kScratchBytes) + " bytes (at most " + std::to_string(nmax) +
+                                      " vectors on this grid and precision)");
+  }
+  char* base = scratch_of(c->device);
+  if (!base)
+    return set_err(c, LGW_EDEVICE, c->scratch_err.empty() ? "no scratch address for this device" : c->scratch_err);
+  try {
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const z64* dx = reinterpret_cast<const z64*>(x);
+    z64* dy = reinterpret_cast<z64*>(y);
+    if (c->opts.precision == LGW_FP64) {
+      z64* sh = reinterpret_cast<z64*>(base);
+      z64* Tb = reinterpret_cast<z64*>(base + al(n * sizeof(z64)));
+      launch_fill<double>(sh, z64{shift.re, shift.im}, n, c->stream);
+      launch_zinv<double>(c->geom, tw_of<double>(c), dx, npw, Tb, ldt, 1.0, nullptr, n, c->stream);
+      launch_plane_hv<double>(c->geom, tw_of<double>(c), Tb, ldt, vt_of<double>(c), nullptr, n, c->stream);
+      launch_zfwd<double>(c->geom, tw_of<double>(c), Tb, ldt, 1.0 / (double)c->n3, dx, npw, sh, nullptr, 0,
+                          nullptr, dy, npw, nullptr, n, c->stream, nullptr, CgDot<double>{});
+    } else {
+      char* p = base;
+      z32* sh = reinterpret_cast<z32*>(p);
+      p += al(n * sizeof(z32));
+      z32* Tb = reinterpret_cast<z32*>(p);
+      p += al(n * ldt * sizeof(z32));
+      z32* x32 = reinterpret_cast<z32*>(p);
+      p += al(n * npw * sizeof(z32));
+      z32* y32 = reinterpret_cast<z32*>(p);
+      launch_fill<float>(sh, z32{(float)shift.re, (float)shift.im}, n, c->stream);
+      launch_cvt_64_32(dx, x32, (long)n * npw, c->stream);
+      launch_zinv<float>(c->geom, tw_of<float>(c), x32, npw, Tb, ldt, 1.0f, nullptr, n, c->stream);
+      launch_plane_hv<float>(c->geom, tw_of<float>(c), Tb, ldt, vt_of<float>(c), nullptr, n, c->stream);
+      launch_zfwd<float>(c->geom, tw_of<float>(c), Tb, ldt, (float)(1.0 / (double)c->n3), x32, npw, sh, nullptr,
+                         0, nullptr, y32, npw, nullptr, n, c->stream, nullptr, CgDot<float>{});
+      launch_cvt_32_64(y32, dy, (long)n * npw, c->stream);
+    }
+    c->check_launch();
+    c->tot_h += n;
     return LGW_OK;
   } catch (const Fail& f) {
     return set_err(c, f.st, f.msg);

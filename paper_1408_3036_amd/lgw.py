@@ -88,6 +88,7 @@ def load_library():
     lib.lgw_chi0_apply_many.argtypes = [I, C.POINTER(P), C.POINTER(I), C.POINTER(P), I,
                                         C.POINTER(c128), C.POINTER(P)]
     lib.lgw_hpsi.argtypes = [P, I, c128, P, P]
+    lib.lgw_hpsi_noalloc.argtypes = [P, I, c128, P, P]
     lib.lgw_vhalf.argtypes = [P, I, P, P]
     lib.lgw_get_info.argtypes = [P, C.POINTER(Info)]
     lib.lgw_sphere.argtypes = [P, C.POINTER(I)]
@@ -99,7 +100,7 @@ def load_library():
     lib.lgw_free.argtypes = [P]
     lib.lgw_free.restype = None
     for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_block_lanczos",
-                 "lgw_chi0_apply_many", "lgw_chi0_apply_vjp", "lgw_hpsi",
+                 "lgw_chi0_apply_many", "lgw_chi0_apply_vjp", "lgw_hpsi", "lgw_hpsi_noalloc",
                  "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats", "lgw_profile",
                  "lgw_kernel_timing"]:
         getattr(lib, name).restype = I
@@ -338,6 +339,18 @@ class Lgw:
         t.cuda.synchronize()
         self._check(self.lib.lgw_hpsi(self.ctx, x.shape[0], c128(shift.real, shift.imag),
                                       x.data_ptr(), y.data_ptr()))
+        return y
+
+    def hpsi_noalloc(self, x, y, shift: complex = 0.0):
+        """y = (H - shift) x into the caller's device tensor y through
+        lgw_hpsi_noalloc (no allocation in the library; asynchronous on the
+        context's stream: synchronise before reading y)."""
+        t = self.torch
+        assert x.is_cuda and y.is_cuda and x.dtype == t.complex128 and y.dtype == t.complex128
+        assert x.is_contiguous() and y.is_contiguous() and x.shape == y.shape and x.shape[-1] == self.npw
+        n = x.numel() // self.npw
+        self._check(self.lib.lgw_hpsi_noalloc(self.ctx, n, c128(shift.real, shift.imag),
+                                              x.data_ptr(), y.data_ptr()))
         return y
 
     def vhalf(self, x):

@@ -109,6 +109,10 @@ def make_workload(cfg: int, sys: int = 0, with_ground_state: bool = True,
     batch, see uneven_box_params); reseed until the gap is >= 1e-3 Ha."""
     p = dict(CONFIGS[cfg]) if cfg != 4 else uneven_box_params(sys)
     p.update(override)
+    # a box of the uneven batch whose drawn N_v would split a degenerate level
+    # (few wells: the upper states are the box's free-particle shells) takes
+    # the closed shell below it, the largest n <= N_v (n >= 2) with a gap
+    shell_down = cfg == 4 and "n_v" not in override
     for attempt in range(max_attempts):
         seed = (SEED_BASE, cfg, sys, attempt)
         rng = np.random.default_rng(list(seed))
@@ -118,6 +122,14 @@ def make_workload(cfg: int, sys: int = 0, with_ground_state: bool = True,
             from .ground_state import ground_state
             psi, eps, eps_all = ground_state(V, p["L"], p["ecut"], p["n_v"])
             gap = float(eps_all[p["n_v"]] - eps_all[p["n_v"] - 1])
+            if gap < 1e-3 and shell_down:
+                n = p["n_v"] - 1
+                while n >= 2 and eps_all[n] - eps_all[n - 1] < 1e-3:
+                    n -= 1
+                if n >= 2:
+                    p["n_v"] = n
+                    psi, eps = psi[:n].copy(), eps[:n].copy()
+                    gap = float(eps_all[n] - eps_all[n - 1])
             if gap < 1e-3:
                 continue
         return Workload(name=p["name"], L=p["L"], N=p["N"], ecut=p["ecut"], n_v=p["n_v"],

@@ -318,3 +318,80 @@ def test_large72_recycling_and_model():
     for k, z in enumerate(zs):
         for j in range(2):
             assert rel(dn[k, j], md.chi0(z, x[j])) < 1e-12
+
+
+def test_large72_block_lanczos_full_shape(tmp_path):
+    """The large-molecule workload at its stated shape: block Lanczos with
+    8-vector blocks to 256 vectors (32 block steps) on eps(0) - 1 at 72^3 with
+    16 valence bands, then E(z) = Q^H (eps(z) - 1) Q at the 32 imaginary
+    frequencies, in the mixed-precision multi-shift form: 256 columns x 32
+    frequencies x 16 bands.  Sampled against the oracle: the first block is
+    the orthonormalised seed block, which the oracle forms itself (QR of the
+    same synthetic seeds), so its rows and two of its columns of E(z) are
+    checked at two frequencies against the oracle's matrix-free chi0, in mixed
+    precision (1e-6) and, re-projected by an FP64 context, in FP64 (1e-10).
+    The rest is held to properties of the exact operator: Q orthonormal,
+    E(0) the block tridiagonal, E(i w) Hermitian positive semidefinite and
+    decreasing in w."""
+    from tests.oracle_pool import chi0_by_bands, save_box
+    w = make_workload(3)
+    b = Basis(w.L, w.N, w.ecut)
+    assert (b.npw, w.n_v, len(w.z)) == (38401, 16, 32)
+    zs = list(w.z)
+    seeds = random_potentials(w.N, 8, (14083036, 3, 0, 80))
+    mixed = _lgw(w, precision="mixed", tol=1e-10, multishift=True, **FAST)
+    try:
+        torch.cuda.synchronize()
+        t = time.time()
+        A, B, Q, nd = mixed.block_lanczos(torch.from_numpy(seeds), 32)
+        torch.cuda.synchronize()
+        t_l = time.time() - t
+        t = time.time()
+        E = mixed.project(Q, zs)
+        torch.cuda.synchronize()
+        t_p = time.time() - t
+        Q = Q.cpu().numpy()
+        E = E.cpu().numpy()
+        A, B = A.cpu().numpy(), B.cpu().numpy()
+    finally:
+        mixed.close()
+    print(f"large-72 block Lanczos 32 x 8 vectors: {t_l:.2f}s; E(z) at {len(zs)} z: {t_p:.2f}s "
+          f"({256 * (len(zs) - 1) / t_p:.0f} chi0 applies/s)", flush=True)
+    assert nd == 32 and Q.shape == (256, w.N ** 3)
+    G = Q.conj() @ Q.T
+    assert np.abs(G - np.eye(256)).max() < 1e-12
+    T = olz.block_tridiag(A, B)
+    assert np.abs(E[0] - T).max() < 1e-6 * np.abs(T).max()
+    prev = None
+    for i, z in enumerate(zs):
+        assert np.abs(E[i] - E[i].conj().T).max() < 1e-6 * np.abs(E[i]).max()
+        ev = np.linalg.eigvalsh(0.5 * (E[i] + E[i].conj().T))
+        assert ev.min() > -1e-6 * ev.max()
+        if prev is not None:       # eps(i w) - 1 decreases with w (Loewner order)
+            assert np.linalg.eigvalsh(0.5 * ((prev - E[i]) + (prev - E[i]).conj().T)).min() > -1e-6 * ev.max()
+        prev = E[i]
+    # oracle: its own first block from the same seeds, two columns at two z
+    Q0, _ = olz._qr_pos(seeds.T)
+    Q0 = Q0.T
+    assert colwise_rel(Q[:8], Q0) < 1e-12
+    pick_z = [0, 12]
+    pre = save_box(str(tmp_path), "c3", w.L, w.N, w.ecut, w.V, w.psi, w.eps)
+    t = time.time()
+    xv = [b.apply_vhalf(Q0[j]) for j in (0, 1)]
+    chi = chi0_by_bands([(pre, w.n_v, [zs[i] for i in pick_z], x) for x in xv])
+    print(f"large-72 oracle: {2 * len(pick_z) * w.n_v} band solves in {time.time() - t:.1f}s", flush=True)
+    ref = np.zeros((len(pick_z), 8, 2), dtype=np.complex128)
+    for j in range(2):
+        for k in range(len(pick_z)):
+            ref[k, :, j] = Q0.conj() @ (-b.apply_vhalf(chi[j][k]))
+    fp64 = _lgw(w, tol=1e-13, multishift=True, **FAST)
+    try:
+        E64 = fp64.project(torch.from_numpy(Q0), [zs[i] for i in pick_z]).cpu().numpy()
+    finally:
+        fp64.close()
+    for k, i in enumerate(pick_z):
+        em = rel(E[i][:8, :2], ref[k])
+        e64 = rel(E64[k][:, :2], ref[k])
+        print(f"large-72 E(z={zs[i]:.4f}) first block, 2 columns: mixed {em:.2e}, fp64 {e64:.2e}")
+        assert em < 1e-6
+        assert e64 < 1e-10
