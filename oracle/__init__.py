@@ -20,6 +20,12 @@ Contents (each function cites the passage of the paper it follows):
                     static basis (Sec. VI).
 * ``lindhard``    - closed-form chi0 of the free-electron box (V = 0), used to
                     pin the oracle.
+* ``sigma``       - the correlation self-energy pieces in the dielectric basis:
+                    the integrand traces sigma_N, sigma_N0 and the Lorentzian
+                    model term Sigma_A (Secs. II, III.B, IV) as sums over
+                    states and as traces with H inverted by linear solves,
+                    and the residue term Sigma_P from a real-frequency Lanczos
+                    recursion per pole (Sec. VI).
 
 Parity status: every function here is pinned by a test in tests/ against a
 closed form, an invariant or brute force; none is "parity unpinned".

@@ -60,8 +60,15 @@ def ground_state(V: np.ndarray, L: float, ecut: float, n_v: int, n_extra: int = 
         v0 = rng.standard_normal(npw) + 0j
         w, C = spla.eigsh(op, k=nev, which="SA", tol=1e-14, v0=v0,
                           ncv=max(4 * nev, 40), maxiter=100000)
-        order = np.argsort(w)
-        w, C = w[order], C[:, order]
+        # Rayleigh-Ritz on the converged subspace: for a complex operator the
+        # Krylov eigensolver's vectors within a degenerate level need not be
+        # orthogonal; an orthonormal basis of the subspace and the eigenvectors
+        # of H projected on it are
+        C, _ = np.linalg.qr(C)
+        HC = np.stack([matvec(C[:, i]) for i in range(nev)], axis=1)
+        Hs = C.conj().T @ HC
+        w, U = scipy.linalg.eigh(0.5 * (Hs + Hs.conj().T))
+        C = C @ U
     C = C[:, :n_v]
     grid = np.zeros((n_v, N ** 3), dtype=np.complex128)
     grid[:, idx] = C.T
