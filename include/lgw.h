@@ -248,6 +248,46 @@ lgw_status lgw_lanczos_loss_vjp(lgw_ctx* ctx, const lgw_c128* q0, int k, int n_z
  *   x, y [n][npw] in the library's sphere order (lgw_sphere). */
 lgw_status lgw_hpsi(lgw_ctx* ctx, int n, lgw_c128 shift, const lgw_c128* x, lgw_c128* y);
 
+/* Correlation self-energy of state e in the dielectric basis Q (Secs. II,
+ * III.B and IV; the integrand of Eq. (e_c) and its Lorentzian-model terms).
+ * With s = eps_e + delta, the pair operator K = v^1/2 Phi_e f(H) Phi_e^+ v^1/2
+ * (Phi_e: multiplication by psi_e) and eps^-1 - 1 inverted within span(Q),
+ * W(z) = (I + E(z))^-1 - I with E(z) = Q^H (eps(z) - 1) Q:
+ *   sigma_N[i]  = Re tr[W(i w_i) K_i],  f(x) = (x - s) / ((x - s)^2 + w_i^2)
+ *                 (Eqs. (ge), (kge); every w from one shift-Lanczos
+ *                 recursion of H per basis vector, Sec. VI),
+ *   sigma_N0[i] = a^2 / (w_i^2 + a^2) Re tr[W(0) K_i]          (Eq. (g0e)),
+ *   sigma_A     = Re tr[W(0) K_A],  f(x) = (a/2) / (x - s + a sgn(x - s)),
+ *                 0 at x = s (Eqs. (he), (khe): the conduction states by
+ *                 (H - s + a) y = P_c g on the conduction space, the valence
+ *                 states by their energies).
+ * The correlation energy of Eq. (e_c) is then
+ * (1/pi) sum_i wt_i (sigma_N[i] - sigma_N0[i]) + sigma_A + Sigma_P for the
+ * caller's quadrature (w_i, wt_i) of the half line.
+ *   e      index of a valence state (0 .. n_v - 1); s must lie below every
+ *          conduction state (not checked: the library knows only the
+ *          valence set).
+ *   alpha  Lorentzian width a > 0 (the paper uses 1 Ha).
+ *   Q      [k][N^3] orthonormal basis (opts.mem layout), e.g. from lgw_lanczos.
+ *   w      [n_w] imaginary frequencies > 0, host.  sigma_N, sigma_N0 [n_w]
+ *          and sigma_A [1] are host memory.
+ * FP64 throughout (whatever opts.precision for the resolvents of H; E(z)
+ * follows the context's solver options); LGW_EINVAL for the model operator
+ * (opts.model = 1) or invalid arguments; LGW_EBREAKDOWN if I + E(i w) is
+ * not positive definite. */
+lgw_status lgw_sigma_traces(lgw_ctx* ctx, int e, double delta, double alpha, int k, const lgw_c128* Q,
+                            int n_w, const double* w, double* sigma_N, double* sigma_N0, double* sigma_A);
+
+/* Residue term Sigma_P of Eq. (pe) for state e (Sec. VI): for every valence
+ * state v with w_v = eps_v - s > 0 (weight 1; weight 1/2 at w_v = 0,
+ * Theta(0) = 1/2), the element <ev*| v^1/2 (eps^-1(w_v) - 1) v^1/2 |v*e> at
+ * the real frequency w_v (no broadening) from k_p Lanczos steps on
+ * eps(w_v) - 1 seeded with v^1/2 |v*e>: dV |p|^2 [(I + T)^-1 - I]_00.
+ *   Sigma_P = - sum_v weight_v element_v.
+ * Conduction poles (states below s) are not included: s must lie below the
+ * conduction band.  sigma_P [1] and n_poles [1] (or NULL) are host memory. */
+lgw_status lgw_sigma_residues(lgw_ctx* ctx, int e, double delta, int k_p, double* sigma_P, int* n_poles);
+
 /* lgw_hpsi without any allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc): the same y = (H - shift) x with the same kernels and

@@ -555,6 +555,11 @@ k_cvt_32_64(const z32* __restrict__ in, z64* __restrict__ out, long n) {
     out[e] = cvt<double>(in[e]);
 }
 
+__global__ void __launch_bounds__(NT)
+k_mul(z64* __restrict__ y, const z64* __restrict__ a, const z64* __restrict__ b, long n) {
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) y[e] = a[e] * b[e];
+}
+
 template <class T>
 __global__ void __launch_bounds__(NT)
 k_fill(cplx<T>* __restrict__ p, cplx<T> v, long n) {
@@ -723,6 +728,11 @@ void launch_cvt_64_32(const z64* in, z32* out, long n, hipStream_t s) {
 void launch_cvt_32_64(const z32* in, z64* out, long n, hipStream_t s) {
   if (n <= 0) return;
   k_cvt_32_64<<<blocks_for(n), NT, 0, s>>>(in, out, n);
+}
+
+void launch_mul(z64* y, const z64* a, const z64* b, long n, hipStream_t s) {
+  if (n <= 0) return;
+  k_mul<<<blocks_for(n), NT, 0, s>>>(y, a, b, n);
 }
 
 template <class T>

@@ -175,6 +175,8 @@ void launch_norm(const z64* w, long n, double* out, z64* partial, hipStream_t s)
 void launch_scale_into(const z64* w, const double* nrm, z64* q, long n, hipStream_t s);
 void launch_axpby(z64* y, const z64* x, z64 a, z64 b, long n, hipStream_t s);
 void launch_add(z64* y, const z64* a, const z64* b, long n, hipStream_t s);
+// y = a .* b (elementwise)
+void launch_mul(z64* y, const z64* a, const z64* b, long n, hipStream_t s);
 // any non-finite value -> *flag = 1
 void launch_finite_check(const double* x, long n, int* flag, hipStream_t s);
 // mixed precision conversions

@@ -117,6 +117,11 @@ struct lgw_ctx {
   long long tot_iters = 0, tot_h = 0;
   std::string err;
   std::string scratch_err;   // why this device has no scratch address (lgw_hpsi_noalloc)
+  // the self-energy's resolvents of H run without the conduction projector
+  // (every proj() is then the identity; set only by a scope guard)
+  bool no_proj = false;
+  // frequency of the operator eps(z) - 1 of the Lanczos recursion (0: static)
+  z64 lz_z{0.0, 0.0};
   bool ones_ready = false;
   // opt-in per-kernel timing with HIP events on the context stream
   bool prof = false;
@@ -380,6 +385,11 @@ void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const 
 template <class T>
 void proj(lgw_ctx* c, const cplx<T>* X, cplx<T>* Y, long ldy, const int* act, int nsys, const T* dpre = nullptr,
           const T* dpost = nullptr) {
+  if (c->no_proj) {
+    // only the unscaled in-place form occurs there (no preconditioner)
+    if (X != Y || dpre || dpost) throw Fail{LGW_EINVAL, "internal: scaled projection without a projector"};
+    return;
+  }
   const int ks = proj_ksplit<T>(c->npw, nsys);
   cplx<T>* part = c->buf<cplx<T>>(sizeof(T) == 8 ? "proj.part64" : "proj.part32", (size_t)ks * nsys * c->nv);
   hipEvent_t t0 = c->begin(nsys);
@@ -932,7 +942,9 @@ lgw_status worst(lgw_status a, lgw_status b);
 // residual |b - (A - tau) x_tau| = beta_k |e_k^T y_tau|.  A system stops when
 // that bound is below tol for all its shifts; every x_tau is then checked by
 // its true residual, and any above tol is corrected by the shifted solver.
-lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128* zl, z64* F) {
+// base (or null): the shift of system p is base[p] instead of e_v.
+lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128* zl, z64* F,
+                      const double* base = nullptr) {
   const int npw = c->npw, nv = c->nv;
   const long ldt = (long)c->N * c->ncols;
   const double tol = c->opts.tol;
@@ -981,7 +993,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     std::vector<z64> sh(n);
     for (int s = 0; s < n; ++s) {
       idx[s] = s0 + s;
-      sh[s] = z64{c->eps[(s0 + s) % nv], 0.0};
+      sh[s] = z64{base ? base[s0 + s] : c->eps[(s0 + s) % nv], 0.0};
     }
     h2d_async(c, d_idx, idx.data(), n * sizeof(int));
     h2d_async(c, d_sh, sh.data(), n * sizeof(z64));
@@ -1639,13 +1651,14 @@ struct SolveTally {
   }
 };
 
-// w = (eps(0) - 1) q = -v^1/2 chi0(0) v^1/2 q on plane-major grids
+// w = (eps(z) - 1) q = -v^1/2 chi0(z) v^1/2 q on plane-major grids, z = c->lz_z
+// (the static operator unless a real-frequency recursion set it)
 lgw_status apply_M0(lgw_ctx* c, const z64* q, z64* w, SolveTally& tally) {
   const long n3 = c->n3;
   z64* x1 = c->buf<z64>("lz.x1", n3);
   HIPCHK(hipMemcpyAsync(x1, q, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
   vhalf_inplace(c, x1, 1, 1.0);
-  const lgw_c128 z0{0.0, 0.0};
+  const lgw_c128 z0{c->lz_z.x, c->lz_z.y};
   c->tot_iters = c->tot_h = 0;
   const lgw_status st = chi0_internal(c, 1, x1, 1, &z0, w, n3);
   tally.add(c);
@@ -2166,6 +2179,72 @@ void recycle_E(lgw_ctx* c, int m, const z64* Bk, const z64* Fk, int n_w, const d
 }  // namespace
 
 // ======================================================================= ABI
+namespace {
+
+// E[z][a][b] = <q_a, (eps(z) - 1) q_b> (host, row-major) for the plane-major
+// basis Qz [k][N^3] on the device.
+lgw_status project_internal(lgw_ctx* c, int k, const z64* Qz, int n_z, const lgw_c128* z, std::vector<z64>& e) {
+  const long n3 = c->n3;
+  z64* X = c->buf<z64>("pj.X", (size_t)k * n3);
+  HIPCHK(hipMemcpyAsync(X, Qz, (size_t)k * n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+  vhalf_inplace(c, X, k, 1.0);
+  z64* D = c->buf<z64>("pj.D", (size_t)n_z * k * n3);
+  c->tot_iters = c->tot_h = 0;
+  lgw_status st = chi0_internal(c, k, X, n_z, z, D, (long)k * n3);
+  vhalf_inplace(c, D, n_z * k, -1.0);
+  z64* Et = c->buf<z64>("pj.E", (size_t)n_z * k * k);
+  z64* part = c->buf<z64>("pj.part", (size_t)gemm_hn_slices(n3, n_z * k) * std::min(k, 64) * n_z * k);
+  launch_gemm_hn_mfma(Qz, n3, k, D, n3, n_z * k, n3, Et, part, c->stream);   // Et[z * k + b][a]
+  c->check_launch();
+  std::vector<z64> h((size_t)n_z * k * k);
+  HIPCHK(hipMemcpyAsync(h.data(), Et, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+  c->sync();
+  // Et[z][b][a] = <q_a, M q_b>  ->  E[z][a][b]
+  e.assign(h.size(), z64{0, 0});
+  for (int i = 0; i < n_z; ++i)
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) e[((size_t)i * k + a) * k + b] = h[((size_t)i * k + b) * k + a];
+  return st;
+}
+
+// Scope of the self-energy's resolvents of H: FP64, no preconditioner and
+// no conduction projector; graphs captured with the other settings are
+// dropped on entry and those captured inside on exit.
+struct ResolventScope {
+  lgw_ctx* c;
+  lgw_opts saved;
+  explicit ResolventScope(lgw_ctx* cc) : c(cc), saved(cc->opts) {
+    c->drop_graphs();
+    c->opts.precision = LGW_FP64;
+    c->opts.precond = 0;
+    c->no_proj = true;
+  }
+  ~ResolventScope() {
+    c->drop_graphs();
+    c->no_proj = false;
+    c->opts = saved;
+  }
+};
+
+// Re tr(A B) for k x k row-major matrices
+double re_trace_prod(const std::vector<z64>& A, const std::vector<z64>& B, int k) {
+  double t = 0.0;
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < k; ++b) {
+      const z64 x = A[(size_t)a * k + b], y = B[(size_t)b * k + a];
+      t += x.x * y.x - x.y * y.y;
+    }
+  return t;
+}
+
+// F_ne of the Lorentzian model: (1/2) a / (w + a sgn w), 0 at w = 0
+double lorentz_F(double w, double a) {
+  if (std::abs(w) <= 1e-12) return 0.0;
+  return 0.5 * a / (w + (w > 0 ? a : -a));
+}
+
+}  // namespace
+
 extern "C" {
 
 void lgw_default_opts(lgw_opts* o) {
@@ -3141,26 +3220,9 @@ lgw_status lgw_project(lgw_ctx* c, int k, const lgw_c128* Q, int n_z, const lgw_
     const long n3 = c->n3;
     const z64* dQ = static_cast<const z64*>(stage_in(c, Q, (size_t)k * n3 * sizeof(z64), "io.Qin"));
     z64* Qz = c->buf<z64>("pj.Q", (size_t)k * n3);
-    z64* X = c->buf<z64>("pj.X", (size_t)k * n3);
     launch_xyz_to_zxy(c->N, dQ, n3, Qz, n3, k, false, c->stream);
-    HIPCHK(hipMemcpyAsync(X, Qz, (size_t)k * n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
-    vhalf_inplace(c, X, k, 1.0);
-    z64* D = c->buf<z64>("pj.D", (size_t)n_z * k * n3);
-    c->tot_iters = c->tot_h = 0;
-    lgw_status st = chi0_internal(c, k, X, n_z, z, D, (long)k * n3);
-    vhalf_inplace(c, D, n_z * k, -1.0);
-    z64* Et = c->buf<z64>("pj.E", (size_t)n_z * k * k);
-    z64* part = c->buf<z64>("pj.part", (size_t)gemm_hn_slices(n3, n_z * k) * std::min(k, 64) * n_z * k);
-    launch_gemm_hn_mfma(Qz, n3, k, D, n3, n_z * k, n3, Et, part, c->stream);   // Et[z * k + b][a]
-    c->check_launch();
-    std::vector<z64> h((size_t)n_z * k * k);
-    HIPCHK(hipMemcpyAsync(h.data(), Et, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
-    c->sync();
-    // Et[z][b][a] = <q_a, M q_b>  ->  E[z][a][b]
-    std::vector<z64> e(h.size());
-    for (int i = 0; i < n_z; ++i)
-      for (int a = 0; a < k; ++a)
-        for (int b = 0; b < k; ++b) e[((size_t)i * k + a) * k + b] = h[((size_t)i * k + b) * k + a];
+    std::vector<z64> e;
+    const lgw_status st = project_internal(c, k, Qz, n_z, z, e);
     if (c->opts.mem == LGW_MEM_DEVICE)
       h2d(c, E, e.data(), e.size() * sizeof(z64));
     else
@@ -3169,6 +3231,181 @@ lgw_status lgw_project(lgw_ctx* c, int k, const lgw_c128* Q, int n_z, const lgw_
     if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
     return st;
   } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_sigma_traces(lgw_ctx* c, int e, double delta, double alpha, int k, const lgw_c128* Q, int n_w,
+                            const double* w, double* sigma_N, double* sigma_N0, double* sigma_A) {
+  if (!c) return LGW_EINVAL;
+  if (e < 0 || e >= c->nv) return set_err(c, LGW_EINVAL, "e must index a valence state (0 .. n_v - 1)");
+  if (!std::isfinite(delta)) return set_err(c, LGW_ENAN, "non-finite delta");
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return set_err(c, LGW_EINVAL, "alpha must be positive");
+  if (k < 1 || !Q || n_w < 0 || !sigma_A || (n_w > 0 && (!w || !sigma_N || !sigma_N0)))
+    return set_err(c, LGW_EINVAL, "invalid arguments");
+  for (int i = 0; i < n_w; ++i)
+    if (!(w[i] > 0.0) || !std::isfinite(w[i])) return set_err(c, LGW_EINVAL, "frequencies must be positive");
+  if (c->opts.model == 1) return set_err(c, LGW_EINVAL, "the self-energy traces need the exact operator (model = 0)");
+  try {
+    const long n3 = c->n3;
+    const int npw = c->npw, nv = c->nv;
+    const double s = c->eps[e] + delta;
+    const z64* dQ = static_cast<const z64*>(stage_in(c, Q, (size_t)k * n3 * sizeof(z64), "io.Qin"));
+    z64* Qz = c->buf<z64>("sg.Q", (size_t)k * n3);
+    launch_xyz_to_zxy(c->N, dQ, n3, Qz, n3, k, false, c->stream);
+    // W(z) = (I + E(z))^-1 - I at z = 0 and every i w (Sec. IV: eps inverted in the basis)
+    std::vector<lgw_c128> zl(1 + n_w, lgw_c128{0.0, 0.0});
+    for (int i = 0; i < n_w; ++i) zl[1 + i] = lgw_c128{0.0, w[i]};
+    std::vector<z64> E;
+    lgw_status st = project_internal(c, k, Qz, 1 + n_w, zl.data(), E);
+    std::vector<std::vector<z64>> W(1 + n_w);
+    for (int i = 0; i <= n_w; ++i) {
+      std::vector<z64> C((size_t)k * k);
+      for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) {
+          const z64 x = E[((size_t)i * k + a) * k + b], y = E[((size_t)i * k + b) * k + a];
+          C[(size_t)a * k + b] = z64{0.5 * (x.x + y.x) + (a == b ? 1.0 : 0.0), 0.5 * (x.y - y.y)};
+        }
+      double ld = 0.0;
+      if (!hpd_logdet_inverse(C, k, ld, W[i])) throw Fail{LGW_EBREAKDOWN, "I + E(i w) is not positive definite"};
+      for (int a = 0; a < k; ++a) W[i][(size_t)a * k + a].x -= 1.0;
+    }
+    // right-hand sides g_l = Gather(conj(psi_e) v^1/2 q_l) (Eq. (kge))
+    z64* X = c->buf<z64>("sg.X", (size_t)k * n3);
+    HIPCHK(hipMemcpyAsync(X, Qz, (size_t)k * n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+    vhalf_inplace(c, X, k, 1.0);
+    z64* G = c->buf<z64>("sg.G", (size_t)k * npw);
+    gather_products(c, c->d_u.as<z64>() + (size_t)e * n3, 1, X, k, G, 1.0);
+    const double idv = 1.0 / c->dV;
+    // K(i w)[l'][l] = (1/dV) g_l'^H (H - s)((H - s)^2 + w^2)^-1 g_l: all w from one
+    // shift-Lanczos recursion per column (Sec. VI), shifts s -+ i w, no projector
+    std::vector<std::vector<z64>> K(n_w);
+    if (n_w > 0) {
+      z64* F = c->buf<z64>("sg.F", (size_t)n_w * k * npw);   // F[i][l] = 2 (H - s)((H - s)^2 + w_i^2)^-1 g_l
+      {
+        ResolventScope scope(c);
+        std::vector<double> base(k, s);
+        std::vector<lgw_c128> zw(n_w);
+        for (int i = 0; i < n_w; ++i) zw[i] = lgw_c128{0.0, w[i]};
+        st = worst(st, multishift(c, G, k, n_w, zw.data(), F, base.data()));
+      }
+      z64* Ct = c->buf<z64>("sg.Ct", (size_t)n_w * k * k);
+      z64* part = c->buf<z64>("sg.part", (size_t)gemm_hn_slices(npw, n_w * k) * std::min(k, 64) * n_w * k);
+      launch_gemm_hn_mfma(G, npw, k, F, npw, n_w * k, npw, Ct, part, c->stream);   // Ct[i k + l][l'] = g_l'^H F[i][l]
+      c->check_launch();
+      std::vector<z64> h((size_t)n_w * k * k);
+      HIPCHK(hipMemcpyAsync(h.data(), Ct, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      for (int i = 0; i < n_w; ++i) {
+        K[i].assign((size_t)k * k, z64{0, 0});
+        for (int l = 0; l < k; ++l)
+          for (int lp = 0; lp < k; ++lp) K[i][(size_t)lp * k + l] = (0.5 * idv) * h[((size_t)i * k + l) * k + lp];
+      }
+    }
+    // Sigma_A (Eqs. (he), (khe)): the conduction states, all above s, through
+    // (H - s + a) y = P_c g on the conduction space; each valence state v
+    // through its weight F(e_v - s) on the valence block
+    std::vector<z64> KA((size_t)k * k, z64{0, 0});
+    {
+      z64* PG = c->buf<z64>("sg.PG", (size_t)k * npw);
+      HIPCHK(hipMemcpyAsync(PG, G, (size_t)k * npw * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
+      proj<double>(c, PG, npw, nullptr, k);
+      std::vector<int> bidx(k);
+      for (int l = 0; l < k; ++l) bidx[l] = l;
+      std::vector<z64> sh(k, z64{s - alpha, 0.0});
+      z64* YA = c->buf<z64>("sg.YA", (size_t)k * npw);
+      SolveOut so;
+      c->tot_iters = c->tot_h = 0;
+      solve(c, K_CGLIN, PG, bidx, sh, {}, YA, so);
+      for (int l = 0; l < k; ++l) {
+        if (so.flags[l] == FLAG_BREAK) st = worst(st, LGW_EBREAKDOWN);
+        else if (so.flags[l] != FLAG_CONV) st = worst(st, LGW_ENOCONV);
+      }
+      z64* Ct = c->buf<z64>("sg.CA", (size_t)k * k + (size_t)k * nv);
+      z64* part = c->buf<z64>("sg.partA", (size_t)64 * k * std::max(k, nv) + 64);
+      launch_gemm_hn(G, npw, k, YA, npw, k, npw, Ct, part, c->stream);                          // [l][l'] = g_l'^H y_l
+      launch_gemm_hn(c->d_Phi.as<z64>(), npw, nv, G, npw, k, npw, Ct + (size_t)k * k, part, c->stream);   // [l][v] = u_v^H g_l
+      c->check_launch();
+      std::vector<z64> h((size_t)k * k + (size_t)k * nv);
+      HIPCHK(hipMemcpyAsync(h.data(), Ct, h.size() * sizeof(z64), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      const z64* cm = h.data() + (size_t)k * k;
+      std::vector<double> Fv(nv);
+      for (int v = 0; v < nv; ++v) Fv[v] = lorentz_F(c->eps[v] - s, alpha);
+      for (int lp = 0; lp < k; ++lp)
+        for (int l = 0; l < k; ++l) {
+          z64 acc = (0.5 * alpha) * h[(size_t)l * k + lp];
+          for (int v = 0; v < nv; ++v) acc = acc + Fv[v] * cmulc(cm[(size_t)lp * nv + v], cm[(size_t)l * nv + v]);
+          KA[(size_t)lp * k + l] = idv * acc;
+        }
+    }
+    for (int i = 0; i < n_w; ++i) {
+      sigma_N[i] = re_trace_prod(W[1 + i], K[i], k);
+      sigma_N0[i] = alpha * alpha / (w[i] * w[i] + alpha * alpha) * re_trace_prod(W[0], K[i], k);
+    }
+    *sigma_A = re_trace_prod(W[0], KA, k);
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_sigma_residues(lgw_ctx* c, int e, double delta, int k_p, double* sigma_P, int* n_poles) {
+  if (!c) return LGW_EINVAL;
+  if (e < 0 || e >= c->nv) return set_err(c, LGW_EINVAL, "e must index a valence state (0 .. n_v - 1)");
+  if (!std::isfinite(delta)) return set_err(c, LGW_ENAN, "non-finite delta");
+  if (k_p < 1 || !sigma_P) return set_err(c, LGW_EINVAL, "invalid arguments");
+  if (c->opts.model == 1) return set_err(c, LGW_EINVAL, "the residues need the exact operator (model = 0)");
+  try {
+    const long n3 = c->n3;
+    const double s = c->eps[e] + delta;
+    struct FreqScope {
+      lgw_ctx* c;
+      ~FreqScope() { c->lz_z = z64{0.0, 0.0}; }
+    } fscope{c};
+    double total = 0.0;
+    int np = 0;
+    lgw_status st = LGW_OK;
+    z64* Qd = c->buf<z64>("sp.Q", (size_t)k_p * n3);
+    double* ab = c->buf<double>("sp.ab", 2 * (size_t)k_p);
+    z64* pv = c->buf<z64>("sp.p", n3);
+    z64* part = c->buf<z64>("sp.part", 64);
+    double* d_nrm = c->buf<double>("sp.nrm", 1);
+    for (int v = 0; v < c->nv; ++v) {
+      // poles of Eq. (pe): valence states above s, half weight on s (Theta(0) = 1/2)
+      const double om = c->eps[v] - s;
+      const double th = om > 1e-12 ? 1.0 : (om >= -1e-12 ? 0.5 : 0.0);
+      if (th == 0.0) continue;
+      ++np;
+      // seed v^1/2 |v* e>: conj(psi_v) psi_e on the grid, then v^1/2
+      launch_mul(pv, c->d_u.as<z64>() + (size_t)v * n3, c->d_psi.as<z64>() + (size_t)e * n3, n3, c->stream);
+      vhalf_inplace(c, pv, 1, 1.0);
+      launch_norm(pv, n3, d_nrm, part, c->stream);
+      double nrm = 0.0;
+      HIPCHK(hipMemcpyAsync(&nrm, d_nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      if (!(nrm > 0.0)) continue;   // a vanishing pair function has no residue
+      launch_scale_into(pv, d_nrm, Qd, n3, c->stream);
+      // Lanczos on eps(om) - 1 at the real frequency om (no broadening)
+      c->lz_z = z64{th == 1.0 ? om : 0.0, 0.0};
+      int done = 0;
+      st = worst(st, lanczos_core(c, k_p, Qd, nullptr, ab, ab + k_p, &done));
+      std::vector<double> h(2 * (size_t)k_p);
+      HIPCHK(hipMemcpyAsync(h.data(), ab, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+      // |p|^2 dV [(I + T)^-1]_00 - |p|^2 dV: (T + 1) y = e_1
+      std::vector<z64> y(done);
+      tri_shift_solve(h.data(), h.data() + k_p, done, z64{-1.0, 0.0}, 1.0, y.data());
+      const double elem = c->dV * nrm * nrm * (y[0].x - 1.0);
+      total -= th * elem;
+    }
+    *sigma_P = total;
+    if (n_poles) *n_poles = np;
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    c->lz_z = z64{0.0, 0.0};
     return set_err(c, f.st, f.msg);
   }
 }

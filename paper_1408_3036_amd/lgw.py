@@ -89,6 +89,8 @@ def load_library():
                                         C.POINTER(c128), C.POINTER(P)]
     lib.lgw_hpsi.argtypes = [P, I, c128, P, P]
     lib.lgw_hpsi_noalloc.argtypes = [P, I, c128, P, P]
+    lib.lgw_sigma_traces.argtypes = [P, I, C.c_double, C.c_double, I, P, I, P, P, P, P]
+    lib.lgw_sigma_residues.argtypes = [P, I, C.c_double, I, P, P]
     lib.lgw_vhalf.argtypes = [P, I, P, P]
     lib.lgw_get_info.argtypes = [P, C.POINTER(Info)]
     lib.lgw_sphere.argtypes = [P, C.POINTER(I)]
@@ -101,6 +103,7 @@ def load_library():
     lib.lgw_free.restype = None
     for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_block_lanczos",
                  "lgw_chi0_apply_many", "lgw_chi0_apply_vjp", "lgw_hpsi", "lgw_hpsi_noalloc",
+                 "lgw_sigma_traces", "lgw_sigma_residues",
                  "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats", "lgw_profile",
                  "lgw_kernel_timing"]:
         getattr(lib, name).restype = I
@@ -340,6 +343,30 @@ class Lgw:
         self._check(self.lib.lgw_hpsi(self.ctx, x.shape[0], c128(shift.real, shift.imag),
                                       x.data_ptr(), y.data_ptr()))
         return y
+
+    def sigma_traces(self, e: int, delta: float, Q, w, alpha: float = 1.0):
+        """Self-energy integrand traces in the basis Q [k, N^3] (lgw_sigma_traces):
+        returns (sigma_N [n_w], sigma_N0 [n_w], sigma_A)."""
+        t = self.torch
+        Q = self._dev(Q, t.complex128).reshape(-1, self.N ** 3)
+        w = np.ascontiguousarray(np.atleast_1d(np.asarray(w, dtype=np.float64)))
+        sN = np.zeros(len(w))
+        sN0 = np.zeros(len(w))
+        sA = np.zeros(1)
+        t.cuda.synchronize()
+        self.last_status = self._check(self.lib.lgw_sigma_traces(
+            self.ctx, int(e), float(delta), float(alpha), Q.shape[0], Q.data_ptr(), len(w),
+            w.ctypes.data, sN.ctypes.data, sN0.ctypes.data, sA.ctypes.data))
+        return sN, sN0, float(sA[0])
+
+    def sigma_residues(self, e: int, delta: float, k_p: int = 4):
+        """Residue term Sigma_P of state e (lgw_sigma_residues): (Sigma_P, n_poles)."""
+        sp = np.zeros(1)
+        npl = C.c_int(0)
+        self.torch.cuda.synchronize()
+        self.last_status = self._check(self.lib.lgw_sigma_residues(
+            self.ctx, int(e), float(delta), int(k_p), sp.ctypes.data, C.byref(npl)))
+        return float(sp[0]), npl.value
 
     def hpsi_noalloc(self, x, y, shift: complex = 0.0):
         """y = (H - shift) x into the caller's device tensor y through
