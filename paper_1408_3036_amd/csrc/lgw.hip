@@ -886,6 +886,59 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       }
       lst = bad;
     }
+    // Systems the FP32 sweeps could not bring to the tolerance (an inner
+    // solve that stagnates or breaks down on a nearly singular system) get an
+    // FP64 correction on their true residual: solve A e = R in FP64 to
+    // tol |b| / |R| and x += e; judged by the combined residual.
+    std::vector<int> fail;
+    for (int s = 0; s < nsys; ++s)
+      if (out.rel[s] > 10 * tol) fail.push_back(s);
+    if (!fail.empty()) {
+      true_resid(fail);   // R rows of the failing systems, h_res = |R|^2
+      const int nf = (int)fail.size();
+      z64* Rf = c->buf<z64>("sv.Rfb", (size_t)nf * npw);
+      std::vector<int> rows(nf), ident(nf);
+      for (int i = 0; i < nf; ++i) {
+        rows[i] = fail[i];
+        ident[i] = i;
+      }
+      int* d_rows = c->buf<int>("sv.fbrows", 2 * (size_t)nf);
+      h2d_async(c, d_rows, rows.data(), nf * sizeof(int));
+      h2d_async(c, d_rows + nf, ident.data(), nf * sizeof(int));
+      launch_rows_out(R, npw, Rf, npw, d_rows + nf, d_rows, nullptr, npw, nf, c->stream);   // Rf[i] = R[fail[i]]
+      std::vector<z64> fsh(nf);
+      std::vector<double> fw2(nf, 0.0);
+      double rtol = 0.5;
+      for (int i = 0; i < nf; ++i) {
+        const int sy = fail[i];
+        fsh[i] = shift[sy];
+        if (!w2v.empty()) fw2[i] = w2v[sy];
+        if (h_res[sy] > 0) rtol = std::min(rtol, tol * std::sqrt(h_bb[sy] / h_res[sy]));
+      }
+      rtol = std::max(rtol, tol);
+      z64* Ef = c->buf<z64>("sv.Efb", (size_t)nf * npw);
+      SolveOut so;
+      {
+        struct OptScope {
+          lgw_ctx* c;
+          lgw_opts saved;
+          ~OptScope() { c->opts = saved; }
+        } scope{c, c->opts};
+        c->opts.precision = LGW_FP64;
+        c->opts.tol = rtol;
+        solve(c, kind, Rf, ident, fsh, fw2, Ef, so);
+      }
+      // the inner call reused this call's workspace: X and the host copies stand
+      for (int i = 0; i < nf; ++i) {
+        z64* xr = X + (size_t)fail[i] * npw;
+        launch_add(xr, xr, Ef + (size_t)i * npw, npw, c->stream);
+        const int sy = fail[i];
+        out.rel[sy] = h_bb[sy] > 0 ? so.rel[i] * std::sqrt(h_res[sy] / h_bb[sy]) : 0.0;
+        out.iters[sy] += so.iters[i];
+        out.sweeps[sy] += 1;
+      }
+      c->check_launch();
+    }
     for (int s = 0; s < nsys; ++s) out.flags[s] = out.rel[s] <= 10 * tol ? FLAG_CONV : FLAG_MAXIT;
   }
   for (int s = 0; s < nsys; ++s) c->tot_iters += out.iters[s];
