@@ -128,6 +128,156 @@ def cpu_baseline(w, zs_sample, xs, cores):
     return np.array([r[0] for r in res]), wall, sum(r[1] for r in res)
 
 
+def bench_large72(log_fn):
+    """The large-molecule workload at its shape: block Lanczos, 8-vector blocks
+    to 256 vectors, then eps(z) - 1 on that basis at the 32 imaginary
+    frequencies (mixed precision with the fast solver options, multi-shift
+    projection).  Returns the record for the JSON line."""
+    import torch
+    from paper_1408_3036_amd import Lgw
+    from synthetic import make_workload, random_potentials
+    w = make_workload(3)
+    seeds = torch.from_numpy(random_potentials(w.N, 8, (14083036, 3, 0, 80)))
+    zs = list(w.z)
+    lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps, precision="mixed",
+             tol=1e-10, precond=True, imag_form="shifted", multishift=True)
+    try:
+        lg.block_lanczos(seeds, 2, want_Q=False)          # warm-up (workspace, graphs)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        A, B, Q, nd = lg.block_lanczos(seeds, 32)
+        torch.cuda.synchronize()
+        t_l = time.perf_counter() - t
+        t = time.perf_counter()
+        E = lg.project(Q, zs)
+        torch.cuda.synchronize()
+        t_p = time.perf_counter() - t
+        npw = lg.npw
+    finally:
+        lg.close()
+    n_apply = 256 + (len(zs) - 1) * 256      # the z = 0 block of E is the recursion's (distinct applies)
+    log_fn(f"[large-72] block Lanczos {t_l:.2f}s, projection {t_p:.2f}s")
+    return {"workload": f"{w.name}: L={w.L} bohr, {w.N}^3 grid, ecut {w.ecut} Ha, {npw} PW, {w.n_wells} wells, "
+                        f"n_v={w.n_v}; block Lanczos 32 x 8 vectors + eps(z)-1 at {len(zs)} imaginary z",
+            "chi0_applies": n_apply, "seconds": round(t_l + t_p, 3),
+            "chi0_applies_per_s": round(n_apply / (t_l + t_p), 1),
+            "block_lanczos_s": round(t_l, 3), "projection_s": round(t_p, 3),
+            "band_systems": 16 * n_apply,
+            "how": "mixed precision (FP32 transforms inside FP64 refinement) with the kinetic preconditioner "
+                   "for the 256 static columns, multi-shift FP64 recursions for the projection; the projection "
+                   "recomputes z = 0, counted once"}
+
+
+def bench_uneven(log_fn, n_box: int = 32):
+    """The batched uneven-systems workload: every box runs a 32-step Lanczos
+    and eps(z) - 1 at its 8 imaginary frequencies (lanczos_project), first one
+    box after the other (per-system rates), then all boxes at once, one host
+    thread and stream per box (aggregate rate).  Ground states are built over
+    the host cores beforehand."""
+    import tempfile
+    import shutil
+    import threading
+    import torch
+    from paper_1408_3036_amd import Lgw
+    from synthetic import random_potentials
+    from synthetic.boxes import make_uneven_boxes
+    d = tempfile.mkdtemp(prefix="lgw_uneven_")
+    try:
+        t = time.perf_counter()
+        boxes = make_uneven_boxes(d, n_box)
+        log_fn(f"[uneven] {n_box} boxes built in {time.perf_counter() - t:.1f}s")
+        lgs, q0s = [], []
+        for bx in boxes:
+            V = torch.from_numpy(np.load(bx["pre"] + "_V.npy"))
+            psi = torch.from_numpy(np.load(bx["pre"] + "_psi.npy"))
+            eps = np.load(bx["pre"] + "_eps.npy")
+            lgs.append(Lgw(bx["L"], bx["N"], bx["ecut"], V, psi, eps, precision="mixed", tol=1e-10,
+                           precond=True, imag_form="shifted", multishift=True))
+            q0s.append(torch.from_numpy(random_potentials(bx["N"], 1, (14083036, 4, bx["sys"], 99))[0]).cuda())
+        zs = list(boxes[0]["z"])
+        k = 32
+        n_apply = k + (len(zs) - 1) * k
+        try:
+            for lg, q0 in zip(lgs, q0s):                     # warm-up
+                lg.lanczos_project(q0, k, zs, want_Q=False)
+            torch.cuda.synchronize()
+            per = []
+            for lg, q0 in zip(lgs, q0s):
+                t = time.perf_counter()
+                lg.lanczos_project(q0, k, zs, want_Q=False)
+                torch.cuda.synchronize()
+                per.append(time.perf_counter() - t)
+            errs = []
+
+            def run(i):
+                try:
+                    lgs[i].lanczos_project(q0s[i], k, zs, want_Q=False)
+                except Exception as e:          # reported, not raised in the thread
+                    errs.append(repr(e))
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            th = [threading.Thread(target=run, args=(i,)) for i in range(len(lgs))]
+            for x in th:
+                x.start()
+            for x in th:
+                x.join()
+            torch.cuda.synchronize()
+            conc = time.perf_counter() - t
+        finally:
+            for lg in lgs:
+                lg.close()
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    seq = sum(per)
+    log_fn(f"[uneven] one after the other {seq:.2f}s, all at once {conc:.2f}s")
+    return {"workload": f"{n_box} boxes, grids {sorted(set(b['N'] for b in boxes))}, n_v "
+                        f"{min(b['n_v'] for b in boxes)}..{max(b['n_v'] for b in boxes)}; per box {k}-step "
+                        f"Lanczos + eps(z)-1 at {len(zs)} imaginary z",
+            "chi0_applies": n_apply * n_box,
+            "aggregate_chi0_applies_per_s": round(n_apply * n_box / conc, 1),
+            "sequential_chi0_applies_per_s": round(n_apply * n_box / seq, 1),
+            "concurrent_over_sequential": round(seq / conc, 3),
+            "errors": errs,
+            "per_system": [{"sys": b["sys"], "N": b["N"], "n_v": b["n_v"], "seconds": round(p, 4),
+                            "chi0_applies_per_s": round(n_apply / p, 1)} for b, p in zip(boxes, per)],
+            "how": "mixed precision, fast solver options, multi-shift projection; per-system rates from the "
+                   "boxes run one after the other, the aggregate from all boxes at once (one host thread, "
+                   "context and stream per box)"}
+
+
+def bench_sigma(w, lg_kw, q0, log_fn):
+    """Correlation self-energy of the highest valence state on the silane-sized
+    basis: sigma_N, sigma_N0 at 8 Gauss-Legendre frequencies of the half line,
+    the Lorentzian term (a = 1 Ha) and the residues (4 Lanczos steps per pole)."""
+    import torch
+    from paper_1408_3036_amd import Lgw
+    t_nodes, t_w = np.polynomial.legendre.leggauss(8)
+    ws = (1 + t_nodes) / (1 - t_nodes)
+    wts = t_w * 2 / (1 - t_nodes) ** 2
+    lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps, **lg_kw)
+    try:
+        _, _, Q, kd = lg.lanczos(q0, 64)
+        e, delta = w.n_v - 1, -0.1
+        lg.sigma_traces(e, delta, Q[:8], ws[:2])     # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sN, sN0, sA = lg.sigma_traces(e, delta, Q, ws)
+        t_tr = time.perf_counter() - t
+        t = time.perf_counter()
+        sP, npl = lg.sigma_residues(e, delta, 4)
+        t_res = time.perf_counter() - t
+    finally:
+        lg.close()
+    sc = float(np.sum(wts * (sN - sN0)) / np.pi + sA + sP)
+    log_fn(f"[sigma] traces {t_tr:.2f}s, residues {t_res:.2f}s, Sigma_c {sc:.6f} Ha")
+    return {"state": "highest valence", "delta_Ha": delta, "basis": kd, "frequencies": len(ws),
+            "traces_s": round(t_tr, 3), "residues_s": round(t_res, 3), "poles": npl,
+            "sigma_c_Ha": sc, "sigma_A_Ha": sA, "sigma_P_Ha": sP,
+            "how": "lgw_sigma_traces (E(z) at 9 frequencies, shift-Lanczos of H for the 8 integrand "
+                   "frequencies, one static solve per basis vector for the Lorentzian term) and "
+                   "lgw_sigma_residues on the 64-vector static Lanczos basis"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +301,8 @@ def main():
                     help="skip the frequency-recycling measurement beside the headline mode")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the large-72, uneven-batch and self-energy measurements beside the headline")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -286,6 +438,16 @@ def main():
     # serve as the z = 0 column of E(z), so the other len(zs) - 1 frequencies
     # add k applies each (z = 0 is one of the 32 frequencies)
     n_apply = k + (len(zs) - 1) * k if any(z == 0 for z in zs) else k + len(zs) * k
+    extras = {}
+    if not args.no_extra:
+        for name, fn in (("large72", lambda: bench_large72(log)), ("uneven32", lambda: bench_uneven(log)),
+                         ("sigma", lambda: bench_sigma(w, dict(tol=1e-13, precond=True, imag_form="shifted",
+                                                                multishift=True), q0, log))):
+            try:
+                extras[name] = fn()
+            except Exception as e:      # a failed extra is reported; it does not cost the headline line
+                extras[name] = {"error": repr(e)}
+                log(f"[{name}] failed: {e!r}")
     main_mode = [m for m in ("mixed", "fp64", "mixed_paper", "fp64_paper") if m in results][0]
     main_prec = "mixed" if main_mode.startswith("mixed") else "fp64"
     r = results[main_mode]
@@ -359,6 +521,7 @@ def main():
                 "kernel_GBps": {n: round(v["model_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
                                 for n, v in ki.items() if v["total_ms"] > 0},
                 "how": "batched launches of the one-after-the-other Lanczos and projection pass"}
+    out.update(extras)
     if model:
         out["model_operator"] = {"chi0_applies_per_s": round(n_apply / model, 2), "step_s": round(model, 4),
                                  "how": "the same 64-step Lanczos + 32-frequency projection on eps~ - 1, the "

@@ -46,6 +46,7 @@ struct Geom {
   const int* col_h;      // [ncols] column holds mz in [-h, h]
   const int* col_pos;    // [ncols] (mx mod N) * N + (my mod N)
   const double* kin;     // [npw] |K|^2 / 2
+  const int* col_of;     // [N * N] column at plane position x * N + y, -1 where none
 };
 
 // LDS position of element e of a length-N line with one pad slot every 8

@@ -281,4 +281,62 @@ __device__ __forceinline__ void fft_filter_rows(cplx<T>* buf, const cplx<T>* tw,
   fft_stage<T, N, B, A, -1, NT, MAXCNT, false>(buf, tw, cnt, addr);
 }
 
+// The row filter when only the rows' elements e in {0..h} U {N-h..N-1} carry
+// data: the first stage reads those and takes zeros for the rest (which are
+// never read from LDS, so they need not be cleared), the last stage stores
+// only those outputs.  Same arithmetic as fft_filter_rows otherwise.
+template <typename T, int N, int NT, int MAXCNT, class Addr, class Mul>
+__device__ __forceinline__ void fft_filter_rows_pruned(cplx<T>* buf, const cplx<T>* tw, int cnt, int h, Addr addr,
+                                                       Mul mul) {
+  constexpr int A = first_of(typename Plan<N>::type{});
+  constexpr int B = second_of(typename Plan<N>::type{});
+  auto live = [h](int e) { return e <= h || e >= N - h; };
+  // inverse stage 1: radix B, P = 1
+  fft_stage_ls<T, N, B, 1, +1, NT, MAXCNT, false, true>(
+      tw, cnt, [&](int t, int e) { return live(e) ? buf[addr(t, e)] : cplx<T>{0, 0}; },
+      [&](int t, int e, cplx<T> x) { buf[addr(t, e)] = x; });
+  // inverse stage 2 (radix A, P = B) + multiply + forward stage 1 (radix A, P = 1)
+  {
+    constexpr int MAXB = (MAXCNT * B + NT - 1) / NT;
+    const int nb = cnt * B;
+    cplx<T> v[MAXB][A];
+#pragma unroll
+    for (int k = 0; k < MAXB; ++k) {
+      const int b = threadIdx.x + k * NT;
+      if (b < nb) {
+        const int i = b % B, t = b / B;
+#pragma unroll
+        for (int r = 0; r < A; ++r) v[k][r] = buf[addr(t, i + r * B)];
+#pragma unroll
+        for (int r = 1; r < A; ++r) {
+          cplx<T> w = tw[r * i];
+          w.y = -w.y;
+          v[k][r] = v[k][r] * w;
+        }
+        Dft<A, +1, T>::run(v[k]);
+#pragma unroll
+        for (int r = 0; r < A; ++r) v[k][r] = mul(t, i + r * B) * v[k][r];
+        Dft<A, -1, T>::run(v[k]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MAXB; ++k) {
+      const int b = threadIdx.x + k * NT;
+      if (b < nb) {
+        const int i = b % B, t = b / B;
+#pragma unroll
+        for (int r = 0; r < A; ++r) buf[addr(t, i * A + r)] = v[k][r];
+      }
+    }
+    __syncthreads();
+  }
+  // forward stage 2: radix B, P = A
+  fft_stage_ls<T, N, B, A, -1, NT, MAXCNT, false, true>(
+      tw, cnt, [&](int t, int e) { return buf[addr(t, e)]; },
+      [&](int t, int e, cplx<T> x) {
+        if (live(e)) buf[addr(t, e)] = x;
+      });
+}
+
 }  // namespace lgw

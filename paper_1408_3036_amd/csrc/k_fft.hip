@@ -210,31 +210,51 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
 // --------------------------------------------------------------- plane_hv
 // One z plane of one system: x-inverse on the columns y that carry plane
 // waves, y-filter on every row (inverse, times V, forward, with the middle
-// stages fused in registers), x-forward on the same columns.
+// stages fused in registers), x-forward on the same columns.  The first
+// x-stage takes its butterflies straight from the plane's sphere columns
+// (zero where the position map has none) and the last x-stage stores only the
+// sphere columns back, so the plane is never cleared, scattered or gathered
+// in LDS; the y-filter reads and writes only the 2 hy + 1 data rows at its
+// ends.
 template <typename T, int N>
 __global__ void __launch_bounds__(plane_threads<N>())
 k_plane_hv(Geom g, const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ Tb, long ldt,
            const T* __restrict__ Vt, const int* __restrict__ act) {
   constexpr int NT = plane_threads<N>();
+  constexpr int A = first_of(typename Plan<N>::type{});
+  constexpr int B = second_of(typename Plan<N>::type{});
   __shared__ cplx<T> pl[N * N];
   __shared__ cplx<T> tws[N];
   const int z = blockIdx.x;
   const int sys = sys_of(act, blockIdx.y);
   cplx<T>* Ts = Tb + (long)sys * ldt + (long)z * g.ncols;
-  load_tw<T, N>(tws, tw);
-  for (int i = threadIdx.x; i < N * N; i += NT) pl[i] = cplx<T>{0, 0};
-  __syncthreads();
-  for (int c = threadIdx.x; c < g.ncols; c += NT) pl[g.col_pos[c]] = Ts[c];
-  __syncthreads();
+  const int* __restrict__ colof = g.col_of;
+  load_tw<T, N>(tws, tw);   // first read after the first stage's closing barrier
   const int hy = g.hy;
   const int ny = 2 * hy + 1;
   auto col = [hy](int t, int e) { return e * N + pruned<N>(t, hy); };
-  fft_lds<T, N, +1, NT, N, true>(pl, tws, ny, col);
+  // x-inverse stage 1 (radix A, no twiddles) from the sphere columns
+  fft_stage_ls<T, N, A, 1, +1, NT, N, true, false>(
+      tws, ny,
+      [&](int t, int e) {
+        const int ci = colof[e * N + pruned<N>(t, hy)];
+        return ci >= 0 ? Ts[ci] : cplx<T>{0, 0};
+      },
+      [&](int t, int e, cplx<T> v) { pl[col(t, e)] = v; });
+  // x-inverse stage 2 (radix B after A)
+  fft_stage<T, N, B, A, +1, NT, N, true>(pl, tws, ny, col);
   const T* Vz = Vt + (long)z * N * N;
-  fft_filter_rows<T, N, NT, N>(pl, tws, N, [](int t, int e) { return t * N + e; },
-                               [Vz](int t, int e) { return Vz[t * N + e]; });
-  fft_lds<T, N, -1, NT, N, true>(pl, tws, ny, col);
-  for (int c = threadIdx.x; c < g.ncols; c += NT) Ts[c] = pl[g.col_pos[c]];
+  fft_filter_rows_pruned<T, N, NT, N>(pl, tws, N, hy, [](int t, int e) { return t * N + e; },
+                                      [Vz](int t, int e) { return Vz[t * N + e]; });
+  // x-forward stage 1
+  fft_stage<T, N, A, 1, -1, NT, N, true>(pl, tws, ny, col);
+  // x-forward stage 2, stored to the sphere columns
+  fft_stage_ls<T, N, B, A, -1, NT, N, true, false>(
+      tws, ny, [&](int t, int e) { return pl[col(t, e)]; },
+      [&](int t, int e, cplx<T> v) {
+        const int ci = colof[e * N + pruned<N>(t, hy)];
+        if (ci >= 0) Ts[ci] = v;
+      });
 }
 
 // --------------------------------------------------------- plane_pair_fwd

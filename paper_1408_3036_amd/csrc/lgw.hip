@@ -103,7 +103,7 @@ struct lgw_ctx {
   int nv = 0, npw = 0, ncols = 0, hx = 0, hy = 0;
   std::vector<int> m, col_start, col_h, col_pos;
   std::vector<double> kin, eps;
-  DevBuf d_col_start, d_col_h, d_col_pos, d_kin, d_Vt, d_Vt32, d_sqrtv, d_tw64, d_tw32, d_psi, d_u, d_Phi,
+  DevBuf d_col_start, d_col_h, d_col_pos, d_col_of, d_kin, d_Vt, d_Vt32, d_sqrtv, d_tw64, d_tw32, d_psi, d_u, d_Phi,
       d_Phi32;
   // kinetic preconditioner (opts.precond = 1): diagonal scalings of the
   // linear / SQMR systems (|K|^2/2 + shift)^(-1/2) and of the squared form
@@ -1863,6 +1863,7 @@ lgw_ctx* twin_of(lgw_ctx* c, size_t i) {
   dup_buf(c, t->d_col_start, c->d_col_start);
   dup_buf(c, t->d_col_h, c->d_col_h);
   dup_buf(c, t->d_col_pos, c->d_col_pos);
+  dup_buf(c, t->d_col_of, c->d_col_of);
   dup_buf(c, t->d_kin, c->d_kin);
   dup_buf(c, t->d_Vt, c->d_Vt);
   dup_buf(c, t->d_Vt32, c->d_Vt32);
@@ -1879,7 +1880,7 @@ lgw_ctx* twin_of(lgw_ctx* c, size_t i) {
   }
   c->sync();
   t->geom = Geom{t->N, t->npw, t->ncols, t->hx, t->hy, t->d_col_start.as<int>(), t->d_col_h.as<int>(),
-                 t->d_col_pos.as<int>(), t->d_kin.as<double>()};
+                 t->d_col_pos.as<int>(), t->d_kin.as<double>(), t->d_col_of.as<int>()};
   c->twins[i] = std::move(t);
   return c->twins[i].get();
 }
@@ -2428,6 +2429,12 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
     upload(c.get(), c->d_col_start, col_start);
     upload(c.get(), c->d_col_h, col_h);
     upload(c.get(), c->d_col_pos, col_pos);
+    {
+      // plane position -> column (the transforms' direct loads and stores)
+      std::vector<int> col_of((size_t)N * N, -1);
+      for (size_t ci = 0; ci < col_pos.size(); ++ci) col_of[col_pos[ci]] = (int)ci;
+      upload(c.get(), c->d_col_of, col_of);
+    }
     upload(c.get(), c->d_kin, kin);
     if (o.precond == 1) {
       double kmax = 0.0;
@@ -2447,7 +2454,7 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
       }
     }
     c->geom = Geom{N, c->npw, c->ncols, hx, hy, c->d_col_start.as<int>(), c->d_col_h.as<int>(),
-                   c->d_col_pos.as<int>(), c->d_kin.as<double>()};
+                   c->d_col_pos.as<int>(), c->d_kin.as<double>(), c->d_col_of.as<int>()};
     // twiddles exp(-2 pi i j / N)
     std::vector<z64> tw(N);
     std::vector<z32> tw32(N);
