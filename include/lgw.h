@@ -99,6 +99,15 @@ typedef struct {
                           chi0 / Lanczos / projection call then works on
                           eps~ - 1, the second basis of Sec. V; the VJP and
                           recycling calls return EINVAL.  0 (default): H      */
+  int    autotune;     /* 1 (default): the plane pass of every H application
+                          uses the tile variant (threads per workgroup, LDS
+                          row layout) measured fastest for this grid,
+                          precision and batch size; the measurement runs once
+                          per process at the first set-up with a grid (a few
+                          tens of ms), and with the environment variable
+                          LGW_TUNE_CACHE naming a file it is read from and
+                          appended to that file.  Every variant computes the
+                          same values.  0: a fixed variant                    */
 } lgw_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -348,6 +357,15 @@ typedef struct { long long launches; double total_ms; double model_bytes; } lgw_
 lgw_status lgw_profile(lgw_ctx* ctx, int enable);
 lgw_status lgw_kernel_timing(const lgw_ctx* ctx, int kernel, lgw_timing* out);
 void lgw_free(lgw_ctx* ctx);
+
+/* The plane-pass tile variant an H application of nsys systems uses in the
+ * given precision (LGW_FP64, or LGW_MIXED for the single-precision inner
+ * solves) on this context's grid: variant index, threads per workgroup, padded
+ * LDS rows (1) or not (0), and in us[4] (or NULL) the autotuner's measured
+ * microseconds per launch of each variant (zeros if not measured).  Host
+ * memory; no device work. */
+lgw_status lgw_tune_info(const lgw_ctx* ctx, int precision, int nsys, int* variant, int* threads, int* pad,
+                         double* us);
 
 #ifdef __cplusplus
 }

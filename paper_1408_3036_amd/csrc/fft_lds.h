@@ -285,14 +285,18 @@ __device__ __forceinline__ void fft_filter_rows(cplx<T>* buf, const cplx<T>* tw,
 // data: the first stage reads those and takes zeros for the rest (which are
 // never read from LDS, so they need not be cleared), the last stage stores
 // only those outputs.  Same arithmetic as fft_filter_rows otherwise.
-template <typename T, int N, int NT, int MAXCNT, class Addr, class Mul>
+// TFAST: consecutive threads take consecutive rows (with a row stride of
+// N + 1 elements the lanes of one LDS access then fall in distinct banks for
+// every stage, including the stride-R stores of the stages with P = 1); else
+// consecutive butterflies of one row.
+template <typename T, int N, int NT, int MAXCNT, bool TFAST, class Addr, class Mul>
 __device__ __forceinline__ void fft_filter_rows_pruned(cplx<T>* buf, const cplx<T>* tw, int cnt, int h, Addr addr,
                                                        Mul mul) {
   constexpr int A = first_of(typename Plan<N>::type{});
   constexpr int B = second_of(typename Plan<N>::type{});
   auto live = [h](int e) { return e <= h || e >= N - h; };
   // inverse stage 1: radix B, P = 1
-  fft_stage_ls<T, N, B, 1, +1, NT, MAXCNT, false, true>(
+  fft_stage_ls<T, N, B, 1, +1, NT, MAXCNT, TFAST, true>(
       tw, cnt, [&](int t, int e) { return live(e) ? buf[addr(t, e)] : cplx<T>{0, 0}; },
       [&](int t, int e, cplx<T> x) { buf[addr(t, e)] = x; });
   // inverse stage 2 (radix A, P = B) + multiply + forward stage 1 (radix A, P = 1)
@@ -304,7 +308,7 @@ __device__ __forceinline__ void fft_filter_rows_pruned(cplx<T>* buf, const cplx<
     for (int k = 0; k < MAXB; ++k) {
       const int b = threadIdx.x + k * NT;
       if (b < nb) {
-        const int i = b % B, t = b / B;
+        const int t = TFAST ? b % cnt : b / B, i = TFAST ? b / cnt : b % B;
 #pragma unroll
         for (int r = 0; r < A; ++r) v[k][r] = buf[addr(t, i + r * B)];
 #pragma unroll
@@ -324,7 +328,7 @@ __device__ __forceinline__ void fft_filter_rows_pruned(cplx<T>* buf, const cplx<
     for (int k = 0; k < MAXB; ++k) {
       const int b = threadIdx.x + k * NT;
       if (b < nb) {
-        const int i = b % B, t = b / B;
+        const int t = TFAST ? b % cnt : b / B, i = TFAST ? b / cnt : b % B;
 #pragma unroll
         for (int r = 0; r < A; ++r) buf[addr(t, i * A + r)] = v[k][r];
       }
@@ -332,7 +336,7 @@ __device__ __forceinline__ void fft_filter_rows_pruned(cplx<T>* buf, const cplx<
     __syncthreads();
   }
   // forward stage 2: radix B, P = A
-  fft_stage_ls<T, N, B, A, -1, NT, MAXCNT, false, true>(
+  fft_stage_ls<T, N, B, A, -1, NT, MAXCNT, TFAST, true>(
       tw, cnt, [&](int t, int e) { return buf[addr(t, e)]; },
       [&](int t, int e, cplx<T> x) {
         if (live(e)) buf[addr(t, e)] = x;

@@ -215,15 +215,20 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
 // (zero where the position map has none) and the last x-stage stores only the
 // sphere columns back, so the plane is never cleared, scattered or gathered
 // in LDS; the y-filter reads and writes only the 2 hy + 1 data rows at its
-// ends.
-template <typename T, int N>
-__global__ void __launch_bounds__(plane_threads<N>())
+// ends.  Tile variants (chosen per grid, precision and batch size by the
+// library's autotuner; every variant computes the same values):
+//   NT   threads per workgroup;
+//   PAD  rows of N + 1 elements with the y-stages' threads on consecutive
+//        rows (distinct LDS banks for every access), else rows of N
+//        elements with consecutive butterflies of a row.
+template <typename T, int N, int NT, bool PAD>
+__global__ void __launch_bounds__(NT)
 k_plane_hv(Geom g, const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ Tb, long ldt,
            const T* __restrict__ Vt, const int* __restrict__ act) {
-  constexpr int NT = plane_threads<N>();
   constexpr int A = first_of(typename Plan<N>::type{});
   constexpr int B = second_of(typename Plan<N>::type{});
-  __shared__ cplx<T> pl[N * N];
+  constexpr int LD = PAD ? N + 1 : N;
+  __shared__ cplx<T> pl[N * LD];
   __shared__ cplx<T> tws[N];
   const int z = blockIdx.x;
   const int sys = sys_of(act, blockIdx.y);
@@ -232,7 +237,7 @@ k_plane_hv(Geom g, const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ Tb, lon
   load_tw<T, N>(tws, tw);   // first read after the first stage's closing barrier
   const int hy = g.hy;
   const int ny = 2 * hy + 1;
-  auto col = [hy](int t, int e) { return e * N + pruned<N>(t, hy); };
+  auto col = [hy](int t, int e) { return e * LD + pruned<N>(t, hy); };
   // x-inverse stage 1 (radix A, no twiddles) from the sphere columns
   fft_stage_ls<T, N, A, 1, +1, NT, N, true, false>(
       tws, ny,
@@ -244,8 +249,8 @@ k_plane_hv(Geom g, const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ Tb, lon
   // x-inverse stage 2 (radix B after A)
   fft_stage<T, N, B, A, +1, NT, N, true>(pl, tws, ny, col);
   const T* Vz = Vt + (long)z * N * N;
-  fft_filter_rows_pruned<T, N, NT, N>(pl, tws, N, hy, [](int t, int e) { return t * N + e; },
-                                      [Vz](int t, int e) { return Vz[t * N + e]; });
+  fft_filter_rows_pruned<T, N, NT, N, PAD>(pl, tws, N, hy, [](int t, int e) { return t * LD + e; },
+                                           [Vz](int t, int e) { return Vz[t * N + e]; });
   // x-forward stage 1
   fft_stage<T, N, A, 1, -1, NT, N, true>(pl, tws, ny, col);
   // x-forward stage 2, stored to the sphere columns
@@ -415,12 +420,34 @@ void launch_zinv_fed(const Geom& g, const cplx<T>* tw, const ProjFeed<T>& f, con
   LGW_DISPATCH_N(g.N, (k_zinv<T, NN_, true><<<grid, 256, 0, s>>>(g, tw, D, ldx, Tb, ldt, T(1), act, f, Xout)));
 }
 
+// plane-pass tile variants: (threads, padded rows); grids of 64 and more take
+// twice the threads (one workgroup per compute unit fits their planes)
+template <int N, int V> constexpr int plane_var_threads() { return (N >= 64 ? 512 : 256) << (V >> 1); }
+
+template <typename T, int N, int V>
+void launch_plane_var(const Geom& g, const cplx<T>* tw, cplx<T>* Tb, long ldt, const T* Vt, const int* act,
+                      int nsys, hipStream_t s) {
+  constexpr int NT = plane_var_threads<N, V>();
+  k_plane_hv<T, N, NT, (V & 1) != 0><<<dim3(g.N, nsys), NT, 0, s>>>(g, tw, Tb, ldt, Vt, act);
+}
+
+int plane_variants() { return 4; }
+
+void plane_variant_shape(int N, int v, int* threads, int* pad) {
+  *threads = (N >= 64 ? 512 : 256) << (v >> 1);
+  *pad = v & 1;
+}
+
 template <typename T>
 void launch_plane_hv(const Geom& g, const cplx<T>* tw, cplx<T>* Tb, long ldt, const T* Vt,
-                     const int* act, int nsys, hipStream_t s) {
+                     const int* act, int nsys, hipStream_t s, int variant) {
   if (nsys <= 0) return;
-  dim3 grid(g.N, nsys);
-  LGW_DISPATCH_N(g.N, (k_plane_hv<T, NN_><<<grid, plane_threads<NN_>(), 0, s>>>(g, tw, Tb, ldt, Vt, act)));
+  switch (variant & 3) {
+    case 0: LGW_DISPATCH_N(g.N, (launch_plane_var<T, NN_, 0>(g, tw, Tb, ldt, Vt, act, nsys, s))); break;
+    case 1: LGW_DISPATCH_N(g.N, (launch_plane_var<T, NN_, 1>(g, tw, Tb, ldt, Vt, act, nsys, s))); break;
+    case 2: LGW_DISPATCH_N(g.N, (launch_plane_var<T, NN_, 2>(g, tw, Tb, ldt, Vt, act, nsys, s))); break;
+    default: LGW_DISPATCH_N(g.N, (launch_plane_var<T, NN_, 3>(g, tw, Tb, ldt, Vt, act, nsys, s))); break;
+  }
 }
 
 template <typename T>
@@ -483,7 +510,7 @@ void launch_zfull_mul(int N, const cplx<T>* tw, cplx<T>* G, long ldg, const T* m
   template void launch_zinv_fed<T>(const Geom&, const cplx<T>*, const ProjFeed<T>&, const cplx<T>*,    \
                                    cplx<T>*, long, cplx<T>*, long, const int*, int, hipStream_t);     \
   template void launch_plane_hv<T>(const Geom&, const cplx<T>*, cplx<T>*, long, const T*, const int*, \
-                                   int, hipStream_t);                                                 \
+                                   int, hipStream_t, int);                                            \
   template void launch_zfwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, T, const cplx<T>*,  \
                                long, const cplx<T>*, const cplx<T>*, long, const T*, cplx<T>*, long,  \
                                const int*, int, hipStream_t, const T*, const CgDot<T>&);              \

@@ -75,7 +75,10 @@ void launch_zinv_fed(const Geom& g, const cplx<T>* tw, const ProjFeed<T>& f, con
 // middle pass of H: Tb <- FFT_xy(Vt[z] * IFFT_xy(Tb)) on every z plane (unscaled)
 template <typename T>
 void launch_plane_hv(const Geom& g, const cplx<T>* tw, cplx<T>* Tb, long ldt, const T* Vt,
-                     const int* act, int nsys, hipStream_t s);
+                     const int* act, int nsys, hipStream_t s, int variant);
+// tile variants of the plane pass: count, and (threads, padded rows) of one
+int plane_variants();
+void plane_variant_shape(int N, int v, int* threads, int* pad);
 // columns -> sphere: Y = scale * FFT_z(Tb) [+ (kin - shift[sys]) X] [+ ecoef[sys] E]
 template <typename T>
 void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, T scale,

@@ -353,6 +353,36 @@ void upload(lgw_ctx* c, DevBuf& b, const std::vector<T>& h) {
   h2d(c, b.p, h.data(), h.size() * sizeof(T));
 }
 
+// ---- plane-pass autotuner ---------------------------------------------------
+// The plane pass has tile variants (threads per workgroup, row layout; every
+// variant computes the same values).  The best one per (grid, precision,
+// batch-size bucket) is measured once per process, at the first set-up of a
+// context with that grid, on a zero-filled column buffer of a representative
+// batch, and kept in this table; with LGW_TUNE_CACHE set to a file name the
+// measurements are also read from and appended to that file.
+struct PlaneTune {
+  int best = -1;
+  double us[4] = {0, 0, 0, 0};
+  int rep = 0;   // systems of the timed batch
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, PlaneTune> g_tune;   // (N, single precision, bucket)
+bool g_tune_file_read = false;
+constexpr int kTuneBuckets = 4;
+constexpr int kTuneRep[kTuneBuckets] = {4, 64, 512, 2048};
+
+int tune_bucket(int nsys) { return nsys <= 8 ? 0 : (nsys <= 64 ? 1 : (nsys <= 512 ? 2 : 3)); }
+
+// the variant used without tuning (opts.autotune = 0, or no entry yet)
+int plane_default_variant() { return 0; }
+
+int plane_variant_for(int N, bool f32, int nsys, bool autotune) {
+  if (!autotune) return plane_default_variant();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple(N, f32 ? 1 : 0, tune_bucket(nsys)));
+  return it == g_tune.end() || it->second.best < 0 ? plane_default_variant() : it->second.best;
+}
+
 // y = (H - shift) x [+ ecoef E] for nsys systems (device per-system arrays).
 // With fed: x = P (fed->pre .* D) is formed by the first transform from the
 // direction D and the CG kernels' partial sums, and stored to Xw (X == Xw).
@@ -372,7 +402,8 @@ void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const 
   const int pk = sizeof(T) == 4 ? LGW_K_FP32 : 0;
   c->end(t0, pk + LGW_K_ZINV, e * (sph + cols));
   hipEvent_t t1 = c->begin(nsys);
-  launch_plane_hv<T>(c->geom, tw_of<T>(c), Tb, ldt, vt_of<T>(c), act, nsys, c->stream);
+  launch_plane_hv<T>(c->geom, tw_of<T>(c), Tb, ldt, vt_of<T>(c), act, nsys, c->stream,
+                     plane_variant_for(c->N, sizeof(T) == 4, nsys, c->opts.autotune != 0));
   c->end(t1, pk + LGW_K_PLANE_HV, e * 2.0 * cols + sizeof(T) * (double)c->n3);
   hipEvent_t t2 = c->begin(nsys);
   launch_zfwd<T>(c->geom, tw_of<T>(c), Tb, ldt, T(1.0 / (double)c->n3), X, ldx, shift, E, lde, ecoef, Y, ldy,
@@ -2235,6 +2266,102 @@ void recycle_E(lgw_ctx* c, int m, const z64* Bk, const z64* Fk, int n_w, const d
 // ======================================================================= ABI
 namespace {
 
+void tune_file_read_locked() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = std::getenv("LGW_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    int N, f32, bucket, best, rep;
+    double u[4];
+    if (std::sscanf(line, "plane %d %d %d %d %d %lf %lf %lf %lf", &N, &f32, &bucket, &best, &rep, &u[0], &u[1], &u[2],
+                    &u[3]) == 9 &&
+        best >= 0 && best < 4 && bucket >= 0 && bucket < kTuneBuckets) {
+      PlaneTune t;
+      t.best = best;
+      t.rep = rep;
+      for (int v = 0; v < 4; ++v) t.us[v] = u[v];
+      g_tune[std::make_tuple(N, f32, bucket)] = t;
+    }
+  }
+  std::fclose(f);
+}
+
+// Measure the plane-pass variants for this context's grid in each batch
+// bucket not yet in the table (FP64, and FP32 when the context uses it).
+void autotune_plane(lgw_ctx* c) {
+  if (c->opts.autotune == 0) return;
+  std::vector<std::pair<int, int>> todo;   // (single precision, bucket)
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_file_read_locked();
+    for (int f32 = 0; f32 <= (c->opts.precision == LGW_MIXED ? 1 : 0); ++f32)
+      for (int b = 0; b < kTuneBuckets; ++b)
+        if (!g_tune.count(std::make_tuple(c->N, f32, b))) todo.push_back({f32, b});
+  }
+  if (todo.empty()) return;
+  const long ldt = (long)c->N * c->ncols;
+  const size_t cap_bytes = size_t(256) << 20;
+  std::vector<std::string> lines;
+  DevBuf buf;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (auto [f32, b] : todo) {
+    const size_t e = f32 ? sizeof(z32) : sizeof(z64);
+    const int rep = (int)std::max<long>(1, std::min<long>(kTuneRep[b], (long)(cap_bytes / (ldt * e))));
+    buf.ensure((size_t)rep * ldt * e);
+    HIPCHK(hipMemsetAsync(buf.p, 0, (size_t)rep * ldt * e, c->stream));
+    PlaneTune t;
+    t.rep = rep;
+    for (int v = 0; v < plane_variants(); ++v) {
+      auto launch = [&] {
+        if (f32)
+          launch_plane_hv<float>(c->geom, c->d_tw32.as<z32>(), buf.as<z32>(), ldt, c->d_Vt32.as<float>(), nullptr,
+                                 rep, c->stream, v);
+        else
+          launch_plane_hv<double>(c->geom, c->d_tw64.as<z64>(), buf.as<z64>(), ldt, c->d_Vt.as<double>(), nullptr,
+                                  rep, c->stream, v);
+      };
+      launch();   // warm-up
+      const int reps = b == 0 ? 8 : 3;
+      HIPCHK(hipEventRecord(e0, c->stream));
+      for (int r = 0; r < reps; ++r) launch();
+      HIPCHK(hipEventRecord(e1, c->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      c->check_launch();
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      t.us[v] = 1e3 * ms / reps;
+      if (t.best < 0 || t.us[v] < t.us[t.best]) t.best = v;
+    }
+    char line[256];
+    std::snprintf(line, sizeof line, "plane %d %d %d %d %d %.3f %.3f %.3f %.3f\n", c->N, f32, b, t.best, rep, t.us[0],
+                  t.us[1], t.us[2], t.us[3]);
+    lines.push_back(line);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(c->N, f32, b)] = t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->sync();
+  const char* path = std::getenv("LGW_TUNE_CACHE");
+  if (path && *path) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (FILE* f = std::fopen(path, "a")) {
+      for (const auto& l : lines) std::fputs(l.c_str(), f);
+      std::fclose(f);
+    }
+  }
+}
+
+}  // namespace
+
+namespace {
+
 // E[z][a][b] = <q_a, (eps(z) - 1) q_b> (host, row-major) for the plane-major
 // basis Qz [k][N^3] on the device.
 lgw_status project_internal(lgw_ctx* c, int k, const z64* Qz, int n_z, const lgw_c128* z, std::vector<z64>& e) {
@@ -2320,6 +2447,7 @@ void lgw_default_opts(lgw_opts* o) {
   o->imag_form = 0;
   o->multishift = 0;
   o->model = 0;
+  o->autotune = 1;
 }
 
 lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], double ecut, const double* V_loc,
@@ -2355,6 +2483,7 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
   if (o.imag_form != 0 && o.imag_form != 1) return bad("imag_form must be 0 or 1");
   if (o.multishift != 0 && o.multishift != 1) return bad("multishift must be 0 or 1");
   if (o.model != 0 && o.model != 1) return bad("model must be 0 or 1");
+  if (o.autotune != 0 && o.autotune != 1) return bad("autotune must be 0 or 1");
   if (o.mem != LGW_MEM_DEVICE && o.mem != LGW_MEM_HOST) return bad("invalid mem mode");
   const int N = grid[0];
   const long n3 = (long)N * N * N;
@@ -2604,6 +2733,7 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
       launch_cvt_64_32(c->d_Phi.as<z64>(), c->d_Phi32.as<z32>(), (long)n_v * npw, cp->stream);
       cp->sync();
     }
+    autotune_plane(cp);
     c->drop_graphs();
     c->ws.clear();
     *out = c.release();
@@ -3598,7 +3728,8 @@ lgw_status lgw_hpsi_noalloc(lgw_ctx* c, int n, lgw_c128 shift, const lgw_c128* x
       z64* Tb = reinterpret_cast<z64*>(base + al(n * sizeof(z64)));
       launch_fill<double>(sh, z64{shift.re, shift.im}, n, c->stream);
       launch_zinv<double>(c->geom, tw_of<double>(c), dx, npw, Tb, ldt, 1.0, nullptr, n, c->stream);
-      launch_plane_hv<double>(c->geom, tw_of<double>(c), Tb, ldt, vt_of<double>(c), nullptr, n, c->stream);
+      launch_plane_hv<double>(c->geom, tw_of<double>(c), Tb, ldt, vt_of<double>(c), nullptr, n, c->stream,
+                              plane_variant_for(c->N, false, n, c->opts.autotune != 0));
       launch_zfwd<double>(c->geom, tw_of<double>(c), Tb, ldt, 1.0 / (double)c->n3, dx, npw, sh, nullptr, 0,
                           nullptr, dy, npw, nullptr, n, c->stream, nullptr, CgDot<double>{});
     } else {
@@ -3613,7 +3744,8 @@ lgw_status lgw_hpsi_noalloc(lgw_ctx* c, int n, lgw_c128 shift, const lgw_c128* x
       launch_fill<float>(sh, z32{(float)shift.re, (float)shift.im}, n, c->stream);
       launch_cvt_64_32(dx, x32, (long)n * npw, c->stream);
       launch_zinv<float>(c->geom, tw_of<float>(c), x32, npw, Tb, ldt, 1.0f, nullptr, n, c->stream);
-      launch_plane_hv<float>(c->geom, tw_of<float>(c), Tb, ldt, vt_of<float>(c), nullptr, n, c->stream);
+      launch_plane_hv<float>(c->geom, tw_of<float>(c), Tb, ldt, vt_of<float>(c), nullptr, n, c->stream,
+                             plane_variant_for(c->N, true, n, c->opts.autotune != 0));
       launch_zfwd<float>(c->geom, tw_of<float>(c), Tb, ldt, (float)(1.0 / (double)c->n3), x32, npw, sh, nullptr,
                          0, nullptr, y32, npw, nullptr, n, c->stream, nullptr, CgDot<float>{});
       launch_cvt_32_64(y32, dy, (long)n * npw, c->stream);
@@ -3702,6 +3834,24 @@ lgw_status lgw_kernel_timing(const lgw_ctx* c, int kernel, lgw_timing* out) {
 }
 
 const char* lgw_last_error(const lgw_ctx* c) { return c ? c->err.c_str() : g_setup_err.c_str(); }
+
+lgw_status lgw_tune_info(const lgw_ctx* c, int precision, int nsys, int* variant, int* threads, int* pad,
+                         double* us) {
+  if (!c || !variant || (precision != LGW_FP64 && precision != LGW_MIXED) || nsys < 1) return LGW_EINVAL;
+  const bool f32 = precision == LGW_MIXED;
+  const int v = plane_variant_for(c->N, f32, nsys, c->opts.autotune != 0);
+  *variant = v;
+  int nt = 0, pd = 0;
+  plane_variant_shape(c->N, v, &nt, &pd);
+  if (threads) *threads = nt;
+  if (pad) *pad = pd;
+  if (us) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(c->N, f32 ? 1 : 0, tune_bucket(nsys)));
+    for (int i = 0; i < 4; ++i) us[i] = it == g_tune.end() ? 0.0 : it->second.us[i];
+  }
+  return LGW_OK;
+}
 
 void lgw_free(lgw_ctx* c) {
   if (!c) return;

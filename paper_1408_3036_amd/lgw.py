@@ -37,7 +37,7 @@ class Opts(C.Structure):
                 ("mem", C.c_int), ("stream", C.c_void_p), ("mem_budget_gb", C.c_double),
                 ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("use_graph", C.c_int),
                 ("precond_shift", C.c_double), ("imag_form", C.c_int), ("multishift", C.c_int),
-                ("model", C.c_int)]
+                ("model", C.c_int), ("autotune", C.c_int)]
 
 
 class Info(C.Structure):
@@ -91,6 +91,7 @@ def load_library():
     lib.lgw_hpsi_noalloc.argtypes = [P, I, c128, P, P]
     lib.lgw_sigma_traces.argtypes = [P, I, C.c_double, C.c_double, I, P, I, P, P, P, P]
     lib.lgw_sigma_residues.argtypes = [P, I, C.c_double, I, P, P]
+    lib.lgw_tune_info.argtypes = [P, I, I, P, P, P, P]
     lib.lgw_vhalf.argtypes = [P, I, P, P]
     lib.lgw_get_info.argtypes = [P, C.POINTER(Info)]
     lib.lgw_sphere.argtypes = [P, C.POINTER(I)]
@@ -103,7 +104,7 @@ def load_library():
     lib.lgw_free.restype = None
     for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_block_lanczos",
                  "lgw_chi0_apply_many", "lgw_chi0_apply_vjp", "lgw_hpsi", "lgw_hpsi_noalloc",
-                 "lgw_sigma_traces", "lgw_sigma_residues",
+                 "lgw_sigma_traces", "lgw_sigma_residues", "lgw_tune_info",
                  "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats", "lgw_profile",
                  "lgw_kernel_timing"]:
         getattr(lib, name).restype = I
@@ -136,7 +137,8 @@ class Lgw:
                  inner_tol: float | None = None, max_sweeps: int | None = None,
                  use_graph: bool | None = None, precond: bool | None = None,
                  precond_shift: float | None = None, imag_form: str | None = None,
-                 multishift: bool | None = None, model: bool | None = None):
+                 multishift: bool | None = None, model: bool | None = None,
+                 autotune: bool | None = None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -170,6 +172,8 @@ class Lgw:
             opts.multishift = int(multishift)
         if model is not None:
             opts.model = int(model)
+        if autotune is not None:
+            opts.autotune = int(autotune)
         self.opts = opts
         V = self._dev(V, torch.float64).reshape(-1)
         psi = self._dev(psi, torch.complex128).reshape(len(eps), -1)
@@ -358,6 +362,14 @@ class Lgw:
             self.ctx, int(e), float(delta), float(alpha), Q.shape[0], Q.data_ptr(), len(w),
             w.ctypes.data, sN.ctypes.data, sN0.ctypes.data, sA.ctypes.data))
         return sN, sN0, float(sA[0])
+
+    def tune_info(self, precision: str, nsys: int) -> dict:
+        """Plane-pass tile variant used for nsys systems (lgw_tune_info)."""
+        v, nt, pd = C.c_int(0), C.c_int(0), C.c_int(0)
+        us = (C.c_double * 4)()
+        self._check(self.lib.lgw_tune_info(self.ctx, {"fp64": 0, "mixed": 1}[precision], int(nsys),
+                                           C.byref(v), C.byref(nt), C.byref(pd), us))
+        return {"variant": v.value, "threads": nt.value, "padded_rows": pd.value, "us": list(us)}
 
     def sigma_residues(self, e: int, delta: float, k_p: int = 4):
         """Residue term Sigma_P of state e (lgw_sigma_residues): (Sigma_P, n_poles)."""

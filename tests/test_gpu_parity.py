@@ -632,3 +632,58 @@ def test_model_operator_matches_oracle(sysc1, prec):
             lg.lanczos_loss_vjp(torch.from_numpy(q0), 4, [0.5j])
     finally:
         lg.close()
+
+
+def test_plane_autotune_variants_agree_and_are_measured(sysc1):
+    """The plane pass's tile variants (chosen by the autotuner per grid,
+    precision and batch size) compute the same values: chi0 with the tuned
+    variants equals chi0 with the fixed one bitwise, and the tuner's table
+    holds a measurement for every variant with the fastest one chosen."""
+    from paper_1408_3036_amd import Lgw
+    w, b, s, _ = sysc1
+    x = random_potentials(w.N, 2, 15)
+    zs = [0.0, 0.3j]
+    out = {}
+    for tune in (False, True):
+        lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps, autotune=tune)
+        try:
+            out[tune] = lg.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+            if tune:
+                for n in (4, 100, 1000):
+                    info = lg.tune_info("fp64", n)
+                    print(f"plane variants for {n} systems: {info}")
+                    assert all(u > 0 for u in info["us"])
+                    assert info["us"][info["variant"]] == min(info["us"])
+        finally:
+            lg.close()
+    assert np.array_equal(out[True], out[False])
+
+
+def test_plane_autotune_cache_file(tmp_path):
+    """LGW_TUNE_CACHE: the first process measures and appends its table to the
+    file, a second process reads it and measures nothing new."""
+    import subprocess
+    import sys
+    import textwrap
+    cache = tmp_path / "tune.txt"
+    code = textwrap.dedent(f"""
+        import sys, torch
+        sys.path.insert(0, {str(__import__('os').path.dirname(__import__('os').path.dirname(__file__)))!r})
+        from paper_1408_3036_amd import Lgw
+        from synthetic import make_workload
+        w = make_workload(1)
+        lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps)
+        print(lg.tune_info("fp64", 100)["us"])
+        lg.close()
+    """)
+    env = dict(__import__("os").environ, LGW_TUNE_CACHE=str(cache))
+    r1 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r1.returncode == 0, r1.stderr
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 4 and all(l.startswith("plane 16 0 ") for l in lines)
+    r2 = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r2.returncode == 0, r2.stderr
+    assert cache.read_text().splitlines() == lines           # nothing new measured
+    first = eval(r1.stdout.strip().splitlines()[-1])       # the measured table (full precision)
+    second = eval(r2.stdout.strip().splitlines()[-1])      # read back from the file (3 decimals)
+    assert np.allclose(first, second, rtol=0, atol=6e-4)
