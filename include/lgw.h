@@ -106,8 +106,9 @@ typedef struct {
                           per process at the first set-up with a grid (a few
                           tens of ms), and with the environment variable
                           LGW_TUNE_CACHE naming a file it is read from and
-                          appended to that file.  Every variant computes the
-                          same values.  0: a fixed variant                    */
+                          appended to that file.  The variants compute the
+                          same transform and agree to rounding.  0: a fixed
+                          variant                                             */
 } lgw_opts;
 
 /* Fill *opts with the defaults listed above. */

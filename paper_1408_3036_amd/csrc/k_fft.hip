@@ -134,13 +134,17 @@ __device__ __forceinline__ T zblock_sum(T v, T* sm) {
   return (sm[0] + sm[1]) + (sm[2] + sm[3]);
 }
 
-template <typename T, int N, bool DOT>
+// MODE 0: plain; 1: CG step work (CgDot); 2: projector coefficients of the
+// stored Y per column workgroup (ProjPart, at most 8 bands).
+template <typename T, int N, int MODE>
 __global__ void __launch_bounds__(256)
 k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, long ldt, T scale,
        const cplx<T>* __restrict__ X, long ldx, const cplx<T>* __restrict__ shift,
        const cplx<T>* __restrict__ E, long lde, const T* __restrict__ ecoef,
        cplx<T>* __restrict__ Y, long ldy, const int* __restrict__ act, const T* __restrict__ dout,
-       CgDot<T> cd) {
+       CgDot<T> cd, ProjPart<T> pp) {
+  constexpr bool DOT = MODE == 1;
+  constexpr bool PDOT = MODE == 2;
   constexpr int LDZ = skew(N) + 1;
   __shared__ cplx<T> buf[kZCols * LDZ];
   __shared__ cplx<T> tws[N];
@@ -169,6 +173,11 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
   const T ec = ecoef ? ecoef[sys] : T(0);
   const cplx<T>* Ps = DOT ? cd.p + (long)sys * cd.ldp : nullptr;
   T pap = T(0);
+  cplx<T> pc[8];
+  if constexpr (PDOT) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) pc[u] = cplx<T>{0, 0};
+  }
   for (int i = cs[0] + threadIdx.x; i < cs[nc]; i += 256) {
     int lo = 0, hi = nc;
     while (hi - lo > 1) {
@@ -188,6 +197,31 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
     if (dout) v = dout[i] * v;
     Ys[i] = v;
     if constexpr (DOT) pap += pv.x * v.x + pv.y * v.y;
+    if constexpr (PDOT) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (u < pp.nv) pc[u] = pc[u] + cmulc(pp.Phi[(long)u * pp.ldphi + i], v);
+    }
+  }
+  if constexpr (PDOT) {
+    // the workgroup's sums: over each wave by shuffles, then over the 4 waves
+    __shared__ cplx<T> red[4][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        pc[u].x += __shfl_xor(pc[u].x, o, 64);
+        pc[u].y += __shfl_xor(pc[u].y, o, 64);
+      }
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) red[threadIdx.x >> 6][u] = pc[u];
+    }
+    __syncthreads();
+    if (threadIdx.x < 8)
+      pp.part[((long)blockIdx.y * gridDim.x + blockIdx.x) * 8 + threadIdx.x] =
+          (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
   }
   if constexpr (DOT) {
     __shared__ T smd[4];
@@ -216,7 +250,7 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
 // sphere columns back, so the plane is never cleared, scattered or gathered
 // in LDS; the y-filter reads and writes only the 2 hy + 1 data rows at its
 // ends.  Tile variants (chosen per grid, precision and batch size by the
-// library's autotuner; every variant computes the same values):
+// library's autotuner; the same transform, equal to rounding):
 //   NT   threads per workgroup;
 //   PAD  rows of N + 1 elements with the y-stages' threads on consecutive
 //        rows (distinct LDS banks for every access), else rows of N
@@ -454,15 +488,19 @@ template <typename T>
 void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, T scale,
                  const cplx<T>* X, long ldx, const cplx<T>* shift, const cplx<T>* E, long lde,
                  const T* ecoef, cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s,
-                 const T* dout, const CgDot<T>& cd) {
+                 const T* dout, const CgDot<T>& cd, const ProjPart<T>* pp) {
   if (nsys <= 0) return;
   dim3 grid(zcol_blocks(g), nsys);
+  const ProjPart<T> pq = pp ? *pp : ProjPart<T>{};
   if (cd.part) {
-    LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_, true><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E, lde,
-                                                                 ecoef, Y, ldy, act, dout, cd)));
+    LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_, 1><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E, lde,
+                                                              ecoef, Y, ldy, act, dout, cd, pq)));
+  } else if (pq.part) {
+    LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_, 2><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E, lde,
+                                                              ecoef, Y, ldy, act, dout, cd, pq)));
   } else {
-    LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_, false><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E,
-                                                                  lde, ecoef, Y, ldy, act, dout, cd)));
+    LGW_DISPATCH_N(g.N, (k_zfwd<T, NN_, 0><<<grid, 256, 0, s>>>(g, tw, Tb, ldt, scale, X, ldx, shift, E, lde,
+                                                              ecoef, Y, ldy, act, dout, cd, pq)));
   }
 }
 
@@ -513,7 +551,8 @@ void launch_zfull_mul(int N, const cplx<T>* tw, cplx<T>* G, long ldg, const T* m
                                    int, hipStream_t, int);                                            \
   template void launch_zfwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, T, const cplx<T>*,  \
                                long, const cplx<T>*, const cplx<T>*, long, const T*, cplx<T>*, long,  \
-                               const int*, int, hipStream_t, const T*, const CgDot<T>&);              \
+                               const int*, int, hipStream_t, const T*, const CgDot<T>&,               \
+                               const ProjPart<T>*);                                                   \
   template void launch_plane_pair_fwd<T>(const Geom&, const cplx<T>*, const cplx<T>*, int,            \
                                          const cplx<T>*, long, int, cplx<T>*, long, hipStream_t);     \
   template void launch_plane_acc<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, const cplx<T>*, \

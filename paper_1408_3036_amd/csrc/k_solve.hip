@@ -1584,6 +1584,41 @@ k_ms_dot(const z64* __restrict__ Q, const z64* __restrict__ AQ, long ldq, int np
   if (threadIdx.x == 0) part[blockIdx.y * kMsSplit + blockIdx.x] = acc[0];
 }
 
+// The projection of the step's product folded in: C_v = sum over the column
+// workgroups of ppart (left by the last transform), A q_j = Y - sum_v C_v
+// Phi_v stored back in place, and part[slot][blk] = the slice's share of
+// Re <q_j, A q_j> (what k_ms_dot leaves).
+__global__ void __launch_bounds__(NT)
+k_ms_proj_dot(const z64* __restrict__ Q, z64* __restrict__ AQ, long ldq, int npw, int j,
+              const int* __restrict__ act, const z64* __restrict__ Phi, long ldphi, int nv,
+              const z64* __restrict__ ppart, int nblk, double* __restrict__ part) {
+  __shared__ double sm[NT / 64];
+  __shared__ z64 C[8];
+  const int slot = blockIdx.y, s = act[slot];
+  if (threadIdx.x < 8) {
+    z64 a{0, 0};
+    if (threadIdx.x < nv)
+      for (int b = 0; b < nblk; ++b) a = a + ppart[((long)slot * nblk + b) * 8 + threadIdx.x];
+    C[threadIdx.x] = a;
+  }
+  __syncthreads();
+  int i0, i1;
+  ms_slice(npw, i0, i1);
+  const z64* q = Q + (long)s * ldq + (long)j * npw;
+  z64* aq = AQ + (long)s * ldq + (long)j * npw;
+  double acc[1] = {0.0};
+  for (int i = i0 + threadIdx.x; i < i1; i += NT) {
+    z64 y = aq[i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (u < nv) y = y - C[u] * Phi[(long)u * ldphi + i];
+    aq[i] = y;
+    acc[0] += q[i].x * y.x + q[i].y * y.y;
+  }
+  block_sum<double, 1>(acc, sm);
+  if (threadIdx.x == 0) part[blockIdx.y * kMsSplit + blockIdx.x] = acc[0];
+}
+
 // alpha_j from the partials; w into Q[s][j+1]; part2[slot][blk] = the slice's |w|^2
 __global__ void __launch_bounds__(NT)
 k_ms_upd(z64* __restrict__ Q, const z64* __restrict__ AQ, long ldq, int npw, int j, const int* __restrict__ act,
@@ -1767,13 +1802,16 @@ void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, lo
 
 int ms_step_scratch(int na) { return 2 * na * kMsSplit; }
 
-void launch_ms_step(z64* Q, const z64* AQ, long ldq, int npw, int j, const int* act, int na, double* alpha,
-                    double* beta, int kcap, double* scratch, hipStream_t s) {
+void launch_ms_step(z64* Q, z64* AQ, long ldq, int npw, int j, const int* act, int na, double* alpha,
+                    double* beta, int kcap, double* scratch, hipStream_t s, const ProjPart<double>* pp, int nblk) {
   if (na <= 0) return;
   const dim3 grid(kMsSplit, na);
   double* part = scratch;
   double* part2 = scratch + (size_t)na * kMsSplit;
-  k_ms_dot<<<grid, NT, 0, s>>>(Q, AQ, ldq, npw, j, act, part);
+  if (pp && pp->part)
+    k_ms_proj_dot<<<grid, NT, 0, s>>>(Q, AQ, ldq, npw, j, act, pp->Phi, pp->ldphi, pp->nv, pp->part, nblk, part);
+  else
+    k_ms_dot<<<grid, NT, 0, s>>>(Q, AQ, ldq, npw, j, act, part);
   k_ms_upd<<<grid, NT, 0, s>>>(Q, AQ, ldq, npw, j, act, part, part2, alpha, beta, kcap);
   k_ms_norm<<<grid, NT, 0, s>>>(Q, ldq, npw, j, act, part2, beta, kcap);
 }

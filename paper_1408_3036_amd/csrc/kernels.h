@@ -39,6 +39,18 @@ struct ProjFeed {
 
 bool grid_supported(int N);
 
+// Projector coefficients formed by the last transform (zfwd) as it stores
+// Y: part[(slot * nblk + blk) * 8 + v] = sum over the column workgroup blk
+// of conj(Phi_v) Y, v < nv <= 8 (nblk = zcol_blocks(g)); the multi-shift step
+// then applies Y - Phi C with C the sum of the blocks.  part == null: off.
+template <typename T>
+struct ProjPart {
+  const cplx<T>* Phi = nullptr;
+  long ldphi = 0;
+  int nv = 0;
+  cplx<T>* part = nullptr;
+};
+
 // CG step work done by the last transform of an operator application: per
 // column workgroup k of active slot j, part[j * nblk + k] = the block's
 // Re p^H y of its store y with the given vectors p (the directions where the
@@ -86,7 +98,8 @@ void launch_zfwd(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt, 
                  const cplx<T>* E, long lde, const T* ecoef,
                  cplx<T>* Y, long ldy, const int* act, int nsys, hipStream_t s,
                  const T* dout = nullptr,     // optional per-plane-wave scaling of Y
-                 const CgDot<T>& cd = {});     // optional CG dot products (CgDot)
+                 const CgDot<T>& cd = {},     // optional CG dot products (CgDot)
+                 const ProjPart<T>* pp = nullptr);   // optional projector coefficients (ProjPart)
 // column workgroups of the column passes (one run of the sphere vector each)
 int zcol_blocks(const Geom& g);
 // Tb[j*nv+v][z][c] = FFT_xy(U[v][z] * X[j][z]) at the column positions (unscaled)
@@ -258,10 +271,13 @@ void launch_model_div(const z64* B, int npw, const double* kin, const double* ep
                       int nz, z64* F, hipStream_t s);
 void launch_ms_init(const z64* B, long ldb, const int* bidx, int npw, z64* Q, long ldq, double* nrm, int nsys,
                     hipStream_t s);
-// scratch needs ms_step_scratch(na) doubles
+// scratch needs ms_step_scratch(na) doubles.  With pp (projector
+// coefficients the last transform left over nblk column workgroups), AQ[s][j]
+// holds the unprojected product on entry and is projected in place first.
 int ms_step_scratch(int na);
-void launch_ms_step(z64* Q, const z64* AQ, long ldq, int npw, int j, const int* act, int na, double* alpha,
-                    double* beta, int kcap, double* scratch, hipStream_t s);
+void launch_ms_step(z64* Q, z64* AQ, long ldq, int npw, int j, const int* act, int na, double* alpha,
+                    double* beta, int kcap, double* scratch, hipStream_t s, const ProjPart<double>* pp = nullptr,
+                    int nblk = 0);
 // X[s][t] = Q[s] y and res[s * ntp + t] = |b - AQ[s] y + tau_t X[s][t]|^2 with
 // y = Y[s][.][t], b = B[bidx[s]]; part needs nsys * ntp * ms_res_tiles(npw)
 // entries (rows t >= ntau of res are zero)

@@ -354,8 +354,8 @@ void upload(lgw_ctx* c, DevBuf& b, const std::vector<T>& h) {
 }
 
 // ---- plane-pass autotuner ---------------------------------------------------
-// The plane pass has tile variants (threads per workgroup, row layout; every
-// variant computes the same values).  The best one per (grid, precision,
+// The plane pass has tile variants (threads per workgroup, row layout; the
+// same transform, equal to rounding).  The best one per (grid, precision,
 // batch-size bucket) is measured once per process, at the first set-up of a
 // context with that grid, on a zero-filled column buffer of a representative
 // batch, and kept in this table; with LGW_TUNE_CACHE set to a file name the
@@ -390,7 +390,7 @@ template <class T>
 void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const cplx<T>* shift,
             const cplx<T>* E, long lde, const T* ecoef, cplx<T>* Tb, const int* act, int nsys,
             const T* dout = nullptr, const ProjFeed<T>* fed = nullptr, const cplx<T>* D = nullptr,
-            cplx<T>* Xw = nullptr, const CgDot<T>* cd = nullptr) {
+            cplx<T>* Xw = nullptr, const CgDot<T>* cd = nullptr, const ProjPart<T>* pp = nullptr) {
   const long ldt = (long)c->N * c->ncols;
   const double e = 2.0 * sizeof(T);   // bytes of one complex value
   const double cols = (double)nsys * c->N * c->ncols, sph = (double)nsys * c->npw;
@@ -407,7 +407,7 @@ void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const 
   c->end(t1, pk + LGW_K_PLANE_HV, e * 2.0 * cols + sizeof(T) * (double)c->n3);
   hipEvent_t t2 = c->begin(nsys);
   launch_zfwd<T>(c->geom, tw_of<T>(c), Tb, ldt, T(1.0 / (double)c->n3), X, ldx, shift, E, lde, ecoef, Y, ldy,
-                 act, nsys, c->stream, dout, cd ? *cd : CgDot<T>{});
+                 act, nsys, c->stream, dout, cd ? *cd : CgDot<T>{}, pp);
   c->end(t2, pk + LGW_K_ZFWD, e * (cols + (E ? 3.0 : 2.0) * sph));
   c->tot_h += nsys;
 }
@@ -920,7 +920,11 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
     // Systems the FP32 sweeps could not bring to the tolerance (an inner
     // solve that stagnates or breaks down on a nearly singular system) get an
     // FP64 correction on their true residual: solve A e = R in FP64 to
-    // tol |b| / |R| and x += e; judged by the combined residual.
+    // tol |b| / |R| and x += e; judged by the combined residual.  The
+    // correction runs unpreconditioned (the plain projected Krylov solve of
+    // Sec. III.A): with the kinetic scaling, rounding in the scaled operator's
+    // null space (the scaled valence directions) has broken down such a
+    // correction for the highest valence band at 72^3.
     std::vector<int> fail;
     for (int s = 0; s < nsys; ++s)
       if (out.rel[s] > 10 * tol) fail.push_back(s);
@@ -953,10 +957,15 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
         struct OptScope {
           lgw_ctx* c;
           lgw_opts saved;
-          ~OptScope() { c->opts = saved; }
+          ~OptScope() {
+            c->drop_graphs();
+            c->opts = saved;
+          }
         } scope{c, c->opts};
         c->opts.precision = LGW_FP64;
+        c->opts.precond = 0;
         c->opts.tol = rtol;
+        c->drop_graphs();   // graphs captured with the preconditioner bake in its buffers
         solve(c, kind, Rf, ident, fsh, fw2, Ef, so);
       }
       // the inner call reused this call's workspace: X and the host copies stand
@@ -1066,6 +1075,16 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     z64* Q = c->buf<z64>("ms.Q", (size_t)n * ldq);
     z64* AQ = c->buf<z64>("ms.AQ", (size_t)n * ldq);   // A q_j as applied, for the true residuals
     double* mscratch = c->buf<double>("ms.scr", ms_step_scratch(n));
+    // up to 8 bands: the projector folded into the steps (ProjPart)
+    const bool fold = !c->no_proj && nv <= 8;
+    const int nblk = zcol_blocks(c->geom);
+    ProjPart<double> pp;
+    if (fold) {
+      pp.Phi = c->d_Phi.as<z64>();
+      pp.ldphi = npw;
+      pp.nv = nv;
+      pp.part = c->buf<z64>("ms.ppart", (size_t)n * nblk * 8);
+    }
     double* alpha = c->buf<double>("ms.al", (size_t)n * kcap);
     double* beta = c->buf<double>("ms.be", (size_t)n * kcap);
     double* nrm = c->buf<double>("ms.nrm", n);
@@ -1102,9 +1121,17 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
       const int na = (int)act.size();
       const int steps = std::min(check, kcap - j);
       for (int t = 0; t < steps; ++t, ++j) {
-        apply_op<double>(c, K_CGLIN, Q + (size_t)j * npw, AQ + (size_t)j * npw, nullptr, Tb, ldq, d_sh,
-                         nullptr, d_act, na);
-        launch_ms_step(Q, AQ, ldq, npw, j, d_act, na, alpha, beta, kcap, mscratch, c->stream);
+        if (fold) {
+          // the projection of A q_j folded into the transform (coefficients)
+          // and the recursion step (the update): no projector launches
+          happly<double>(c, Q + (size_t)j * npw, ldq, AQ + (size_t)j * npw, ldq, d_sh, nullptr, 0, nullptr, Tb, d_act,
+                         na, nullptr, nullptr, nullptr, nullptr, nullptr, &pp);
+          launch_ms_step(Q, AQ, ldq, npw, j, d_act, na, alpha, beta, kcap, mscratch, c->stream, &pp, nblk);
+        } else {
+          apply_op<double>(c, K_CGLIN, Q + (size_t)j * npw, AQ + (size_t)j * npw, nullptr, Tb, ldq, d_sh,
+                           nullptr, d_act, na);
+          launch_ms_step(Q, AQ, ldq, npw, j, d_act, na, alpha, beta, kcap, mscratch, c->stream);
+        }
       }
       c->check_launch();
       readback(c, {{ha.data(), alpha, ha.size() * sizeof(double)}, {hb.data(), beta, hb.size() * sizeof(double)}});

@@ -636,9 +636,11 @@ def test_model_operator_matches_oracle(sysc1, prec):
 
 def test_plane_autotune_variants_agree_and_are_measured(sysc1):
     """The plane pass's tile variants (chosen by the autotuner per grid,
-    precision and batch size) compute the same values: chi0 with the tuned
-    variants equals chi0 with the fixed one bitwise, and the tuner's table
-    holds a measurement for every variant with the fastest one chosen."""
+    precision and batch size) compute the same transform: chi0 with the tuned
+    variants equals chi0 with the fixed one to rounding (the compiler may
+    contract the butterflies' products differently per variant), and the
+    tuner's table holds a measurement for every variant with the fastest one
+    chosen."""
     from paper_1408_3036_amd import Lgw
     w, b, s, _ = sysc1
     x = random_potentials(w.N, 2, 15)
@@ -656,7 +658,7 @@ def test_plane_autotune_variants_agree_and_are_measured(sysc1):
                     assert info["us"][info["variant"]] == min(info["us"])
         finally:
             lg.close()
-    assert np.array_equal(out[True], out[False])
+    assert colwise_rel(out[True].reshape(-1, w.N ** 3), out[False].reshape(-1, w.N ** 3)) < 1e-13
 
 
 def test_plane_autotune_cache_file(tmp_path):
