@@ -128,6 +128,54 @@ def cpu_baseline(w, zs_sample, xs, cores):
     return np.array([r[0] for r in res]), wall, sum(r[1] for r in res)
 
 
+def rocpd_counters(db: str, pattern: str):
+    """Per dispatch of the kernels whose name contains `pattern` in a
+    rocprofv3 results database: {dispatch_id: (systems, {counter: value},
+    duration_ns)}; systems is the grid's y extent (the system count of the
+    batched launches)."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    out = {}
+    for disp, name, gy, cname, val, dur in con.execute(
+            "select dispatch_id, kernel_name, grid_size_y, counter_name, value, duration "
+            "from counters_collection"):
+        if pattern not in name:
+            continue
+        ent = out.setdefault(disp, [int(gy), {}, dur])
+        ent[1][cname] = ent[1].get(cname, 0.0) + float(val)
+    return out
+
+
+def summarise_traffic(fetch_db, write_db, calib_fetch_db, calib_write_db, kernel, model_per_system,
+                      model_fixed, min_systems=16):
+    """HBM bytes per system of `kernel` from FETCH_SIZE and WRITE_SIZE runs
+    (KiB per dispatch), each scaled by the factor that makes the same counter
+    read 1 GiB for a plain 1 GiB device copy (bench.py --calib-copy); only
+    dispatches of at least min_systems systems are averaged.  The bytes read
+    once per launch (model_fixed: the potential plane) are taken off each
+    dispatch's scaled fetch before the division, so the per-system figures
+    compare with model_per_system alone."""
+    def totals(db, cname):
+        rows = [(g, c[cname]) for g, c, _ in rocpd_counters(db, kernel).values() if cname in c and g >= min_systems]
+        return sum(v for _, v in rows) * 1024.0, sum(g for g, _ in rows), len(rows)
+
+    def calib(db, cname):
+        rows = [c[cname] for g, c, _ in rocpd_counters(db, "copyBuffer").values() if cname in c]
+        rows = rows or [c[cname] for g, c, _ in rocpd_counters(db, "").values() if cname in c]
+        return (1 << 30) / (max(rows) * 1024.0)
+    cf, cw = calib(calib_fetch_db, "FETCH_SIZE"), calib(calib_write_db, "WRITE_SIZE")
+    F, sf, nf = totals(fetch_db, "FETCH_SIZE")
+    W, sw, nw = totals(write_db, "WRITE_SIZE")
+    f = (F * cf - nf * model_fixed) / sf
+    w = W * cw / sw
+    return {"kernel": kernel, "dispatches": [nf, nw], "systems": [sf, sw],
+            "fetch_bytes_per_system": round(f), "write_bytes_per_system": round(w),
+            "hbm_bytes_per_system": round(f + w),
+            "calibration": {"fetch_scale": cf, "write_scale": cw},
+            "model_bytes_per_system": model_per_system, "model_bytes_fixed": model_fixed,
+            "counters_over_model": round((f + w) / model_per_system, 3)}
+
+
 def bench_large72(log_fn):
     """The large-molecule workload at its shape: block Lanczos, 8-vector blocks
     to 256 vectors, then eps(z) - 1 on that basis at the 32 imaginary
@@ -303,11 +351,57 @@ def main():
                     help="skip the frequency-recycling measurement beside the headline mode")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarise-traffic", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="print the plane pass's HBM traffic summary from rocprofv3 --pmc databases")
+    ap.add_argument("--counter-summary", nargs="+", metavar="DB_THEN_PATTERNS",
+                    help="print per-kernel means of a rocprofv3 --pmc database (kernel-name substrings follow)")
     ap.add_argument("--mixed-tol", type=float, default=1e-10,
                     help="relative residual tolerance of every solve in the mixed-precision path")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the large-72, uneven-batch and self-energy measurements beside the headline")
     args = ap.parse_args()
+    if args.summarise_traffic:
+        # profiles/traffic_silane48.json from four rocprofv3 databases:
+        # FETCH_SIZE and WRITE_SIZE of the bench, then of the 1 GiB copy
+        from synthetic import make_workload
+        fdb, wdb, cfdb, cwdb = args.summarise_traffic
+        w = make_workload(2, with_ground_state=False)
+        N = w.N
+        m = np.arange(-N // 2 + 1, N // 2)
+        kxy = 0.5 * (2 * np.pi / w.L) ** 2 * (m[:, None] ** 2 + m[None, :] ** 2)
+        ncols = int(np.count_nonzero(kxy <= w.ecut))      # z-columns holding plane waves
+        rec = {"source_hash": kernel_source_hash(), "workload": "silane-48",
+               "kernels": {"plane_hv_f64": summarise_traffic(fdb, wdb, cfdb, cwdb, "k_plane_hv<double",
+                                                             16.0 * 2 * N * ncols, 8.0 * N ** 3)},
+               "model": "plane pass per system: e 2 N ncols (the columns read and written once); "
+                        "the potential plane (8 N^3 per launch) once per launch"}
+        print(json.dumps(rec, indent=1))
+        return
+    if args.counter_summary:
+        # per-kernel means of every counter in a rocprofv3 --pmc database
+        db = args.counter_summary[0]
+        pats = args.counter_summary[1:] or [""]
+        import collections
+        for pat in pats:
+            rows = rocpd_counters(db, pat)
+            import sqlite3
+            names = {}
+            con = sqlite3.connect(db)
+            for disp, name in con.execute("select dispatch_id, kernel_name from counters_collection"):
+                names[disp] = name
+            by = collections.defaultdict(list)
+            for disp, (gy, cs, dur) in rows.items():
+                import re
+                mk = re.search(r"(k_\w+(<[^()]*>)?)", names[disp])
+                by[mk.group(1) if mk else names[disp][:60]].append((gy, cs, dur))
+            for kname, lst in sorted(by.items(), key=lambda t: -sum(x[2] for x in t[1])):
+                cn = sorted(set(c for _, cs, _ in lst for c in cs))
+                line = {c: sum(cs.get(c, 0.0) for _, cs, _ in lst) / len(lst) for c in cn}
+                print(f"{kname}: dispatches {len(lst)}, mean systems {sum(g for g, _, _ in lst) / len(lst):.1f}, "
+                      f"mean duration {sum(d for _, _, d in lst) / len(lst) / 1e3:.2f} us")
+                for c in cn:
+                    print(f"    {c:32s} {line[c]:.6g} per dispatch")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
