@@ -371,14 +371,15 @@ k_plane_acc(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ 
 // -------------------------------------------------------------- plane_full
 template <typename T, int N, int SIGN>
 __global__ void __launch_bounds__(plane_threads<N>())
-k_plane_full(const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ G, long ldg) {
+k_plane_full(const cplx<T>* __restrict__ tw, cplx<T>* G, long ldg, const cplx<T>* src) {
   constexpr int NT = plane_threads<N>();
   constexpr long NN = (long)N * N;
   __shared__ cplx<T> pl[N * N];
   __shared__ cplx<T> tws[N];
   cplx<T>* Gz = G + (long)blockIdx.y * ldg + blockIdx.x * NN;
+  const cplx<T>* Sz = src ? src + (long)blockIdx.y * ldg + blockIdx.x * NN : Gz;
   load_tw<T, N>(tws, tw);
-  for (int i = threadIdx.x; i < N * N; i += NT) pl[i] = Gz[i];
+  for (int i = threadIdx.x; i < N * N; i += NT) pl[i] = Sz[i];
   __syncthreads();
   fft_lds<T, N, SIGN, NT, N, false>(pl, tws, N, [](int t, int e) { return t * N + e; });
   fft_lds<T, N, SIGN, NT, N, true>(pl, tws, N, [](int t, int e) { return e * N + t; });
@@ -524,13 +525,14 @@ void launch_plane_acc(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long 
 }
 
 template <typename T>
-void launch_plane_full(int N, const cplx<T>* tw, cplx<T>* G, long ldg, int nvec, int sign, hipStream_t s) {
+void launch_plane_full(int N, const cplx<T>* tw, cplx<T>* G, long ldg, int nvec, int sign, hipStream_t s,
+                       const cplx<T>* src) {
   if (nvec <= 0) return;
   dim3 grid(N, nvec);
   if (sign < 0) {
-    LGW_DISPATCH_N(N, (k_plane_full<T, NN_, -1><<<grid, plane_threads<NN_>(), 0, s>>>(tw, G, ldg)));
+    LGW_DISPATCH_N(N, (k_plane_full<T, NN_, -1><<<grid, plane_threads<NN_>(), 0, s>>>(tw, G, ldg, src)));
   } else {
-    LGW_DISPATCH_N(N, (k_plane_full<T, NN_, +1><<<grid, plane_threads<NN_>(), 0, s>>>(tw, G, ldg)));
+    LGW_DISPATCH_N(N, (k_plane_full<T, NN_, +1><<<grid, plane_threads<NN_>(), 0, s>>>(tw, G, ldg, src)));
   }
 }
 
@@ -557,7 +559,8 @@ void launch_zfull_mul(int N, const cplx<T>* tw, cplx<T>* G, long ldg, const T* m
                                          const cplx<T>*, long, int, cplx<T>*, long, hipStream_t);     \
   template void launch_plane_acc<T>(const Geom&, const cplx<T>*, const cplx<T>*, long, const cplx<T>*, \
                                     int, cplx<T>*, long, T, int, bool, hipStream_t);                  \
-  template void launch_plane_full<T>(int, const cplx<T>*, cplx<T>*, long, int, int, hipStream_t);     \
+  template void launch_plane_full<T>(int, const cplx<T>*, cplx<T>*, long, int, int, hipStream_t,       \
+                                     const cplx<T>*);                                                 \
   template void launch_zfull_mul<T>(int, const cplx<T>*, cplx<T>*, long, const T*, T, int, hipStream_t);
 
 LGW_INST(double)

@@ -428,7 +428,7 @@ k_resid(const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx,
 }
 
 // the same over ns workgroups per system (grid (ns, nsys)): res[sys][blk] are
-// the slice norms, summed by the caller
+// the slice norms, summed by the caller; AX null stands for zero (R = b)
 template <typename T>
 __global__ void __launch_bounds__(NT)
 k_resid_split(const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ bidx,
@@ -439,11 +439,11 @@ k_resid_split(const cplx<T>* __restrict__ b, long ldb, const int* __restrict__ b
   const int chunk = (npw + gridDim.x - 1) / gridDim.x;
   const int i0 = blockIdx.x * chunk, i1 = min(npw, i0 + chunk);
   const cplx<T>* bs = b + (long)(bidx ? bidx[sys] : sys) * ldb;
-  const cplx<T>* as = AX + (long)sys * lda;
+  const cplx<T>* as = AX ? AX + (long)sys * lda : nullptr;
   cplx<T>* rs = R ? R + (long)sys * ldr : nullptr;
   double acc[1] = {0.0};
   for (int i = i0 + threadIdx.x; i < i1; i += NT) {
-    const cplx<T> ri = bs[i] - as[i];
+    const cplx<T> ri = as ? bs[i] - as[i] : bs[i];
     if (rs) rs[i] = ri;
     acc[0] += (double)norm2(ri);
   }
@@ -480,6 +480,38 @@ __global__ void k_dots_final(const z64* __restrict__ partial, int nblk, z64* __r
   }
 }
 
+// One classical Gram-Schmidt pass after k_dots_partial: h_i = sum_b
+// partial[i][b] (summed in order by every workgroup, as k_dots_final does),
+// w = in - sum_i h_i A_i with in = src or w; workgroup 0 stores Re h_{m-1}
+// in re_last when given.  m <= kCgsMax.
+constexpr int kCgsMax = 512;
+__global__ void __launch_bounds__(NT)
+k_cgs_sub(const z64* __restrict__ A, long lda, int m, const z64* __restrict__ partial, int nblk, z64* w,
+          const z64* src, long n, double* __restrict__ re_last) {
+  __shared__ z64 hs[kCgsMax];
+  for (int i = threadIdx.x; i < m; i += NT) {
+    z64 s{0, 0};
+    for (int b = 0; b < nblk; ++b) s = s + partial[(long)i * nblk + b];
+    hs[i] = s;
+  }
+  __syncthreads();
+  if (re_last && blockIdx.x == 0 && threadIdx.x == 0) *re_last = hs[m - 1].x;
+  const z64* in = src ? src : w;
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
+    z64 acc = in[e];
+    for (int i = 0; i < m; ++i) acc = acc - hs[i] * A[(long)i * lda + e];
+    w[e] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_copy(const z64* __restrict__ a, z64* __restrict__ b, long n) {
+  for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) b[e] = a[e];
+}
+
+__global__ void k_re_of(const z64* __restrict__ h, double* __restrict__ out) {
+  if (threadIdx.x == 0) *out = h->x;
+}
+
 __global__ void __launch_bounds__(NT)
 k_gemv_sub(const z64* __restrict__ A, long lda, int m, const z64* __restrict__ h,
            z64* __restrict__ w, long n) {
@@ -499,22 +531,30 @@ __global__ void k_alpha_final(const z64* __restrict__ partial, int nblk, double*
 }
 
 __global__ void __launch_bounds__(NT)
-k_lanczos_sub(z64* __restrict__ w, const z64* __restrict__ q, const z64* __restrict__ qprev,
-              const double* __restrict__ alpha, const double* __restrict__ beta_prev, long n) {
+k_lanczos_sub(z64* w, const z64* __restrict__ q, const z64* __restrict__ qprev,
+              const double* __restrict__ alpha, const double* __restrict__ beta_prev, long n, const z64* src) {
   const double a = *alpha;
   const double b = beta_prev ? *beta_prev : 0.0;
+  const z64* in = src ? src : w;
   for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) {
-    z64 r = w[e] - a * q[e];
+    z64 r = in[e] - a * q[e];
     if (qprev) r = r - b * qprev[e];
     w[e] = r;
   }
 }
 
-__global__ void k_norm_final(const z64* __restrict__ partial, int nblk, double* __restrict__ out) {
+// *out = the norm; with pair, also pair[0] = *alpha and pair[1] = the norm
+// (a Lanczos step's two scalars side by side for one readback)
+__global__ void k_norm_final(const z64* __restrict__ partial, int nblk, double* __restrict__ out,
+                             const double* __restrict__ alpha, double* __restrict__ pair) {
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += partial[b].x;
     *out = sqrt(s);
+    if (pair) {
+      pair[0] = *alpha;
+      pair[1] = sqrt(s);
+    }
   }
 }
 
@@ -566,15 +606,17 @@ k_fill(cplx<T>* __restrict__ p, cplx<T> v, long n) {
   for (long e = (long)blockIdx.x * NT + threadIdx.x; e < n; e += (long)gridDim.x * NT) p[e] = v;
 }
 
-// x[sys] += scale[sys] * e[sys] (e in single precision)
+// x[sys] += scale[sys] * (d .* e[sys]) (e in single precision; d optional,
+// applied in single precision); assign: x[sys] = scale[sys] * (d .* e[sys])
 __global__ void __launch_bounds__(NT)
 k_cvt_32_64_axpy(const z32* __restrict__ e, z64* __restrict__ x, const double* __restrict__ scale,
-                 const int* __restrict__ act, long ld, int npw) {
+                 const int* __restrict__ act, long ld, int npw, const float* __restrict__ d, int assign) {
   const int sys = sys_of(act, blockIdx.y);
   const double s = scale[sys];
   for (int i = blockIdx.x * NT + threadIdx.x; i < npw; i += gridDim.x * NT) {
-    const z64 ev = cvt<double>(e[(long)sys * ld + i]);
-    x[(long)sys * ld + i] = x[(long)sys * ld + i] + s * ev;
+    const z32 e32 = e[(long)sys * ld + i];
+    const z64 ev = cvt<double>(d ? d[i] * e32 : e32);
+    x[(long)sys * ld + i] = assign ? s * ev : x[(long)sys * ld + i] + s * ev;
   }
 }
 
@@ -685,6 +727,21 @@ void launch_dots(const z64* A, long lda, int m, const z64* w, long n, z64* h, z6
   k_dots_final<<<m, 64, 0, s>>>(partial, kDotBlocks, h);
 }
 
+void launch_cgs_pass(const z64* A, long lda, int m, z64* w, const z64* src, long n, z64* h, z64* partial,
+                     double* re_last, hipStream_t s) {
+  if (m <= 0) return;
+  const z64* in = src ? src : w;
+  k_dots_partial<<<dim3(kDotBlocks, m), NT, 0, s>>>(A, lda, in, n, partial);
+  if (m <= kCgsMax) {
+    k_cgs_sub<<<blocks_for(n), NT, 0, s>>>(A, lda, m, partial, kDotBlocks, w, src, n, re_last);
+    return;
+  }
+  k_dots_final<<<m, 64, 0, s>>>(partial, kDotBlocks, h);
+  if (re_last) k_re_of<<<1, 64, 0, s>>>(h + m - 1, re_last);
+  if (src) k_copy<<<blocks_for(n), NT, 0, s>>>(src, w, n);
+  k_gemv_sub<<<blocks_for(n), NT, 0, s>>>(A, lda, m, h, w, n);
+}
+
 void launch_gemv_sub(const z64* A, long lda, int m, const z64* h, z64* w, long n, hipStream_t s) {
   if (m <= 0) return;
   k_gemv_sub<<<blocks_for(n), NT, 0, s>>>(A, lda, m, h, w, n);
@@ -696,13 +753,14 @@ void launch_lanczos_alpha(const z64* q, const z64* w, long n, double* alpha_j, z
 }
 
 void launch_lanczos_sub(z64* w, const z64* q, const z64* qprev, const double* alpha_j, const double* beta_prev,
-                        long n, hipStream_t s) {
-  k_lanczos_sub<<<blocks_for(n), NT, 0, s>>>(w, q, qprev, alpha_j, beta_prev, n);
+                        long n, hipStream_t s, const z64* src) {
+  k_lanczos_sub<<<blocks_for(n), NT, 0, s>>>(w, q, qprev, alpha_j, beta_prev, n, src);
 }
 
-void launch_norm(const z64* w, long n, double* out, z64* partial, hipStream_t s) {
+void launch_norm(const z64* w, long n, double* out, z64* partial, hipStream_t s, const double* alpha,
+                 double* pair) {
   k_dots_partial<<<dim3(kDotBlocks, 1), NT, 0, s>>>(w, 0, w, n, partial);
-  k_norm_final<<<1, 64, 0, s>>>(partial, kDotBlocks, out);
+  k_norm_final<<<1, 64, 0, s>>>(partial, kDotBlocks, out, alpha, pair);
 }
 
 void launch_scale_into(const z64* w, const double* nrm, z64* q, long n, hipStream_t s) {
@@ -744,9 +802,9 @@ template void launch_fill<double>(z64*, z64, long, hipStream_t);
 template void launch_fill<float>(z32*, z32, long, hipStream_t);
 
 void launch_cvt_32_64_axpy(const z32* e, z64* x, const double* scale, const int* act, long ld, int npw,
-                           int nsys, hipStream_t s) {
+                           int nsys, hipStream_t s, const float* d, bool assign) {
   if (nsys <= 0) return;
-  k_cvt_32_64_axpy<<<dim3((npw + NT - 1) / NT, nsys), NT, 0, s>>>(e, x, scale, act, ld, npw);
+  k_cvt_32_64_axpy<<<dim3((npw + NT - 1) / NT, nsys), NT, 0, s>>>(e, x, scale, act, ld, npw, d, assign ? 1 : 0);
 }
 
 void launch_xyz_to_zxy(int N, const z64* in, long ldi, z64* out, long ldo, int nvec, bool conj_in,
@@ -814,11 +872,13 @@ k_rows_out(const z64* __restrict__ src, long lds, z64* __restrict__ dst, long ld
 // out32[sys] = in64[sys] * inv[sys]
 __global__ void __launch_bounds__(256)
 k_scale_cvt(const z64* __restrict__ in, long ldi, z32* __restrict__ out, long ldo,
-            const double* __restrict__ scale, const int* __restrict__ act, int n) {
+            const double* __restrict__ scale, const int* __restrict__ act, int n, const float* __restrict__ d) {
   const int sys = sys_of(act, blockIdx.y);
   const double s = scale[sys];
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
-    out[(long)sys * ldo + i] = cvt<float>(s * in[(long)sys * ldi + i]);
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const z32 v = cvt<float>(s * in[(long)sys * ldi + i]);
+    out[(long)sys * ldo + i] = d ? d[i] * v : v;
+  }
 }
 
 // Y[yrow] = d * X[xrow] elementwise over the first n entries, row i of the
@@ -896,9 +956,9 @@ void launch_rows_out(const z64* src, long lds, z64* dst, long ldd, const int* di
 }
 
 void launch_scale_cvt(const z64* in, long ldi, z32* out, long ldo, const double* scale, const int* act, int n,
-                      int nsys, hipStream_t s) {
+                      int nsys, hipStream_t s, const float* d) {
   if (nsys <= 0) return;
-  k_scale_cvt<<<dim3((n + 255) / 256, nsys), 256, 0, s>>>(in, ldi, out, ldo, scale, act, n);
+  k_scale_cvt<<<dim3((n + 255) / 256, nsys), 256, 0, s>>>(in, ldi, out, ldo, scale, act, n, d);
 }
 
 template <typename T>
@@ -1773,19 +1833,23 @@ k_model_div(const z64* __restrict__ B, int npw, const double* __restrict__ kin, 
 }  // namespace
 
 namespace {
-__global__ void __launch_bounds__(256) k_sqrt_inv(const double* __restrict__ bb, double* __restrict__ r,
+// r = sqrt(|b|^2), ir = 1 / r, |b|^2 of system i the sum of its ns slice
+// norms bb[i][0..ns) in order
+__global__ void __launch_bounds__(256) k_sqrt_inv(const double* __restrict__ bb, int ns, double* __restrict__ r,
                                                   double* __restrict__ ir, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const double v = sqrt(bb[i]);
+  double t = 0.0;
+  for (int k = 0; k < ns; ++k) t += bb[(long)i * ns + k];
+  const double v = sqrt(t);
   r[i] = v;
   ir[i] = v > 0.0 ? 1.0 / v : 0.0;
 }
 }  // namespace
 
-void launch_sqrt_inv(const double* bb, double* r, double* ir, int n, hipStream_t s) {
+void launch_sqrt_inv(const double* bb, int ns, double* r, double* ir, int n, hipStream_t s) {
   if (n <= 0) return;
-  k_sqrt_inv<<<(n + 255) / 256, 256, 0, s>>>(bb, r, ir, n);
+  k_sqrt_inv<<<(n + 255) / 256, 256, 0, s>>>(bb, ns, r, ir, n);
 }
 
 void launch_model_div(const z64* B, int npw, const double* kin, const double* eps, int nv, int nb, const z64* zl,

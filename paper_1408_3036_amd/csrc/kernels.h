@@ -112,10 +112,11 @@ template <typename T>
 void launch_plane_acc(const Geom& g, const cplx<T>* tw, const cplx<T>* Tb, long ldt,
                       const cplx<T>* Psi, int nv, cplx<T>* out, long ldo, T coef, int nj,
                       bool accumulate, hipStream_t s);
-// full in-place 2D transform of every z plane of nvec grid vectors
+// full 2D transform of every z plane of nvec grid vectors, in place, or from
+// src (same layout, not overlapping G) into G
 template <typename T>
 void launch_plane_full(int N, const cplx<T>* tw, cplx<T>* G, long ldg, int nvec, int sign,
-                       hipStream_t s);
+                       hipStream_t s, const cplx<T>* src = nullptr);
 // every z-line of nvec grid vectors: G <- IFFT_z(scale * mul * FFT_z(G))
 template <typename T>
 void launch_zfull_mul(int N, const cplx<T>* tw, cplx<T>* G, long ldg, const T* mul, T scale,
@@ -185,9 +186,17 @@ void launch_gemv_sub(const z64* A, long lda, int m, const z64* h, z64* w, long n
 // scalar Lanczos helpers (device scalars)
 void launch_lanczos_alpha(const z64* q, const z64* w, long n, double* alpha_j, z64* partial,
                           hipStream_t s);
-void launch_lanczos_sub(z64* w, const z64* q, const z64* qprev, const double* alpha_j,
-                        const double* beta_prev, long n, hipStream_t s);
-void launch_norm(const z64* w, long n, double* out, z64* partial, hipStream_t s);
+// one classical Gram-Schmidt pass: w = in - A (A^H in) over the m rows of A,
+// in = src (not overlapping w) or w itself; re_last (or null) receives
+// Re <A_{m-1}, in>.  h [m] and partial [m * 64] are workspace.
+void launch_cgs_pass(const z64* A, long lda, int m, z64* w, const z64* src, long n, z64* h, z64* partial,
+                     double* re_last, hipStream_t s);
+// w = src - alpha_j q - beta_prev qprev (src null: w itself)
+void launch_lanczos_sub(z64* w, const z64* q, const z64* qprev, const double* alpha_j, const double* beta_prev,
+                        long n, hipStream_t s, const z64* src = nullptr);
+// out = |w|; with pair (and alpha), also pair[0] = *alpha, pair[1] = |w|
+void launch_norm(const z64* w, long n, double* out, z64* partial, hipStream_t s, const double* alpha = nullptr,
+                 double* pair = nullptr);
 void launch_scale_into(const z64* w, const double* nrm, z64* q, long n, hipStream_t s);
 void launch_axpby(z64* y, const z64* x, z64 a, z64 b, long n, hipStream_t s);
 void launch_add(z64* y, const z64* a, const z64* b, long n, hipStream_t s);
@@ -201,16 +210,20 @@ void launch_cvt_32_64(const z32* in, z64* out, long n, hipStream_t s);
 // p[0..n) = v (a fill kernel: no memset node, so it can sit in a captured graph)
 template <class T>
 void launch_fill(cplx<T>* p, cplx<T> v, long n, hipStream_t s);
+// x[sys] += scale[sys] * (d .* e[sys]), d (per plane wave, single precision)
+// optional; assign: x[sys] = scale[sys] * (d .* e[sys])
 void launch_cvt_32_64_axpy(const z32* e, z64* x, const double* scale, const int* sys_of_vec,
-                           long ld, int npw, int nsys, hipStream_t s);
+                           long ld, int npw, int nsys, hipStream_t s, const float* d = nullptr,
+                           bool assign = false);
 
 }  // namespace lgw
 
 namespace lgw {
 void launch_rows_out(const z64* src, long lds, z64* dst, long ldd, const int* didx, const int* a, const int* b,
                      int n, int np, hipStream_t s);
+// out[sys] = d .* single(scale[sys] * in[sys]), d (per plane wave) optional
 void launch_scale_cvt(const z64* in, long ldi, z32* out, long ldo, const double* scale, const int* act, int n,
-                      int nsys, hipStream_t s);
+                      int nsys, hipStream_t s, const float* d = nullptr);
 void launch_gemm_hn(const z64* A, long lda, int m, const z64* B, long ldb, int p, long n, z64* C, z64* partial,
                     hipStream_t s);
 // Y[yrow] = d .* X[xrow] for nrows rows (xrow = xi ? xi[i] : i, same for yrow)
@@ -264,7 +277,8 @@ namespace lgw {
 // Multi-shift Lanczos: Q rows of system s at Q + s * ldq (k vectors of npw);
 // alpha/beta [nsys][kcap]; Y [nsys][ntau][kcap]
 // r = sqrt(bb), ir = 1 / r (0 where bb = 0)
-void launch_sqrt_inv(const double* bb, double* r, double* ir, int n, hipStream_t s);
+// r = |b|, ir = 1/|b| (0 for a zero b) from the ns slice norms per system bb[n][ns]
+void launch_sqrt_inv(const double* bb, int ns, double* r, double* ir, int n, hipStream_t s);
 // model operator (H -> T): F[k][p] = B[p] / (kin - e_{p mod nv} - z_k) + B[p] / (kin - e_{p mod nv} + z_k),
 // terms with a vanishing denominator dropped
 void launch_model_div(const z64* B, int npw, const double* kin, const double* eps, int nv, int nb, const z64* zl,

@@ -183,6 +183,7 @@ struct lgw_ctx {
   // keyed by every pointer and size their capture bakes in; all are dropped
   // before any workspace buffer is reallocated
   std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+  std::map<std::vector<uintptr_t>, long long> graph_h;   // H applications one replay of a graph performs
   // frequency recycling: per-step copies of the band right-hand sides and the
   // static solutions of the recursion's chi0 applications (off while null)
   z64* keep_b = nullptr;
@@ -192,17 +193,26 @@ struct lgw_ctx {
   // the refinement) took: the next one runs that many before its first
   // convergence poll
   std::map<std::tuple<int, int, int>, int> it_hint;
+  // last contents uploaded by h2d_param per destination: small parameter
+  // arrays (system lists, shifts) that no kernel writes are uploaded only when
+  // they change.  Cleared whenever a workspace buffer is (re)allocated, so an
+  // address never outlives the buffer it was recorded for.
+  std::map<const void*, std::vector<char>> up_cache;
   void drop_graphs() {
     if (graphs.empty()) return;
     if (stream) (void)hipStreamSynchronize(stream);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     graphs.clear();
+    graph_h.clear();
   }
 
   template <class T>
   T* buf(const std::string& name, size_t count) {
     DevBuf& b = ws[name];
-    if (!(count * sizeof(T) <= b.n && b.p)) drop_graphs();
+    if (!(count * sizeof(T) <= b.n && b.p)) {
+      drop_graphs();
+      up_cache.clear();
+    }
     b.ensure(count * sizeof(T));
     return b.as<T>();
   }
@@ -323,6 +333,20 @@ void h2d_async(lgw_ctx* c, void* dst, const void* src, size_t bytes) {
   c->pin_off += n;
 }
 
+// h2d_async for a parameter array that no kernel, copy or fill writes (system
+// lists, shifts, index maps): skipped when the destination already holds
+// these bytes from an earlier upload.  Every upload to such a destination goes
+// through here, so the record is the device contents in stream order.
+void h2d_param(lgw_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return;
+  auto it = c->up_cache.find(dst);
+  const char* p = static_cast<const char*>(src);
+  if (it != c->up_cache.end() && it->second.size() == bytes && std::memcmp(it->second.data(), p, bytes) == 0)
+    return;
+  h2d_async(c, dst, src, bytes);
+  c->up_cache[dst].assign(p, p + bytes);
+}
+
 // Device arrays to host memory after the work queued on the context stream:
 // the copies go through the pinned readback buffer and share one wait.
 struct Rd {
@@ -434,6 +458,51 @@ void proj(lgw_ctx* c, cplx<T>* Y, long ldy, const int* act, int nsys) {
   proj<T>(c, Y, Y, ldy, act, nsys);
 }
 
+// Replays a fixed, launch-bound sequence of kernels on the context stream as
+// a HIP graph kept by the context, instantiated at the first call with this
+// key.  The sequence may enqueue kernels only (no copy, fill, host wait or
+// timing event) and must find every workspace buffer it uses already sized;
+// key holds every pointer, size and by-value argument the launches bake in
+// (tag: which sequence).  The H applications the sequence counts are counted
+// again at every replay.  Batches above kTimedMin systems, profiled solvers
+// and contexts without graphs launch the sequence directly.  Captures are
+// relaxed: other host threads (projection workers, other contexts) may
+// allocate, copy or synchronise their own streams while one is open, and the
+// captured sequences make no such call themselves.
+template <class F>
+void replay(lgw_ctx* c, uintptr_t tag, int nsys, std::vector<uintptr_t> key, F&& launch) {
+  if (!c->opts.use_graph || c->time_all || nsys > lgw_ctx::kTimedMin) {
+    launch();
+    return;
+  }
+  key.insert(key.begin(), {tag, (uintptr_t)nsys});
+  auto f = c->graphs.find(key);
+  if (f == c->graphs.end()) {
+    if (c->graphs.size() >= 64) c->drop_graphs();
+    const long long h0 = c->tot_h;
+    hipGraph_t gr = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    try {
+      launch();
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(c->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(c->stream, &gr));
+    hipGraphExec_t gx = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HIPCHK(ie);
+    f = c->graphs.emplace(key, gx).first;
+    c->graph_h[key] = c->tot_h - h0;
+    c->tot_h = h0;
+  }
+  HIPCHK(hipGraphLaunch(f->second, c->stream));
+  c->tot_h += c->graph_h[key];
+}
+
 // Y = A X for the projected operator of the given kind (X is in range(P_c)).
 // With a preconditioner scaling S (pre != null): Y = S P A P S X, with P S X
 // staged in ptmp (formed by the first transform from the CG kernels' partial
@@ -477,6 +546,7 @@ struct Batch {
   cplx<T>* shift = nullptr;
   T* w2 = nullptr;
   int* act = nullptr;
+  size_t poll_off = 0;         // byte offset of v.rr behind v.flag and v.iters
   int nsplit = 1;
   T* split_part = nullptr;
   const T* pre = nullptr;      // preconditioner scaling or null
@@ -492,7 +562,7 @@ struct Batch {
   Batch(Batch&& o) noexcept { *this = std::move(o); }
   Batch& operator=(Batch&& o) noexcept {
     kind = o.kind; nsys = o.nsys; ld = o.ld; v = o.v; tmp = o.tmp; Tb = o.Tb; shift = o.shift; w2 = o.w2;
-    act = o.act; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp; fpart = o.fpart; dot_part = o.dot_part; cp = o.cp; cn = o.cn;
+    act = o.act; poll_off = o.poll_off; nsplit = o.nsplit; split_part = o.split_part; pre = o.pre; ptmp = o.ptmp; fpart = o.fpart; dot_part = o.dot_part; cp = o.cp; cn = o.cn;
     h_iters = std::move(o.h_iters); h_flags = std::move(o.h_flags);
     return *this;
   }
@@ -517,12 +587,16 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
   b.ptmp = b.pre ? c->buf<cplx<T>>(t + ".ptmp", nv) : nullptr;
   b.Tb = c->buf<cplx<T>>(t + ".Tb", (size_t)nsys * c->N * c->ncols);
   b.v.ld = b.ld;
-  b.v.rr = c->buf<T>(t + ".rr", nsys);
+  // flags, iteration counts and residual estimates in one allocation, so a
+  // convergence poll reads them back with one copy
+  b.poll_off = ((size_t)2 * nsys * sizeof(int) + 15) & ~size_t(15);
+  char* poll = c->buf<char>(t + ".poll", b.poll_off + (size_t)nsys * sizeof(T));
+  b.v.flag = reinterpret_cast<int*>(poll);
+  b.v.iters = b.v.flag + nsys;
+  b.v.rr = reinterpret_cast<T*>(poll + b.poll_off);
   b.v.bb = c->buf<T>(t + ".bb", nsys);
   b.v.theta = c->buf<T>(t + ".th", nsys);
   b.v.rho = c->buf<cplx<T>>(t + ".rho", nsys);
-  b.v.flag = c->buf<int>(t + ".flag", nsys);
-  b.v.iters = c->buf<int>(t + ".iters", nsys);
   b.shift = c->buf<cplx<T>>(t + ".shift", nsys);
   b.w2 = c->buf<T>(t + ".w2", nsys);
   b.act = c->buf<int>(t + ".act", nsys);
@@ -545,10 +619,10 @@ Batch<T> make_batch(lgw_ctx* c, const char* tag, int kind, int nsys, const std::
     cap = std::max(cap, (size_t)proj_ksplit<T>(c->npw, nsys) * nsys) + 64;
     (void)c->buf<cplx<T>>(sizeof(T) == 8 ? "proj.part64" : "proj.part32", cap * c->nv);
   }
-  h2d_async(c, b.shift, shift.data(), nsys * sizeof(cplx<T>));
+  h2d_param(c, b.shift, shift.data(), nsys * sizeof(cplx<T>));
   std::vector<T> w(w2);
   w.resize(nsys, T(0));
-  h2d_async(c, b.w2, w.data(), nsys * sizeof(T));
+  h2d_param(c, b.w2, w.data(), nsys * sizeof(T));
   b.h_iters.assign(nsys, 0);
   b.h_flags.assign(nsys, 0);
   return b;
@@ -566,7 +640,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   std::vector<int> act(start);
   if (act.empty()) return;
   const int npw = c->npw;
-  h2d_async(c, b.act, act.data(), act.size() * sizeof(int));
+  h2d_param(c, b.act, act.data(), act.size() * sizeof(int));
   // Small preconditioned CG batches: the CG kernels leave the projector's
   // slice sums of the residual (of b at the initialisation), the first
   // transform updates the direction and forms P S p from them (coefficients
@@ -617,6 +691,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
   int& hint = c->it_hint[{b.kind, (int)sizeof(T), std::min(pass, 3)}];
   std::vector<int> flags(b.nsys), iters(b.nsys);
   std::vector<T> est(b.nsys);
+  std::vector<char> hpoll(b.poll_off + (size_t)b.nsys * sizeof(T));
   std::vector<double> best(b.nsys, 0.0);
   std::vector<int> best_it(b.nsys, -1);
   int it = 0;
@@ -625,9 +700,11 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
     // kernels skip flagged systems, so the first chunk runs without a poll
     // (initialisation flags only zero right-hand sides).
     if (it > 0) {
-      readback(c, {{flags.data(), b.v.flag, b.nsys * sizeof(int)},
-                   {iters.data(), b.v.iters, b.nsys * sizeof(int)},
-                   {est.data(), b.v.rr, stall > 0 ? b.nsys * sizeof(T) : 0}});
+      const size_t ni = (size_t)b.nsys * sizeof(int);
+      readback(c, {{hpoll.data(), b.v.flag, stall > 0 ? hpoll.size() : 2 * ni}});
+      std::memcpy(flags.data(), hpoll.data(), ni);
+      std::memcpy(iters.data(), hpoll.data() + ni, ni);
+      if (stall > 0) std::memcpy(est.data(), hpoll.data() + b.poll_off, b.nsys * sizeof(T));
       std::vector<int> next, stalled;
       for (int s : act) {
         if (flags[s]) continue;
@@ -648,7 +725,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
       for (int s : stalled) h2d_async(c, b.v.flag + s, &fl, sizeof(int));
       act.swap(next);
       if (act.empty() || it >= maxit) break;
-      h2d_async(c, b.act, act.data(), act.size() * sizeof(int));
+      h2d_param(c, b.act, act.data(), act.size() * sizeof(int));
     }
     int chunk = std::min(check, maxit - it);
     if (small && hint > 0) {
@@ -704,7 +781,8 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
                               (size_t)proj_ksplit<T>(c->npw, na) * na * c->nv);
         const long long h0 = c->tot_h;
         hipGraph_t gr = nullptr;
-        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        // relaxed, as in replay(): other threads' calls stay permitted
+        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
         iterate(chunk);
         HIPCHK(hipStreamEndCapture(c->stream, &gr));
         const hipError_t ie = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
@@ -751,44 +829,61 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
   out.sweeps.assign(nsys, 0);
   out.rel.assign(nsys, 0.0);
   int* d_bidx = c->buf<int>("sv.bidx", nsys);
-  h2d_async(c, d_bidx, bidx.data(), nsys * sizeof(int));
+  h2d_param(c, d_bidx, bidx.data(), nsys * sizeof(int));
   z64* R = c->buf<z64>("sv.R", (size_t)nsys * npw);
   z64* AX = c->buf<z64>("sv.AX", (size_t)nsys * npw);
   z64* tmp = c->buf<z64>("sv.tmp", kind == K_CGSQ ? (size_t)nsys * npw : 1);
   z64* Tb = c->buf<z64>("sv.Tb", (size_t)nsys * c->N * c->ncols);
-  double* bb = c->buf<double>("sv.bb", nsys);
+  // the slice norms of |b|^2 sit behind the true residuals' slice norms
+  // (resp), so the first true-residual readback takes both with one copy
+  const int rsn = std::max(1, std::min(64, npw / 1024));
+  double* resp = c->buf<double>("sv.resp", (size_t)2 * nsys * rsn);
+  double* bbp = resp + (size_t)nsys * rsn;
   z64* d_shift = c->buf<z64>("sv.shift", nsys);
   double* d_w2 = c->buf<double>("sv.w2", nsys);
   int* d_act = c->buf<int>("sv.act", nsys);
-  h2d_async(c, d_shift, shift.data(), nsys * sizeof(z64));
+  h2d_param(c, d_shift, shift.data(), nsys * sizeof(z64));
   std::vector<double> w2v(w2);
   w2v.resize(nsys, 0.0);
-  h2d_async(c, d_w2, w2v.data(), nsys * sizeof(double));
+  h2d_param(c, d_w2, w2v.data(), nsys * sizeof(double));
   std::vector<int> all(nsys);
   for (int s = 0; s < nsys; ++s) all[s] = s;
-  h2d_async(c, d_act, all.data(), nsys * sizeof(int));
-  // |b|^2 per system (|B - 0|^2 with a zero AX), read back with the first true
-  // residuals: the host needs it only to form relative residuals
+  h2d_param(c, d_act, all.data(), nsys * sizeof(int));
+  // |b|^2 per system as slice norms (|B - 0|^2, no AX), read back with the
+  // first true residuals: the host needs it only to form relative residuals.
+  // The mixed path starts from R = B, which the same pass writes.
   std::vector<double> h_bb(nsys), h_res(nsys);
   bool have_bb = false;
-  const int rsn = std::max(1, std::min(64, npw / 1024));
-  double* resp = c->buf<double>("sv.resp", (size_t)nsys * rsn);
-  std::vector<double> h_resp((size_t)nsys * rsn);
-  HIPCHK(hipMemsetAsync(AX, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
-  launch_resid<double>(B, npw, d_bidx, AX, npw, nullptr, 0, bb, npw, d_act, nsys, c->stream);
+  std::vector<double> h_resp((size_t)2 * nsys * rsn);
+  const bool mixed = c->opts.precision != LGW_FP64;
+  launch_resid_split<double>(B, npw, d_bidx, nullptr, npw, mixed ? R : nullptr, npw, bbp, rsn, npw, d_act, nsys,
+                             c->stream);
   // true residual R = B - A X over the listed systems; returns rel. residuals
   auto true_resid = [&](const std::vector<int>& lst) {
     if (lst.empty()) return;
-    h2d_async(c, d_act, lst.data(), lst.size() * sizeof(int));
-    // the solution lives in the conduction space: remove what rounding (or the
-    // single-precision corrections) left in the valence space, which the
-    // projected residual below cannot see
-    proj<double>(c, X, npw, d_act, (int)lst.size());
-    apply_op<double>(c, kind, X, AX, tmp, Tb, npw, d_shift, d_w2, d_act, (int)lst.size());
-    // slice norms over several workgroups per system, summed here in order
-    launch_resid_split<double>(B, npw, d_bidx, AX, npw, R, npw, resp, rsn, npw, d_act, (int)lst.size(), c->stream);
-    readback(c, {{h_resp.data(), resp, h_resp.size() * sizeof(double)},
-                 {h_bb.data(), bb, have_bb ? 0 : nsys * sizeof(double)}});
+    h2d_param(c, d_act, lst.data(), lst.size() * sizeof(int));
+    const int n = (int)lst.size();
+    (void)c->buf<z64>("proj.part64", (size_t)proj_ksplit<double>(npw, n) * n * c->nv);
+    replay(c, 1001, n,
+           {(uintptr_t)kind, (uintptr_t)X, (uintptr_t)AX, (uintptr_t)tmp, (uintptr_t)Tb, (uintptr_t)d_shift,
+            (uintptr_t)d_w2, (uintptr_t)d_act, (uintptr_t)B, (uintptr_t)d_bidx, (uintptr_t)R, (uintptr_t)resp,
+            (uintptr_t)npw, (uintptr_t)rsn, (uintptr_t)c->buf<z64>("proj.part64", 1)},
+           [&] {
+             // the solution lives in the conduction space: remove what rounding
+             // (or the single-precision corrections) left in the valence space,
+             // which the projected residual below cannot see
+             proj<double>(c, X, npw, d_act, n);
+             apply_op<double>(c, kind, X, AX, tmp, Tb, npw, d_shift, d_w2, d_act, n);
+             // slice norms over several workgroups per system, summed here in order
+             launch_resid_split<double>(B, npw, d_bidx, AX, npw, R, npw, resp, rsn, npw, d_act, n, c->stream);
+           });
+    readback(c, {{h_resp.data(), resp, (size_t)(have_bb ? 1 : 2) * nsys * rsn * sizeof(double)}});
+    if (!have_bb)
+      for (int s = 0; s < nsys; ++s) {
+        double t = 0.0;
+        for (int k = 0; k < rsn; ++k) t += h_resp[(size_t)(nsys + s) * rsn + k];
+        h_bb[s] = t;
+      }
     have_bb = true;
     for (int s : lst) {
       double t = 0.0;
@@ -842,10 +937,10 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
         if (out.rel[s] > tol && b.h_flags[s] != FLAG_BREAK) bad.push_back(s);
       if (bad.empty()) break;
       // restart from x with the true residual: b.v.x already holds X (or y)
-      h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
+      h2d_param(c, d_act, bad.data(), bad.size() * sizeof(int));
       if (pre) launch_scale_diag<double>(R, npw, d_act, R, npw, d_act, pre, npw, (int)bad.size(), c->stream);
       run_batch<double>(c, b, R, npw, nullptr, true, itol, bad, stall, 1 + restart);
-      h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
+      h2d_param(c, d_act, bad.data(), bad.size() * sizeof(int));
       x_out(d_act, (int)bad.size());
       lst = bad;
     }
@@ -859,9 +954,8 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       out.sweeps[s] = 1;
     }
   } else {
-    // mixed precision: X = 0, R = B
-    HIPCHK(hipMemsetAsync(X, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
-    launch_rows_out(B, npw, R, npw, d_act /*identity rows*/, d_bidx, nullptr, npw, nsys, c->stream);
+    // mixed precision: R = B (written with |b|^2 above); X is set by the
+    // first sweep's correction, which every system enters
     // every system enters the first sweep (a zero right-hand side gets zero
     // scalings and converges at initialisation)
     for (int s = 0; s < nsys; ++s) out.rel[s] = 1.0;
@@ -872,42 +966,45 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       w32[s] = (float)w2v[s];
     }
     Batch<float> b = make_batch<float>(c, "b32", kind, nsys, sh32, w32);
-    double* rs = c->buf<double>("sv.rs", nsys);
-    double* irs = c->buf<double>("sv.irs", nsys);
+    double* rs = c->buf<double>("sv.rs", 2 * (size_t)nsys);   // |r| then 1/|r|, uploaded together
+    double* irs = rs + nsys;
     z32* R32 = c->buf<z32>("sv.R32", (size_t)nsys * npw);
-    std::vector<double> h_rs(nsys), h_irs(nsys);
+    std::vector<double> h_rsi(2 * (size_t)nsys);
     const double inner = std::max(c->opts.inner_tol, 1e-7);
     std::vector<int> lst = all;
     std::vector<double> prev(nsys, 1.0);
+    bool x_set = false;   // the first sweep's correction assigns X (every system enters it)
     for (int sweep = 0; sweep < std::max(1, c->opts.max_sweeps); ++sweep) {
       std::vector<int> bad;
       for (int s : lst)
         if (out.rel[s] > tol && out.flags[s] == 0) bad.push_back(s);
       if (bad.empty()) break;
+      if (sweep == 0 && (int)bad.size() != nsys) {
+        HIPCHK(hipMemsetAsync(X, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
+        x_set = true;
+      }
       for (int s : bad) {
         out.sweeps[s] += 1;
         prev[s] = out.rel[s];
       }
       if (sweep == 0) {
-        launch_sqrt_inv(bb, rs, irs, nsys, c->stream);   // |b| and 1/|b| from the device's |b|^2
+        launch_sqrt_inv(bbp, rsn, rs, irs, nsys, c->stream);   // |b| and 1/|b| from the device's slice norms
       } else {
         for (int s : bad) {
-          h_rs[s] = std::sqrt(h_res[s]);
-          h_irs[s] = h_rs[s] > 0 ? 1.0 / h_rs[s] : 0.0;
+          h_rsi[s] = std::sqrt(h_res[s]);
+          h_rsi[nsys + s] = h_rsi[s] > 0 ? 1.0 / h_rsi[s] : 0.0;
         }
-        h2d_async(c, rs, h_rs.data(), nsys * sizeof(double));
-        h2d_async(c, irs, h_irs.data(), nsys * sizeof(double));
+        h2d_async(c, rs, h_rsi.data(), h_rsi.size() * sizeof(double));
       }
-      h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
-      launch_scale_cvt(R, npw, R32, npw, irs, d_act, npw, (int)bad.size(), c->stream);
-      if (b.pre) launch_scale_diag<float>(R32, npw, d_act, R32, npw, d_act, b.pre, npw, (int)bad.size(), c->stream);
+      h2d_param(c, d_act, bad.data(), bad.size() * sizeof(int));
+      launch_scale_cvt(R, npw, R32, npw, irs, d_act, npw, (int)bad.size(), c->stream, b.pre);
       // FP32 SQMR stops on a 32-iteration stagnation window like the FP64 one
       // (an iterate pushed past its attainable accuracy spoils the correction);
       // CG keeps a longer window for slowly converging imaginary-axis systems
       run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad, kind == K_SQMR ? 32 : 96, sweep);
-      h2d_async(c, d_act, bad.data(), bad.size() * sizeof(int));
-      if (b.pre) launch_scale_diag<float>(b.v.x, npw, d_act, b.v.x, npw, d_act, b.pre, npw, (int)bad.size(), c->stream);
-      launch_cvt_32_64_axpy(b.v.x, X, rs, d_act, npw, npw, (int)bad.size(), c->stream);
+      h2d_param(c, d_act, bad.data(), bad.size() * sizeof(int));
+      launch_cvt_32_64_axpy(b.v.x, X, rs, d_act, npw, npw, (int)bad.size(), c->stream, b.pre, !x_set);
+      x_set = true;
       true_resid(bad);
       for (int s : bad) {
         out.iters[s] += b.h_iters[s];
@@ -917,6 +1014,7 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       }
       lst = bad;
     }
+    if (!x_set) HIPCHK(hipMemsetAsync(X, 0, (size_t)nsys * npw * sizeof(z64), c->stream));
     // Systems the FP32 sweeps could not bring to the tolerance (an inner
     // solve that stagnates or breaks down on a nearly singular system) get an
     // FP64 correction on their true residual: solve A e = R in FP64 to
@@ -1098,7 +1196,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
       idx[s] = s0 + s;
       sh[s] = z64{base ? base[s0 + s] : c->eps[(s0 + s) % nv], 0.0};
     }
-    h2d_async(c, d_idx, idx.data(), n * sizeof(int));
+    h2d_param(c, d_idx, idx.data(), n * sizeof(int));
     h2d_async(c, d_sh, sh.data(), n * sizeof(z64));
     launch_ms_init(B0, npw, d_idx, npw, Q, ldq, nrm, n, c->stream);
     c->check_launch();
@@ -1117,7 +1215,7 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
     std::vector<int> cj(n, 0);
     int j = 0;
     while (!act.empty() && j < kcap) {
-      h2d_async(c, d_act, act.data(), act.size() * sizeof(int));
+      h2d_param(c, d_act, act.data(), act.size() * sizeof(int));
       const int na = (int)act.size();
       const int steps = std::min(check, kcap - j);
       for (int t = 0; t < steps; ++t, ++j) {
@@ -1320,8 +1418,9 @@ lgw_status multishift(lgw_ctx* c, const z64* B0, int nb, int nz, const lgw_c128*
 
 // ---------------------------------------------------------------- v^1/2
 // in-place on zxy grid vectors: G <- scale_sign * v^1/2 G
-void vhalf_inplace(lgw_ctx* c, z64* G, int n, double sign) {
-  launch_plane_full<double>(c->N, c->d_tw64.as<z64>(), G, c->n3, n, -1, c->stream);
+// G = v^1/2 src (src null: in place; otherwise src is left unchanged)
+void vhalf_inplace(lgw_ctx* c, z64* G, int n, double sign, const z64* src = nullptr) {
+  launch_plane_full<double>(c->N, c->d_tw64.as<z64>(), G, c->n3, n, -1, c->stream, src);
   launch_zfull_mul<double>(c->N, c->d_tw64.as<z64>(), G, c->n3, c->d_sqrtv.as<double>(), sign / (double)c->n3, n,
                            c->stream);
   launch_plane_full<double>(c->N, c->d_tw64.as<z64>(), G, c->n3, n, +1, c->stream);
@@ -1342,11 +1441,18 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
   z64* Tb = c->buf<z64>("c.Tb", (size_t)nb * ldt);
   z64* B0 = c->buf<z64>("c.B0", (size_t)nb * npw);     // b
   z64* B2 = c->buf<z64>("c.B2", (size_t)nb * npw);     // 2 b
-  launch_plane_pair_fwd<double>(c->geom, c->d_tw64.as<z64>(), c->d_u.as<z64>(), nv, X, n3, nrhs, Tb, ldt, c->stream);
-  launch_zfwd<double>(c->geom, c->d_tw64.as<z64>(), Tb, ldt, std::sqrt(c->omega) / (double)n3, nullptr, 0, nullptr,
-                      nullptr, 0, nullptr, B0, npw, nullptr, nb, c->stream);
-  proj<double>(c, B0, npw, nullptr, nb);
-  launch_add(B2, B0, B0, (long)nb * npw, c->stream);
+  (void)c->buf<z64>("proj.part64", (size_t)proj_ksplit<double>(npw, nb) * nb * nv);
+  replay(c, 1002, nb,
+         {(uintptr_t)X, (uintptr_t)nrhs, (uintptr_t)Tb, (uintptr_t)B0, (uintptr_t)B2,
+          (uintptr_t)c->buf<z64>("proj.part64", 1)},
+         [&] {
+           launch_plane_pair_fwd<double>(c->geom, c->d_tw64.as<z64>(), c->d_u.as<z64>(), nv, X, n3, nrhs, Tb, ldt,
+                                         c->stream);
+           launch_zfwd<double>(c->geom, c->d_tw64.as<z64>(), Tb, ldt, std::sqrt(c->omega) / (double)n3, nullptr, 0,
+                               nullptr, nullptr, 0, nullptr, B0, npw, nullptr, nb, c->stream);
+           proj<double>(c, B0, npw, nullptr, nb);
+           launch_add(B2, B0, B0, (long)nb * npw, c->stream);
+         });
   if (c->opts.model == 1) {
     // model operator (H -> T): f[z][p] = P ((T - e_v - z)^-1 + (T - e_v + z)^-1) b_p
     z64* F = c->buf<z64>("c.F", (size_t)nz * nb * npw);
@@ -1450,7 +1556,7 @@ lgw_status chi0_internal(lgw_ctx* c, int nrhs, const z64* X, int nz, const lgw_c
       std::vector<int> all(didx);
       all.insert(all.end(), a.begin(), a.end());
       all.insert(all.end(), b.begin(), b.end());
-      h2d_async(c, d_idx, all.data(), all.size() * sizeof(int));
+      h2d_param(c, d_idx, all.data(), all.size() * sizeof(int));
       launch_rows_out(Xs, npw, F, npw, d_idx, d_idx + np, kind == K_SQMR ? d_idx + 2 * np : nullptr, npw, np,
                       c->stream);
       for (int i = 0; i < n; ++i) {
@@ -1767,8 +1873,7 @@ struct SolveTally {
 lgw_status apply_M0(lgw_ctx* c, const z64* q, z64* w, SolveTally& tally) {
   const long n3 = c->n3;
   z64* x1 = c->buf<z64>("lz.x1", n3);
-  HIPCHK(hipMemcpyAsync(x1, q, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
-  vhalf_inplace(c, x1, 1, 1.0);
+  vhalf_inplace(c, x1, 1, 1.0, q);
   const lgw_c128 z0{c->lz_z.x, c->lz_z.y};
   c->tot_iters = c->tot_h = 0;
   const lgw_status st = chi0_internal(c, 1, x1, 1, &z0, w, n3);
@@ -1803,34 +1908,36 @@ lgw_status lanczos_start(lgw_ctx* c, const lgw_c128* q0, z64* Q) {
 }
 
 // Lanczos with full reorthogonalisation on eps(0) - 1 (Sec. IV): from q_0 in
-// Q[0], for j < k: w = M q_j, alpha_j = Re <q_j, w>, w -= alpha_j q_j +
-// beta_{j-1} q_{j-1}, then classical Gram-Schmidt against q_0..q_j twice,
-// beta_j = |w|, q_{j+1} = w / beta_j.  Stops early when beta_j < 1e-14
-// max|alpha|.  W0 (or null) keeps every product M q_j.
+// Q[0], for j < k: w = M q_j, classical Gram-Schmidt of w against q_0..q_j
+// twice (the first pass's coefficients are alpha_j = Re <q_j, w> on q_j and
+// beta_{j-1} up to rounding on q_{j-1}, so it also performs the three-term
+// recurrence's subtraction), beta_j = |w|, q_{j+1} = w / beta_j.  Stops early
+// when beta_j < 1e-14 max|alpha|.  W0 (or null) keeps every product M q_j.
 lgw_status lanczos_core(lgw_ctx* c, int k, z64* Qd, z64* W0, double* d_alpha, double* d_beta, int* done_out,
                         const std::function<void(int)>& ready = nullptr) {
   const long n3 = c->n3;
   z64* wbuf = c->buf<z64>("lz.w", n3);
   z64* h = c->buf<z64>("lz.h", k);
   z64* part = c->buf<z64>("lz.part", (size_t)64 * (k + 1));
+  double* pair = c->buf<double>("lz.pair", 2);
   lgw_status st = LGW_OK;
   SolveTally tally;
   double amax = 0.0;
   int done = 0;
   for (int j = 0; j < k; ++j) {
     z64* qj = Qd + (size_t)j * n3;
-    st = worst(st, apply_M0(c, qj, wbuf, tally));
-    if (W0) HIPCHK(hipMemcpyAsync(W0 + (size_t)j * n3, wbuf, n3 * sizeof(z64), hipMemcpyDeviceToDevice, c->stream));
-    launch_lanczos_alpha(qj, wbuf, n3, d_alpha + j, part, c->stream);
-    launch_lanczos_sub(wbuf, qj, j > 0 ? qj - n3 : nullptr, d_alpha + j, j > 0 ? d_beta + j - 1 : nullptr, n3,
-                       c->stream);
-    for (int pass = 0; pass < 2; ++pass) {
-      launch_dots(Qd, n3, j + 1, wbuf, n3, h, part, c->stream);
-      launch_gemv_sub(Qd, n3, j + 1, h, wbuf, n3, c->stream);
-    }
-    launch_norm(wbuf, n3, d_beta + j, part, c->stream);
+    // the product lands in W0[j] when the caller keeps the products, and the
+    // three-term update reads it from there into wbuf
+    z64* mq = W0 ? W0 + (size_t)j * n3 : wbuf;
+    st = worst(st, apply_M0(c, qj, mq, tally));
+    // two classical Gram-Schmidt passes against q_0..q_j; the first one's
+    // coefficient on q_j is alpha_j = Re <q_j, M q_j>, and its coefficients on
+    // q_j and q_{j-1} take out the three-term recurrence's part
+    launch_cgs_pass(Qd, n3, j + 1, wbuf, W0 ? mq : nullptr, n3, h, part, d_alpha + j, c->stream);
+    launch_cgs_pass(Qd, n3, j + 1, wbuf, nullptr, n3, h, part, nullptr, c->stream);
+    launch_norm(wbuf, n3, d_beta + j, part, c->stream, d_alpha + j, pair);
     double hb[2];
-    readback(c, {{&hb[0], d_alpha + j, sizeof(double)}, {&hb[1], d_beta + j, sizeof(double)}});
+    readback(c, {{hb, pair, 2 * sizeof(double)}});
     amax = std::max(amax, std::abs(hb[0]));
     done = j + 1;
     if (hb[1] < 1e-14 * amax) break;
@@ -2763,6 +2870,7 @@ lgw_status lgw_setup(lgw_ctx** out, const double cell[9], const int grid[3], dou
     autotune_plane(cp);
     c->drop_graphs();
     c->ws.clear();
+    c->up_cache.clear();
     *out = c.release();
     return LGW_OK;
   } catch (const Fail& f) {

@@ -3,6 +3,12 @@
 Argument marshalling only: torch tensors supply device memory, every step of
 the computation runs in the library's HIP kernels.  There is no fallback: if
 the library is missing or cannot load, this module raises.
+
+Before each call the calling thread's current torch stream (which wrote the
+inputs) is synchronised, not the whole device: other contexts may be solving
+on their own streams in other threads, and a device-wide synchronisation
+would break their graph captures.  The library's calls return after their
+own stream has finished, so the outputs are ready for any stream.
 """
 from __future__ import annotations
 
@@ -179,7 +185,7 @@ class Lgw:
         psi = self._dev(psi, torch.complex128).reshape(len(eps), -1)
         eps_arr = (C.c_double * len(eps))(*[float(e) for e in eps])
         ctx = C.c_void_p()
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()
         st = self.lib.lgw_setup(C.byref(ctx), cell, grid, float(ecut), V.data_ptr(), len(eps),
                                 psi.data_ptr(), eps_arr, C.byref(opts))
         if st != 0:
@@ -221,7 +227,7 @@ class Lgw:
         dV = dV.reshape(-1, self.N ** 3)
         zarr, nz = _z(z)
         out = t.empty((nz, dV.shape[0], self.N ** 3), dtype=t.complex128, device="cuda")
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self.last_status = self._check(
             self.lib.lgw_chi0_apply(self.ctx, dV.shape[0], dV.data_ptr(), nz, zarr, out.data_ptr()),
             allow_partial)
@@ -237,7 +243,7 @@ class Lgw:
         g = self._dev(g_dn, t.complex128).reshape(nz, dV.shape[0], self.N ** 3)
         gdV = t.empty_like(dV) if want_dV else None
         gV = t.empty(self.N ** 3, dtype=t.float64, device="cuda") if want_V else None
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self.last_status = self._check(self.lib.lgw_chi0_apply_vjp(
             self.ctx, dV.shape[0], dV.data_ptr(), nz, zarr, g.data_ptr(),
             gdV.data_ptr() if gdV is not None else None, gV.data_ptr() if gV is not None else None))
@@ -250,7 +256,7 @@ class Lgw:
         beta = t.zeros(k, dtype=t.float64, device="cuda")
         Q = t.zeros((k, self.N ** 3), dtype=t.complex128, device="cuda") if want_Q else None
         kd = C.c_int(0)
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self.last_status = self._check(self.lib.lgw_lanczos(
             self.ctx, q0.data_ptr(), k, alpha.data_ptr(), beta.data_ptr(),
             Q.data_ptr() if Q is not None else None, C.byref(kd)))
@@ -267,7 +273,7 @@ class Lgw:
         loss = t.zeros(1, dtype=t.float64, device="cuda")
         gV = t.empty(self.N ** 3, dtype=t.float64, device="cuda") if want_V else None
         kd = C.c_int(0)
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self.last_status = self._check(self.lib.lgw_lanczos_loss_vjp(
             self.ctx, q0.data_ptr(), k, nz, zarr, loss.data_ptr(),
             gV.data_ptr() if gV is not None else None, C.byref(kd)))
@@ -285,7 +291,7 @@ class Lgw:
         Q = t.zeros((k, self.N ** 3), dtype=t.complex128, device="cuda") if want_Q else None
         E = t.zeros((nz, k, k), dtype=t.complex128, device="cuda")
         kd = C.c_int(0)
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self.last_status = self._check(self.lib.lgw_lanczos_project(
             self.ctx, q0.data_ptr(), k, nz, zarr, alpha.data_ptr(), beta.data_ptr(),
             Q.data_ptr() if Q is not None else None, E.data_ptr(), C.byref(kd)))
@@ -305,7 +311,7 @@ class Lgw:
         Q = t.zeros((k, self.N ** 3), dtype=t.complex128, device="cuda") if want_Q else None
         E = t.zeros((len(wl), k, k), dtype=t.complex128, device="cuda")
         kd = C.c_int(0)
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self.last_status = self._check(self.lib.lgw_lanczos_recycle(
             self.ctx, q0.data_ptr(), k, len(wl), warr, alpha.data_ptr(), beta.data_ptr(),
             Q.data_ptr() if Q is not None else None, E.data_ptr(), C.byref(kd)))
@@ -321,7 +327,7 @@ class Lgw:
         B = t.zeros((nblk, b, b), dtype=t.complex128, device="cuda")
         Q = t.zeros((nblk * b, self.N ** 3), dtype=t.complex128, device="cuda") if want_Q else None
         nd = C.c_int(0)
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self.last_status = self._check(self.lib.lgw_block_lanczos(
             self.ctx, b, Q0.data_ptr(), nblk, A.data_ptr(), B.data_ptr(),
             Q.data_ptr() if Q is not None else None, C.byref(nd)))
@@ -334,7 +340,7 @@ class Lgw:
         k = Q.shape[0]
         zarr, nz = _z(z)
         E = t.empty((nz, k, k), dtype=t.complex128, device="cuda")
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self.last_status = self._check(
             self.lib.lgw_project(self.ctx, k, Q.data_ptr(), nz, zarr, E.data_ptr()))
         return E
@@ -343,7 +349,7 @@ class Lgw:
         t = self.torch
         x = self._dev(x, t.complex128).reshape(-1, self.npw)
         y = t.empty_like(x)
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self._check(self.lib.lgw_hpsi(self.ctx, x.shape[0], c128(shift.real, shift.imag),
                                       x.data_ptr(), y.data_ptr()))
         return y
@@ -357,7 +363,7 @@ class Lgw:
         sN = np.zeros(len(w))
         sN0 = np.zeros(len(w))
         sA = np.zeros(1)
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self.last_status = self._check(self.lib.lgw_sigma_traces(
             self.ctx, int(e), float(delta), float(alpha), Q.shape[0], Q.data_ptr(), len(w),
             w.ctypes.data, sN.ctypes.data, sN0.ctypes.data, sA.ctypes.data))
@@ -375,7 +381,7 @@ class Lgw:
         """Residue term Sigma_P of state e (lgw_sigma_residues): (Sigma_P, n_poles)."""
         sp = np.zeros(1)
         npl = C.c_int(0)
-        self.torch.cuda.synchronize()
+        self.torch.cuda.current_stream().synchronize()
         self.last_status = self._check(self.lib.lgw_sigma_residues(
             self.ctx, int(e), float(delta), int(k_p), sp.ctypes.data, C.byref(npl)))
         return float(sp[0]), npl.value
@@ -396,7 +402,7 @@ class Lgw:
         t = self.torch
         x = self._dev(x, t.complex128).reshape(-1, self.N ** 3)
         y = t.empty_like(x)
-        t.cuda.synchronize()
+        t.cuda.current_stream().synchronize()
         self._check(self.lib.lgw_vhalf(self.ctx, x.shape[0], x.data_ptr(), y.data_ptr()))
         return y
 
@@ -452,7 +458,7 @@ def chi0_apply_many(systems, dVs, z, allow_partial: bool = False):
     nr = (C.c_int * n)(*[d.shape[0] for d in dVs])
     ins = (C.c_void_p * n)(*[d.data_ptr() for d in dVs])
     ous = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
-    torch.cuda.synchronize()
+    torch.cuda.current_stream().synchronize()
     st = lib.lgw_chi0_apply_many(n, ctxs, nr, ins, nz, zarr, ous)
     if st != 0 and not (allow_partial and st in (5, 6)):
         raise LgwError(st, "lgw_chi0_apply_many failed")
