@@ -264,6 +264,7 @@ struct lgw_ctx {
   }
   ~lgw_ctx() {
     for (auto& t : twins) {
+      if (!t) continue;   // a twin whose creation failed
       hipStream_t ts = t->own_stream ? t->stream : nullptr;
       t.reset();
       if (ts) (void)hipStreamDestroy(ts);
