@@ -217,6 +217,27 @@ lgw_status lgw_chi0_apply_vjp(lgw_ctx* ctx, int n_rhs, const lgw_c128* dV, int n
 lgw_status lgw_lanczos_project(lgw_ctx* ctx, const lgw_c128* q0, int k, int n_z, const lgw_c128* z,
                                double* alpha, double* beta, lgw_c128* Q, lgw_c128* E, int* k_done);
 
+/* The dielectric matrix inverted within the basis (Sec. IV: eps^-1 from the
+ * small matrix of the Lanczos basis instead of the full dielectric matrix).
+ * For each of the n_z matrices E(z) = Q^H (eps(z) - 1) Q [k][k] (row-major,
+ * as lgw_project and lgw_lanczos_project return them),
+ *   Einv[z] = (I + E(z))^-1,
+ * so that 1 + Q (Einv - I) Q^H is the basis approximation of eps(z)^-1
+ * (exact when span(Q) is invariant under eps(z)) and Einv - I is the
+ * screened factor W(z) of the self-energy traces.  Gaussian elimination
+ * with partial pivoting on the host, FP64.  E and Einv [n_z][k][k] follow
+ * opts.mem.  LGW_EBREAKDOWN if some I + E(z) is singular, LGW_ENAN on a
+ * non-finite entry. */
+lgw_status lgw_eps_inverse(lgw_ctx* ctx, int k, int n_z, const lgw_c128* E, lgw_c128* Einv);
+
+/* Ritz values of eps(0) - 1 in the Lanczos basis (Sec. IV): the eigenvalues
+ * of the k x k symmetric tridiagonal T with alpha[0..k) on the diagonal and
+ * beta[0..k-1) beside it (as lgw_lanczos returns them), ascending, into
+ * theta[k] (host memory).  alpha and beta follow opts.mem; beta may be NULL
+ * when k = 1.  Since eps(0) - 1 is positive semidefinite they lie in
+ * [0, max eigenvalue]. */
+lgw_status lgw_ritz_values(lgw_ctx* ctx, int k, const double* alpha, const double* beta, double* theta);
+
 /* Frequency recycling (Sec. VI): the static Lanczos basis of lgw_lanczos and
  * eps(i w) - 1 projected on it at imaginary frequencies without a Sternheimer
  * solve per frequency.  For every valence band the recursion's right-hand

@@ -87,6 +87,21 @@ def logdet_loss(apply_Mz, q0: np.ndarray, k: int, z_list) -> float:
     return total
 
 
+def eps_inverse_in_basis(E: np.ndarray) -> np.ndarray:
+    """(I + E(z))^-1 for every E(z) = Q^H (eps(z) - 1) Q of a list [n_z, k, k]
+    (Sec. IV: the dielectric matrix inverted in the small basis; eps^-1 within
+    span(Q) is 1 + Q ((I + E)^-1 - I) Q^H)."""
+    E = np.asarray(E)
+    k = E.shape[-1]
+    return np.array([np.linalg.inv(np.eye(k) + e) for e in E.reshape(-1, k, k)])
+
+
+def ritz_values(alpha: np.ndarray, beta: np.ndarray) -> np.ndarray:
+    """Ritz values of the Lanczos recursion (Sec. IV): the eigenvalues of the
+    tridiagonal T, ascending."""
+    return np.linalg.eigvalsh(tridiag(alpha, beta))
+
+
 def _qr_pos(W: np.ndarray):
     """Thin QR of the columns of W (n x b) with a non-negative diagonal of R."""
     Qf, R = np.linalg.qr(W)

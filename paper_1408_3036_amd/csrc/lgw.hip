@@ -3535,6 +3535,95 @@ lgw_status lgw_block_lanczos(lgw_ctx* c, int b, const lgw_c128* Q0, int nblk, lg
   }
 }
 
+// (I + E)^-1 of one k x k complex matrix (row-major) by Gaussian elimination
+// with partial pivoting on [I + E | I]; false when a pivot vanishes.
+static bool inverse_i_plus(const z64* E, int k, z64* out) {
+  const int w = 2 * k;
+  std::vector<z64> a((size_t)k * w, z64{0, 0});
+  for (int i = 0; i < k; ++i) {
+    for (int j = 0; j < k; ++j) a[(size_t)i * w + j] = E[(size_t)i * k + j];
+    a[(size_t)i * w + i].x += 1.0;
+    a[(size_t)i * w + k + i] = z64{1.0, 0.0};
+  }
+  auto mag = [](z64 v) { return std::hypot(v.x, v.y); };
+  for (int col = 0; col < k; ++col) {
+    int piv = col;
+    for (int i = col + 1; i < k; ++i)
+      if (mag(a[(size_t)i * w + col]) > mag(a[(size_t)piv * w + col])) piv = i;
+    const z64 pv = a[(size_t)piv * w + col];
+    const double den = pv.x * pv.x + pv.y * pv.y;
+    if (!(den > 0.0) || !std::isfinite(den)) return false;
+    if (piv != col)
+      for (int j = 0; j < w; ++j) std::swap(a[(size_t)piv * w + j], a[(size_t)col * w + j]);
+    const z64 inv{pv.x / den, -pv.y / den};
+    for (int j = 0; j < w; ++j) a[(size_t)col * w + j] = inv * a[(size_t)col * w + j];
+    for (int i = 0; i < k; ++i) {
+      if (i == col) continue;
+      const z64 f = a[(size_t)i * w + col];
+      if (f.x == 0.0 && f.y == 0.0) continue;
+      for (int j = 0; j < w; ++j) a[(size_t)i * w + j] = a[(size_t)i * w + j] - f * a[(size_t)col * w + j];
+    }
+  }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) out[(size_t)i * k + j] = a[(size_t)i * w + k + j];
+  return true;
+}
+
+lgw_status lgw_eps_inverse(lgw_ctx* c, int k, int n_z, const lgw_c128* E, lgw_c128* Einv) {
+  if (!c) return LGW_EINVAL;
+  if (k < 1 || n_z < 1 || !E || !Einv) return set_err(c, LGW_EINVAL, "invalid arguments");
+  try {
+    const size_t nb = (size_t)n_z * k * k * sizeof(z64);
+    std::vector<z64> h((size_t)n_z * k * k), o((size_t)n_z * k * k);
+    if (c->opts.mem == LGW_MEM_DEVICE) {
+      HIPCHK(hipMemcpyAsync(h.data(), E, nb, hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+    } else {
+      std::memcpy(h.data(), E, nb);
+    }
+    for (size_t v = 0; v < h.size(); ++v)
+      if (!std::isfinite(h[v].x) || !std::isfinite(h[v].y)) return set_err(c, LGW_ENAN, "non-finite value in E");
+    for (int iz = 0; iz < n_z; ++iz)
+      if (!inverse_i_plus(h.data() + (size_t)iz * k * k, k, o.data() + (size_t)iz * k * k))
+        return set_err(c, LGW_EBREAKDOWN, "I + E(z) is singular");
+    if (c->opts.mem == LGW_MEM_DEVICE) h2d(c, Einv, o.data(), nb);
+    else std::memcpy(Einv, o.data(), nb);
+    return LGW_OK;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_ritz_values(lgw_ctx* c, int k, const double* alpha, const double* beta, double* theta) {
+  if (!c) return LGW_EINVAL;
+  if (k < 1 || !alpha || !theta || (k > 1 && !beta)) return set_err(c, LGW_EINVAL, "invalid arguments");
+  try {
+    std::vector<double> a(k), b(k > 1 ? k - 1 : 1, 0.0);
+    if (c->opts.mem == LGW_MEM_DEVICE) {
+      HIPCHK(hipMemcpyAsync(a.data(), alpha, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      if (k > 1) HIPCHK(hipMemcpyAsync(b.data(), beta, (k - 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+    } else {
+      std::memcpy(a.data(), alpha, k * sizeof(double));
+      if (k > 1) std::memcpy(b.data(), beta, (k - 1) * sizeof(double));
+    }
+    std::vector<std::complex<double>> T((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) {
+      if (!std::isfinite(a[i]) || (i + 1 < k && !std::isfinite(b[i])))
+        return set_err(c, LGW_ENAN, "non-finite Lanczos coefficient");
+      T[(size_t)i * k + i] = a[i];
+      if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = b[i];
+    }
+    std::vector<double> w;
+    std::vector<std::complex<double>> V;
+    herm_eig(k, T.data(), w, V);
+    std::memcpy(theta, w.data(), k * sizeof(double));
+    return LGW_OK;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
 lgw_status lgw_project(lgw_ctx* c, int k, const lgw_c128* Q, int n_z, const lgw_c128* z, lgw_c128* E) {
   if (!c) return LGW_EINVAL;
   if (k < 1 || n_z < 1 || !Q || !z || !E) return set_err(c, LGW_EINVAL, "invalid arguments");

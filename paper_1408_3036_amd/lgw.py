@@ -98,6 +98,8 @@ def load_library():
     lib.lgw_sigma_traces.argtypes = [P, I, C.c_double, C.c_double, I, P, I, P, P, P, P]
     lib.lgw_sigma_residues.argtypes = [P, I, C.c_double, I, P, P]
     lib.lgw_tune_info.argtypes = [P, I, I, P, P, P, P]
+    lib.lgw_eps_inverse.argtypes = [P, I, I, P, P]
+    lib.lgw_ritz_values.argtypes = [P, I, P, P, P]
     lib.lgw_vhalf.argtypes = [P, I, P, P]
     lib.lgw_get_info.argtypes = [P, C.POINTER(Info)]
     lib.lgw_sphere.argtypes = [P, C.POINTER(I)]
@@ -110,7 +112,8 @@ def load_library():
     lib.lgw_free.restype = None
     for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_block_lanczos",
                  "lgw_chi0_apply_many", "lgw_chi0_apply_vjp", "lgw_hpsi", "lgw_hpsi_noalloc",
-                 "lgw_sigma_traces", "lgw_sigma_residues", "lgw_tune_info",
+                 "lgw_sigma_traces", "lgw_sigma_residues", "lgw_tune_info", "lgw_eps_inverse",
+                 "lgw_ritz_values",
                  "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats", "lgw_profile",
                  "lgw_kernel_timing"]:
         getattr(lib, name).restype = I
@@ -344,6 +347,30 @@ class Lgw:
         self.last_status = self._check(
             self.lib.lgw_project(self.ctx, k, Q.data_ptr(), nz, zarr, E.data_ptr()))
         return E
+
+    def eps_inverse(self, E):
+        """(I + E[z])^-1 for E [n_z, k, k] complex128 (lgw_eps_inverse)."""
+        t = self.torch
+        E = self._dev(E, t.complex128)
+        if E.dim() == 2:
+            E = E[None]
+        nz, k = E.shape[0], E.shape[1]
+        out = t.empty_like(E)
+        t.cuda.current_stream().synchronize()
+        self._check(self.lib.lgw_eps_inverse(self.ctx, k, nz, E.data_ptr(), out.data_ptr()))
+        return out
+
+    def ritz_values(self, alpha, beta):
+        """Eigenvalues of the Lanczos tridiagonal (lgw_ritz_values), ascending."""
+        t = self.torch
+        alpha = self._dev(alpha, t.float64).reshape(-1)
+        k = alpha.shape[0]
+        beta = self._dev(beta, t.float64).reshape(-1) if k > 1 else None
+        theta = np.zeros(k)
+        t.cuda.current_stream().synchronize()
+        self._check(self.lib.lgw_ritz_values(self.ctx, k, alpha.data_ptr(),
+                                             beta.data_ptr() if beta is not None else None, theta.ctypes.data))
+        return theta
 
     def hpsi(self, x, shift: complex = 0.0):
         t = self.torch

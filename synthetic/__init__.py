@@ -10,9 +10,9 @@ Lanczos arithmetic: those live, independently, in the oracle and in the HIP
 library.
 """
 from .workloads import (CONFIGS, Workload, make_workload, gaussian_wells,
-                        random_potentials, imag_freqs, real_freqs, HA_PER_EV)
+                        random_potentials, smooth_directions, imag_freqs, real_freqs, HA_PER_EV)
 from .ground_state import ground_state
 
 __all__ = ["CONFIGS", "Workload", "make_workload", "gaussian_wells",
-           "random_potentials", "imag_freqs", "real_freqs", "ground_state",
+           "random_potentials", "smooth_directions", "imag_freqs", "real_freqs", "ground_state",
            "HA_PER_EV"]

@@ -80,6 +80,24 @@ def random_potentials(N: int, n: int, seed, real: bool = True) -> np.ndarray:
     return x / np.linalg.norm(x, axis=1, keepdims=True)
 
 
+def smooth_directions(N: int, L: float, seed, n: int, n_bumps: int = 3, width: float = 1.5) -> list:
+    """n smooth real potential displacements on the N^3 grid of an L box (for
+    directional derivatives): each a sum of n_bumps periodic Gaussian bumps of
+    the given width, centres uniform in the box, N(0,1) amplitudes; draws
+    from default_rng(seed) in the order centre, amplitude per bump."""
+    rng = np.random.default_rng(seed)
+    r = L * np.stack(np.meshgrid(*[np.arange(N)] * 3, indexing="ij"), -1) / N
+    out = []
+    for _ in range(n):
+        d = np.zeros((N,) * 3)
+        for _ in range(n_bumps):
+            c = rng.uniform(0, L, 3)
+            dd = (r - c + L / 2) % L - L / 2
+            d += rng.standard_normal() * np.exp(-np.sum(dd ** 2, -1) / (2 * width ** 2))
+        out.append(d)
+    return out
+
+
 # (L, N, ecut, n_wells, n_v, lanczos_steps, frequency recipe)
 CONFIGS = {
     1: dict(name="tiny-16", L=10.0, N=16, ecut=6.0, n_wells=5, n_v=4, lanczos=8,

@@ -7,6 +7,8 @@ on the rest: Hermiticity and sign of chi0 on the imaginary axis, agreement of
 the solver forms and precisions, Lanczos invariants, and the gradient against
 central differences of the loss.
 """
+import json
+import os
 import time
 
 import numpy as np
@@ -19,11 +21,16 @@ pytestmark = pytest.mark.gpu
 from oracle.pw import Basis
 from oracle.sternheimer import MatrixFree
 from oracle import lanczos as olz
-from synthetic import make_workload, random_potentials
+from synthetic import make_workload, random_potentials, smooth_directions
 from synthetic.ground_state import ground_state
 from tests.gpu_common import lib_order, rel, colwise_rel
 
 FAST = dict(precond=True, imag_form="shifted")
+# adjoint against the oracle's central differences (tests/golden/c5_oracle.json):
+# Richardson with h = 1e-2 leaves about 4e-8 of the step-h difference; the
+# differences also carry the oracle loss's solver error over 2h (measured
+# agreement 1.3e-8 and 7e-11 on the two directions)
+GRAD_TOL = 1e-6
 
 
 def _lgw(w, V=None, psi=None, eps=None, **kw):
@@ -206,8 +213,6 @@ def test_lanczos_loss_gradient_silane48():
         lg.close()
     assert kd == k
     gV = gV.cpu().numpy()
-    rng = np.random.default_rng(74)
-    r = w.L * np.stack(np.meshgrid(*[np.arange(w.N)] * 3, indexing="ij"), -1) / w.N
 
     def loss_at(V):
         psi, eps, _ = ground_state(V, w.L, w.ecut, w.n_v)
@@ -216,12 +221,7 @@ def test_lanczos_loss_gradient_silane48():
             return l2.lanczos_loss_vjp(q0, k, zs, want_V=False)[0]
         finally:
             l2.close()
-    for i in range(2):
-        d = np.zeros((w.N,) * 3)
-        for _ in range(3):
-            c = rng.uniform(0, w.L, 3)
-            dd = (r - c + w.L / 2) % w.L - w.L / 2
-            d += rng.standard_normal() * np.exp(-np.sum(dd ** 2, -1) / (2 * 1.5 ** 2))
+    for i, d in enumerate(smooth_directions(w.N, w.L, 74, 2)):
         h = 1e-2
         f1 = (loss_at(w.V + h * d) - loss_at(w.V - h * d)) / (2 * h)
         f2 = (loss_at(w.V + 2 * h * d) - loss_at(w.V - 2 * h * d)) / (4 * h)
@@ -230,6 +230,39 @@ def test_lanczos_loss_gradient_silane48():
         err = abs(got - fd) / abs(fd)
         print(f"silane-48 loss gradient, direction {i}: grad.d {got:.10e} FD {fd:.10e} rel {err:.2e}")
         assert err < 1e-5
+
+
+def test_lanczos_loss_and_gradient_silane48_against_oracle():
+    """The differentiation workload against the oracle: the library's log-det
+    loss (64 Lanczos vectors, z = 0 and four imaginary frequencies) and its
+    adjoint gradient dL/dV_loc along the two seeded smooth directions, against
+    the oracle's loss and the oracle's Richardson central differences (ground
+    state recomputed at each displaced potential), stored in
+    tests/golden/c5_oracle.json by tests/golden/make_c5_oracle.py, which calls
+    only the oracle and the seeded inputs."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c5_oracle.json")) as fh:
+        gold = json.load(fh)
+    w = make_workload(2)
+    zs = [1j * x for x in gold["z_imag"]]
+    zs[0] = 0.0
+    q0 = torch.from_numpy(random_potentials(w.N, 1, gold["q0_seed"])[0])
+    lg = _lgw(w, tol=1e-13, **FAST)
+    try:
+        L, gV, kd = lg.lanczos_loss_vjp(q0, gold["k"], zs)
+    finally:
+        lg.close()
+    assert kd == gold["k"]
+    eL = abs(L - gold["loss"]) / abs(gold["loss"])
+    print(f"silane-48 loss: library {L:.15f}, oracle {gold['loss']:.15f}, rel {eL:.2e}")
+    assert eL < 1e-10
+    gV = gV.cpu().numpy()
+    ds = smooth_directions(w.N, w.L, 74, 2)
+    for ent in gold["dL_dV_dot_d"]:
+        got = float(np.dot(gV, ds[ent["index"]].reshape(-1)))
+        fd = ent["richardson"]
+        err = abs(got - fd) / abs(fd)
+        print(f"direction {ent['index']}: adjoint {got:.10e}, oracle differences {fd:.10e}, rel {err:.2e}")
+        assert err < GRAD_TOL
 
 
 def test_silane48_recycling_against_direct_projection():

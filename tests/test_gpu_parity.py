@@ -112,6 +112,36 @@ def test_project_matches_oracle(sysc1):
         assert rel(E[k], Eref[k]) < 1e-10
 
 
+def test_eps_inverse_and_ritz_values_match_oracle(sysc1):
+    """(I + E(z))^-1 in the Lanczos basis and the Ritz values of the
+    tridiagonal (Sec. IV) against the oracle, on the oracle's own basis,
+    E(z) and coefficients; and the error paths of the inverse."""
+    from paper_1408_3036_amd.lgw import LgwError
+    w, b, s, lg = sysc1
+    q0 = random_potentials(w.N, 1, 21)[0]
+    ra, rb, RQ, _ = olz.lanczos(lambda v: s.M(0.0, v), q0, 8)
+    zs = [0.0, 0.3j, 2.0j, 0.5 + 0.0036749j]
+    Eref = olz.project(lambda z, v: s.M(z, v), RQ, zs)
+    inv = lg.eps_inverse(torch.from_numpy(Eref)).cpu().numpy()
+    ref = olz.eps_inverse_in_basis(Eref)
+    for k in range(len(zs)):
+        err = rel(inv[k], ref[k])
+        print(f"(I + E)^-1 at z={zs[k]}: rel {err:.1e}")
+        assert err < 1e-12
+    th = lg.ritz_values(torch.from_numpy(ra), torch.from_numpy(rb))
+    th_ref = olz.ritz_values(ra, rb)
+    assert np.abs(th - th_ref).max() <= 1e-12 * np.abs(th_ref).max()
+    assert np.all(np.diff(th) >= 0)
+    with pytest.raises(LgwError) as e:
+        lg.eps_inverse(-torch.eye(3, dtype=torch.complex128))
+    assert e.value.name == "LGW_EBREAKDOWN"
+    bad = np.zeros((1, 2, 2), dtype=complex)
+    bad[0, 1, 0] = np.nan
+    with pytest.raises(LgwError) as e:
+        lg.eps_inverse(torch.from_numpy(bad))
+    assert e.value.name == "LGW_ENAN"
+
+
 def test_mixed_precision_chi0_within_1e6(sysc1):
     from paper_1408_3036_amd import Lgw
     w, b, s, _ = sysc1
