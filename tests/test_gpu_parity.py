@@ -87,6 +87,58 @@ def test_chi0_many_columns_and_frequencies_in_one_call(sysc1):
         assert colwise_rel(dn[k], s.chi0(z, x)) < 1e-10
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_degenerate_and_empty_inputs(sysc1, precision):
+    """A zero perturbation gives a zero response (every band system has a zero
+    right-hand side); no columns gives empty outputs; a zero starting vector
+    and non-finite inputs are refused before any solve."""
+    from paper_1408_3036_amd import Lgw
+    from paper_1408_3036_amd.lgw import LgwError
+    w, b, s, _ = sysc1
+    lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps,
+             precision=precision, tol=1e-10 if precision == "mixed" else 1e-13)
+    try:
+        n3 = w.N ** 3
+        zs = [0.0, 0.3j, 0.5 + 0.0036749j]
+        x = np.zeros((3, n3), dtype=complex)
+        x[1] = random_potentials(w.N, 1, 31)[0]          # one real column between two zero ones
+        dn = lg.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+        assert not np.any(dn[:, 0]) and not np.any(dn[:, 2])
+        for k, z in enumerate(zs):
+            err = rel(dn[k, 1], s.chi0(z, x[1:2])[0])
+            assert err < (1e-6 if precision == "mixed" else 1e-10), (z, err)
+        assert lg.chi0_apply(torch.zeros((0, n3), dtype=torch.complex128), zs).shape == (3, 0, n3)
+        with pytest.raises(LgwError) as e:
+            lg.lanczos(torch.zeros(n3, dtype=torch.complex128), 4)
+        assert e.value.name == "LGW_EINVAL"
+        x[1, 5] = np.nan
+        with pytest.raises(LgwError) as e:
+            lg.chi0_apply(torch.from_numpy(x), [0.3j])
+        assert e.value.name == "LGW_ENAN"
+        with pytest.raises(LgwError) as e:
+            lg.chi0_apply(torch.from_numpy(x[:1]), [complex(np.inf, 0.0)])
+        assert e.value.name == "LGW_ENAN"
+    finally:
+        lg.close()
+
+
+def test_chi0_batch_split_by_the_workspace_budget(sysc1):
+    """More band systems than the workspace budget holds at once (the smallest
+    budget, 0.25 GB, holds about 1,700 systems at this size): the call runs in
+    several batches and every column still matches the oracle."""
+    from paper_1408_3036_amd import Lgw
+    w, b, s, _ = sysc1
+    lg = Lgw(w.L, w.N, w.ecut, torch.from_numpy(w.V), torch.from_numpy(w.psi), w.eps, mem_budget_gb=0.25)
+    try:
+        zs = list(1j * np.geomspace(0.02, 2.0, 8))
+        x = random_potentials(w.N, 60, 32)                 # 60 x 4 bands x 8 z = 1,920 systems
+        dn = lg.chi0_apply(torch.from_numpy(x), zs).cpu().numpy()
+        for k, z in enumerate(zs):
+            assert colwise_rel(dn[k], s.chi0(z, x)) < 1e-10
+    finally:
+        lg.close()
+
+
 def test_lanczos_matches_oracle(sysc1):
     w, b, s, lg = sysc1
     q0 = random_potentials(w.N, 1, 8)[0]
