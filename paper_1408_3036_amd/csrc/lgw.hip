@@ -1002,7 +1002,17 @@ void solve(lgw_ctx* c, int kind, const z64* B, const std::vector<int>& bidx, con
       // FP32 SQMR stops on a 32-iteration stagnation window like the FP64 one
       // (an iterate pushed past its attainable accuracy spoils the correction);
       // CG keeps a longer window for slowly converging imaginary-axis systems
-      run_batch<float>(c, b, R32, npw, nullptr, false, inner, bad, kind == K_SQMR ? 32 : 96, sweep);
+      // a sweep needs only the reduction that takes the worst listed system
+      // from its FP64 residual to tol (with a factor 4 to spare): the
+      // requested inner tolerance or that, whichever is looser, rounded down
+      // to a half decade (the tolerance is baked into the replayed graphs,
+      // so it takes few distinct values)
+      double worst_rel = 0.0;
+      for (int s : bad) worst_rel = std::max(worst_rel, out.rel[s]);
+      double inner_s = inner;
+      if (worst_rel > 0.0 && 0.25 * tol / worst_rel > inner)
+        inner_s = std::max(inner, std::pow(10.0, std::floor(2.0 * std::log10(0.25 * tol / worst_rel)) / 2.0));
+      run_batch<float>(c, b, R32, npw, nullptr, false, inner_s, bad, kind == K_SQMR ? 32 : 96, sweep);
       h2d_param(c, d_act, bad.data(), bad.size() * sizeof(int));
       launch_cvt_32_64_axpy(b.v.x, X, rs, d_act, npw, npw, (int)bad.size(), c->stream, b.pre, !x_set);
       x_set = true;
