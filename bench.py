@@ -331,7 +331,7 @@ def bench_sigma(w, lg_kw, q0, log_fn):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--lanczos", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
@@ -476,7 +476,7 @@ def main():
             st_ = lg.stats()
             it += st_["total_iters"]
             ha += st_["total_happly"]
-            log(f"[{mode}] step {i}: {time.perf_counter() - s0:.2f}s iters {st_['total_iters']} "
+            log(f"[{mode}] step {i}: {time.perf_counter() - s0:.4f}s iters {st_['total_iters']} "
                 f"H {st_['total_happly']}")
         el = time.perf_counter() - t
         kt = lg.kernel_timing()

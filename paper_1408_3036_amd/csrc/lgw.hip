@@ -34,6 +34,9 @@
 #endif
 // chunk with the multi-shift solver: its recursion is latency-bound for a few
 // systems, so it takes more vectors at a time
+#ifndef LGW_MAX_GRAPHS
+#define LGW_MAX_GRAPHS 64
+#endif
 #ifndef LGW_PROJECT_CHUNK_MS
 #define LGW_PROJECT_CHUNK_MS 16
 #endif
@@ -479,7 +482,7 @@ void replay(lgw_ctx* c, uintptr_t tag, int nsys, std::vector<uintptr_t> key, F&&
   key.insert(key.begin(), {tag, (uintptr_t)nsys});
   auto f = c->graphs.find(key);
   if (f == c->graphs.end()) {
-    if (c->graphs.size() >= 64) c->drop_graphs();
+    if (c->graphs.size() >= LGW_MAX_GRAPHS) c->drop_graphs();
     const long long h0 = c->tot_h;
     hipGraph_t gr = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
@@ -777,7 +780,7 @@ void run_batch(lgw_ctx* c, Batch<T>& b, const cplx<T>* B, long ldb, const int* b
       if (f != c->graphs.end()) {
         gx = f->second;
       } else {
-        if (c->graphs.size() >= 64) c->drop_graphs();
+        if (c->graphs.size() >= LGW_MAX_GRAPHS) c->drop_graphs();
         (void)c->buf<cplx<T>>(sizeof(T) == 8 ? "proj.part64" : "proj.part32",
                               (size_t)proj_ksplit<T>(c->npw, na) * na * c->nv);
         const long long h0 = c->tot_h;
@@ -2455,7 +2458,8 @@ void autotune_plane(lgw_ctx* c) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  for (auto [f32, b] : todo) {
+  for (const auto& fb : todo) {
+    const int f32 = fb.first, b = fb.second;
     const size_t e = f32 ? sizeof(z32) : sizeof(z64);
     const int rep = (int)std::max<long>(1, std::min<long>(kTuneRep[b], (long)(cap_bytes / (ldt * e))));
     buf.ensure((size_t)rep * ldt * e);
