@@ -1,6 +1,9 @@
 """Host logic: the library's small Hermitian eigensolver (csrc/herm_eig.h),
 compiled with g++ into a tiny driver and compared with numpy.linalg.eigh on
-random, degenerate, diagonal and tiny matrices."""
+random, degenerate, diagonal and tiny matrices.  The driver is built twice:
+plain, and with AddressSanitizer and UndefinedBehaviorSanitizer (host code
+only), so an out-of-bounds access or undefined operation in the eigensolver
+fails the run."""
 import os
 import shutil
 import subprocess
@@ -26,8 +29,11 @@ int main() {
 """
 
 
-@pytest.fixture(scope="module")
-def driver(tmp_path_factory):
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+@pytest.fixture(scope="module", params=["plain", "sanitized"])
+def driver(request, tmp_path_factory):
     gxx = shutil.which("g++")
     if not gxx:
         pytest.skip("g++ not available")
@@ -35,8 +41,14 @@ def driver(tmp_path_factory):
     src = d / "drv.cpp"
     src.write_text(DRIVER)
     exe = d / "drv"
-    subprocess.run([gxx, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_1408_3036_amd", "csrc"),
-                    str(src), "-o", str(exe)], check=True)
+    flags = SANITIZE if request.param == "sanitized" else []
+    r = subprocess.run([gxx, "-O2", "-g", "-std=c++17", *flags, "-I",
+                        os.path.join(ROOT, "paper_1408_3036_amd", "csrc"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        if request.param == "sanitized":
+            pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+        raise RuntimeError(r.stderr)
     return str(exe)
 
 
