@@ -165,6 +165,21 @@ lgw_status lgw_chi0_apply_many(int n_sys, lgw_ctx* const* ctx, const int* n_rhs,
 lgw_status lgw_lanczos(lgw_ctx* ctx, const lgw_c128* q0, int k, double* alpha, double* beta,
                        lgw_c128* Q, int* k_done);
 
+/* Continues a Lanczos recursion of lgw_lanczos from a prior state (Sec. IV;
+ * a recursion checkpointed after k0 steps goes on to k steps).
+ *   Q     [k][N^3] in/out: rows q_0..q_{k0-1} of the prior recursion on
+ *         input; rows q_0..q_{k_done-1} on return (the first k0 - 1
+ *         unchanged).
+ *   alpha, beta [k] in/out: entries 0..k0-1 of the prior recursion on input;
+ *         entries 0..k_done-1 on return.
+ * Step k0 - 1 is computed again (one chi0 application) to recover
+ * q_{k0}; with the prior state as this library wrote it, the result is that
+ * of one uninterrupted k-step call.  LGW_EINVAL unless 1 <= k0 <= k and the
+ * prior state has beta > 0 before step k0 - 1; LGW_ENAN on non-finite
+ * input.  Memory per opts.mem. */
+lgw_status lgw_lanczos_resume(lgw_ctx* ctx, int k0, int k, double* alpha, double* beta, lgw_c128* Q,
+                              int* k_done);
+
 /* Block Lanczos with full reorthogonalisation on M = eps(0) - 1, the block
  * form of the Sec. IV construction: b starting vectors (rows of Q0,
  * orthonormalised first), nblk block steps, each applying M to b vectors in

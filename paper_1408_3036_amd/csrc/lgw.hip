@@ -1927,8 +1927,11 @@ lgw_status lanczos_start(lgw_ctx* c, const lgw_c128* q0, z64* Q) {
 // beta_{j-1} up to rounding on q_{j-1}, so it also performs the three-term
 // recurrence's subtraction), beta_j = |w|, q_{j+1} = w / beta_j.  Stops early
 // when beta_j < 1e-14 max|alpha|.  W0 (or null) keeps every product M q_j.
+// j0 > 0 resumes a recursion whose vectors q_0..q_{j0} are in Qd and whose
+// coefficients alpha, beta up to j0 - 1 are in d_alpha, d_beta (amax0 = the
+// largest |alpha| among them): steps j0..k-1 run as they would have.
 lgw_status lanczos_core(lgw_ctx* c, int k, z64* Qd, z64* W0, double* d_alpha, double* d_beta, int* done_out,
-                        const std::function<void(int)>& ready = nullptr) {
+                        const std::function<void(int)>& ready = nullptr, int j0 = 0, double amax0 = 0.0) {
   const long n3 = c->n3;
   z64* wbuf = c->buf<z64>("lz.w", n3);
   z64* h = c->buf<z64>("lz.h", k);
@@ -1936,9 +1939,9 @@ lgw_status lanczos_core(lgw_ctx* c, int k, z64* Qd, z64* W0, double* d_alpha, do
   double* pair = c->buf<double>("lz.pair", 2);
   lgw_status st = LGW_OK;
   SolveTally tally;
-  double amax = 0.0;
-  int done = 0;
-  for (int j = 0; j < k; ++j) {
+  double amax = amax0;
+  int done = j0;
+  for (int j = j0; j < k; ++j) {
     z64* qj = Qd + (size_t)j * n3;
     // the product lands in W0[j] when the caller keeps the products, and the
     // three-term update reads it from there into wbuf
@@ -2996,6 +2999,71 @@ lgw_status lgw_lanczos(lgw_ctx* c, const lgw_c128* q0, int k, double* alpha, dou
       c->sync();
       finish_out(c, Q, dq, qb);
     }
+    c->sync();
+    *k_done = done;
+    if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";
+    return st;
+  } catch (const Fail& f) {
+    return set_err(c, f.st, f.msg);
+  }
+}
+
+lgw_status lgw_lanczos_resume(lgw_ctx* c, int k0, int k, double* alpha, double* beta, lgw_c128* Q, int* k_done) {
+  if (!c) return LGW_EINVAL;
+  if (k0 < 1 || k < k0 || !alpha || !beta || !Q || !k_done) return set_err(c, LGW_EINVAL, "invalid arguments");
+  try {
+    const long n3 = c->n3;
+    z64* Qd = c->buf<z64>("lz.Q", (size_t)k * n3);
+    double* ab = c->buf<double>("lz.ab", 2 * (size_t)k);
+    double* d_alpha = ab;
+    double* d_beta = ab + k;
+    // the prior state: q_0..q_{k0-1} and their coefficients
+    std::vector<double> ha(k0), hb(k0);
+    if (c->opts.mem == LGW_MEM_DEVICE) {
+      HIPCHK(hipMemcpyAsync(ha.data(), alpha, k0 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(hb.data(), beta, k0 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      c->sync();
+    } else {
+      std::memcpy(ha.data(), alpha, k0 * sizeof(double));
+      std::memcpy(hb.data(), beta, k0 * sizeof(double));
+    }
+    double amax0 = 0.0;
+    for (int j = 0; j < k0; ++j) {
+      if (!std::isfinite(ha[j]) || !std::isfinite(hb[j])) return set_err(c, LGW_ENAN, "non-finite Lanczos coefficient");
+      if (j + 1 < k0) {
+        if (!(hb[j] > 0.0)) return set_err(c, LGW_EINVAL, "the prior recursion broke down before k0");
+        amax0 = std::max(amax0, std::abs(ha[j]));
+      }
+    }
+    const z64* dq = static_cast<const z64*>(stage_in(c, Q, (size_t)k0 * n3 * sizeof(z64), "io.Qres"));
+    int* d_flag = c->buf<int>("flag", 1);
+    HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), c->stream));
+    launch_finite_check(reinterpret_cast<const double*>(dq), 2 * (long)k0 * n3, d_flag, c->stream);
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    if (hflag) return set_err(c, LGW_ENAN, "non-finite value in Q");
+    launch_xyz_to_zxy(c->N, dq, n3, Qd, n3, k0, false, c->stream);
+    if (k0 > 1) {
+      h2d(c, d_alpha, ha.data(), (k0 - 1) * sizeof(double));
+      h2d(c, d_beta, hb.data(), (k0 - 1) * sizeof(double));
+    }
+    // step k0 - 1 runs again (one chi0 application) to produce q_{k0}
+    int done = 0;
+    const lgw_status st = lanczos_core(c, k, Qd, nullptr, d_alpha, d_beta, &done, nullptr, k0 - 1, amax0);
+    if (c->opts.mem == LGW_MEM_DEVICE) {
+      HIPCHK(hipMemcpyAsync(alpha, d_alpha, done * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(beta, d_beta, done * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(alpha, d_alpha, done * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipMemcpyAsync(beta, d_beta, done * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    const size_t qb = (size_t)done * n3 * sizeof(z64);
+    z64* qo = static_cast<z64*>(stage_out(c, Q, qb, "io.Qout"));
+    launch_zxy_to_xyz(c->N, Qd, n3, qo, n3, done, c->stream);
+    c->check_launch();
+    c->sync();
+    finish_out(c, Q, qo, qb);
     c->sync();
     *k_done = done;
     if (st != LGW_OK) c->err = "some Sternheimer solves did not converge";

@@ -99,6 +99,7 @@ def load_library():
     lib.lgw_sigma_residues.argtypes = [P, I, C.c_double, I, P, P]
     lib.lgw_tune_info.argtypes = [P, I, I, P, P, P, P]
     lib.lgw_eps_inverse.argtypes = [P, I, I, P, P]
+    lib.lgw_lanczos_resume.argtypes = [P, I, I, P, P, P, P]
     lib.lgw_ritz_values.argtypes = [P, I, P, P, P]
     lib.lgw_vhalf.argtypes = [P, I, P, P]
     lib.lgw_get_info.argtypes = [P, C.POINTER(Info)]
@@ -113,7 +114,7 @@ def load_library():
     for name in ["lgw_setup", "lgw_chi0_apply", "lgw_lanczos", "lgw_project", "lgw_block_lanczos",
                  "lgw_chi0_apply_many", "lgw_chi0_apply_vjp", "lgw_hpsi", "lgw_hpsi_noalloc",
                  "lgw_sigma_traces", "lgw_sigma_residues", "lgw_tune_info", "lgw_eps_inverse",
-                 "lgw_ritz_values",
+                 "lgw_ritz_values", "lgw_lanczos_resume",
                  "lgw_vhalf", "lgw_get_info", "lgw_sphere", "lgw_get_stats", "lgw_profile",
                  "lgw_kernel_timing"]:
         getattr(lib, name).restype = I
@@ -265,6 +266,24 @@ class Lgw:
             Q.data_ptr() if Q is not None else None, C.byref(kd)))
         n = kd.value
         return alpha[:n], beta[:n], (Q[:n] if Q is not None else None), n
+
+    def lanczos_resume(self, alpha, beta, Q, k: int):
+        """Continue a recursion from its first k0 = len(alpha) steps (alpha,
+        beta [k0], Q [k0, N^3]) to k steps (lgw_lanczos_resume)."""
+        t = self.torch
+        k0 = int(alpha.shape[0])
+        a = t.zeros(k, dtype=t.float64, device="cuda")
+        b = t.zeros(k, dtype=t.float64, device="cuda")
+        Qo = t.zeros((k, self.N ** 3), dtype=t.complex128, device="cuda")
+        a[:k0] = self._dev(alpha, t.float64)
+        b[:k0] = self._dev(beta, t.float64)
+        Qo[:k0] = self._dev(Q, t.complex128).reshape(k0, -1)
+        kd = C.c_int(0)
+        t.cuda.current_stream().synchronize()
+        self.last_status = self._check(self.lib.lgw_lanczos_resume(
+            self.ctx, k0, k, a.data_ptr(), b.data_ptr(), Qo.data_ptr(), C.byref(kd)))
+        n = kd.value
+        return a[:n], b[:n], Qo[:n], n
 
     def lanczos_loss_vjp(self, q0, k: int, z, want_V: bool = True):
         """L = sum_z log det(I + Q^H (eps(z)-1) Q) with Q the k-step Lanczos

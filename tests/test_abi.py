@@ -85,5 +85,6 @@ def test_calls_on_null_context_fail_cleanly():
     assert lib.lgw_project(None, 1, None, 1, None, None) == 1
     assert lib.lgw_eps_inverse(None, 1, 1, None, None) == 1
     assert lib.lgw_ritz_values(None, 1, None, None, None) == 1
+    assert lib.lgw_lanczos_resume(None, 1, 2, None, None, None, None) == 1
     assert lib.lgw_lanczos_recycle(None, None, 1, 1, None, None, None, None, None, None) == 1
     lib.lgw_free(None)

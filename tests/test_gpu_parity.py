@@ -153,6 +153,27 @@ def test_lanczos_matches_oracle(sysc1):
     assert np.abs(Q.conj() @ Q.T - np.eye(k)).max() < 1e-13
 
 
+def test_lanczos_resumes_from_a_prior_state(sysc1):
+    """A recursion checkpointed after 4 steps and resumed to 8 gives the
+    uninterrupted 8-step result (the library's reductions are in fixed order,
+    so up to nothing but the repeated step's own arithmetic), and both match
+    the oracle."""
+    w, b, s, lg = sysc1
+    q0 = torch.from_numpy(random_potentials(w.N, 1, 8)[0])
+    a8, b8, Q8, k8 = lg.lanczos(q0, 8)
+    a4, b4, Q4, k4 = lg.lanczos(q0, 4)
+    a, be, Q, kd = lg.lanczos_resume(a4, b4, Q4, 8)
+    assert k8 == kd == 8 and k4 == 4
+    da = float((a - a8).abs().max() / a8.abs().max())
+    db = float((be - b8).abs().max() / a8.abs().max())
+    dq = float((Q - Q8).abs().max())
+    print(f"resumed against uninterrupted: alpha {da:.1e}, beta {db:.1e}, Q {dq:.1e}")
+    assert da < 1e-13 and db < 1e-13 and dq < 1e-13
+    ra, rb, RQ, _ = olz.lanczos(lambda v: s.M(0.0, v), q0.numpy(), 8)
+    assert np.abs(a.cpu().numpy() - ra).max() <= 1e-10 * np.abs(ra).max()
+    assert colwise_rel(Q.cpu().numpy(), RQ) < 1e-10
+
+
 def test_project_matches_oracle(sysc1):
     w, b, s, lg = sysc1
     q0 = random_potentials(w.N, 1, 9)[0]
