@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 #include <map>
@@ -215,9 +216,20 @@ struct lgw_ctx {
     if (!(count * sizeof(T) <= b.n && b.p)) {
       drop_graphs();
       up_cache.clear();
+      b.ensure(count * sizeof(T));
+      if (poison_workspace()) HIPCHK(hipMemsetAsync(b.p, 0xFF, b.n, stream));
     }
-    b.ensure(count * sizeof(T));
     return b.as<T>();
+  }
+  // LGW_POISON=1 (read once per process): every workspace buffer starts
+  // filled with 0xFF bytes, a NaN in every floating-point type, so that a
+  // kernel reading workspace it never wrote turns its results into NaN
+  static bool poison_workspace() {
+    static const bool on = [] {
+      const char* e = std::getenv("LGW_POISON");
+      return e && std::atoi(e) != 0;
+    }();
+    return on;
   }
   void sync() {
     HIPCHK(hipStreamSynchronize(stream));
