@@ -13,6 +13,13 @@
  *     footnote on the symmetric form, Sec. IV);
  *   * eps(z) - 1 projected on that static Lanczos basis (Sec. VI).
  *
+ * Around that path: shift-Lanczos (multi-shift) solves and frequency
+ * recycling (Sec. VI), the model dielectric operator (Sec. V), eps^-1 and the
+ * Ritz values in the basis (Sec. IV), the correlation self-energy traces and
+ * residues in the basis (Secs. II, III.B, IV, VI), adjoints of the chi0 apply
+ * and of a log-det loss, a resumable Lanczos recursion, and an H application
+ * that allocates nothing.
+ *
  * Discretisation (the paper leaves ABINIT's conventions implicit; this is the
  * reading implemented): orthorhombic box with edges L = (Lx, Ly, Lz), a cubic
  * N^3 grid r_n = (n_x Lx, n_y Ly, n_z Lz) / N, Omega = Lx Ly Lz, dV = Omega/N^3;
