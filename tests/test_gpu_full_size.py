@@ -23,7 +23,7 @@ from oracle.sternheimer import MatrixFree
 from oracle import lanczos as olz
 from synthetic import make_workload, random_potentials, smooth_directions
 from synthetic.ground_state import ground_state
-from tests.gpu_common import lib_order, rel, colwise_rel
+from tests.gpu_common import lib_order, rel, colwise_rel, tridiag_of, block_tridiag_of
 
 FAST = dict(precond=True, imag_form="shifted")
 # adjoint against the oracle's central differences (tests/golden/c5_oracle.json):
@@ -100,7 +100,7 @@ def test_silane48_batched_sampled_against_oracle():
     lg = _lgw(w, precision="mixed", tol=1e-10, **FAST)
     l64 = _lgw(w, tol=1e-13, **FAST)
     try:
-        X = lg.vhalf(torch.from_numpy(random_potentials(w.N, 16, 71)))
+        X = torch.from_numpy(b.apply_vhalf(random_potentials(w.N, 16, 71)))
         zs = list(w.z)
         dn = lg.chi0_apply(X, zs).cpu().numpy()
         st = lg.stats()
@@ -159,7 +159,7 @@ def test_large72_full_size():
     fast = _lgw(w, tol=1e-13, **FAST)
     mixed = _lgw(w, precision="mixed", tol=1e-10, **FAST)
     try:
-        X = plain.vhalf(torch.from_numpy(random_potentials(w.N, 8, 72)))
+        X = torch.from_numpy(b.apply_vhalf(random_potentials(w.N, 8, 72)))
         # static column against the oracle
         d0 = {n: l.chi0_apply(X[:1], [0.0]).cpu().numpy()[0, 0] for n, l in
               (("plain", plain), ("fast", fast), ("mixed", mixed))}
@@ -186,7 +186,7 @@ def test_large72_full_size():
         assert nd == 2
         Qh = Q.cpu().numpy()
         assert np.abs(Qh.conj() @ Qh.T - np.eye(16)).max() < 1e-12
-        T = olz.block_tridiag(A.cpu().numpy(), B.cpu().numpy())
+        T = block_tridiag_of(A.cpu().numpy(), B.cpu().numpy())
         E0 = fast.project(Q, [0.0]).cpu().numpy()[0]
         assert np.abs(E0 - T).max() < 1e-9 * np.abs(T).max()
     finally:
@@ -291,15 +291,16 @@ def test_silane48_recycling_against_direct_projection():
         lg.close()
     assert kd == 64
     E = E.cpu().numpy()
-    T = olz.tridiag(a.cpu().numpy(), be.cpu().numpy())
+    T = tridiag_of(a.cpu().numpy(), be.cpu().numpy())
     assert rel(E[0], T) < 1e-8
     errs = [rel(E[i], Ed[i]) for i in range(len(ws))]
     print(f"silane-48 recycling: lanczos+recycle {t_rec:.3f}s (lanczos alone {t_lz:.3f}s); "
           f"rel. deviation from direct projection: max {max(errs):.2e} "
           f"(w=0 {errs[0]:.1e}, w={ws[5]:.3f} {errs[5]:.1e}, w={ws[-1]:.2f} {errs[-1]:.1e})")
     # the recycled E(i w) is an approximation away from w = 0 (Sec. VI); its
-    # deviation from the direct projection measured 1.1e-3 at most at this
-    # workload, bounded here with a small margin
+    # deviation from the direct projection measured 1.1e-3 to 1.4e-3 at this
+    # workload (it moves with the mixed solves' stopping point), bounded here
+    # with a small margin
     assert max(errs) < 2e-3
     assert errs[0] < 1e-8
 
@@ -336,7 +337,7 @@ def test_large72_recycling_and_model():
     finally:
         lg.close()
     assert kd == 4
-    T = olz.tridiag(a.cpu().numpy(), be.cpu().numpy())
+    T = tridiag_of(a.cpu().numpy(), be.cpu().numpy())
     E = E.cpu().numpy()
     assert rel(E[0], T) < 1e-9
     assert np.all(np.linalg.eigvalsh(0.5 * (E[1] + E[1].conj().T)) > -1e-12)   # eps(i w) - 1 >= 0
@@ -393,7 +394,7 @@ def test_large72_block_lanczos_full_shape(tmp_path):
     assert nd == 32 and Q.shape == (256, w.N ** 3)
     G = Q.conj() @ Q.T
     assert np.abs(G - np.eye(256)).max() < 1e-12
-    T = olz.block_tridiag(A, B)
+    T = block_tridiag_of(A, B)
     assert np.abs(E[0] - T).max() < 1e-6 * np.abs(T).max()
     prev = None
     for i, z in enumerate(zs):
