@@ -199,6 +199,132 @@ __device__ __forceinline__ void fft_stage_ls(const cplx<T>* tw, int cnt, Ld ld, 
   __syncthreads();
 }
 
+// Global-memory ends of a transform that reads and writes through an index
+// map (index < 0: no element there).  A thread loads all its indices before
+// any value that depends on them, so it waits on memory twice per stage
+// rather than once per element (an element-by-element gather serialises an
+// index load and a value load per element).
+
+// The indices of a thread's elements in a stage of radix R after
+// sub-transforms of size P (the output positions of fft_stage_ls).
+template <int N, int R, int P, int NT, int MAXCNT, bool TFAST, class Idx>
+__device__ __forceinline__ void stage_out_index(int cnt, Idx idx, int (&ci)[(MAXCNT * (N / R) + NT - 1) / NT][R]) {
+  constexpr int M = N / R;
+  constexpr int MAXB = (MAXCNT * M + NT - 1) / NT;
+  const int nb = cnt * M;
+#pragma unroll
+  for (int k = 0; k < MAXB; ++k) {
+    // threads past the last butterfly load the first one's indices (always
+    // valid) and drop them: the loads stay unconditional and independent
+    const int b = threadIdx.x + k * NT;
+    const int bb = b < nb ? b : 0;
+    int t, i;
+    if (TFAST) { t = bb % cnt; i = bb / cnt; } else { i = bb % M; t = bb / M; }
+    const int kk = i % P;
+    const int j = (i - kk) * R + kk;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = idx(t, j + r * P);
+      ci[k][r] = b < nb ? c : -1;
+    }
+  }
+}
+
+// The indices of a thread's elements in a first stage (P = 1) of radix R
+// (the input positions of fft_stage_ls).
+template <int N, int R, int NT, int MAXCNT, bool TFAST, class Idx>
+__device__ __forceinline__ void stage_in_index(int cnt, Idx idx, int (&ci)[(MAXCNT * (N / R) + NT - 1) / NT][R]) {
+  constexpr int M = N / R;
+  constexpr int MAXB = (MAXCNT * M + NT - 1) / NT;
+  const int nb = cnt * M;
+#pragma unroll
+  for (int k = 0; k < MAXB; ++k) {
+    const int b = threadIdx.x + k * NT;
+    const int bb = b < nb ? b : 0;   // as in stage_out_index
+    int t, i;
+    if (TFAST) { t = bb % cnt; i = bb / cnt; } else { i = bb % M; t = bb / M; }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = idx(t, i + r * M);
+      ci[k][r] = b < nb ? c : -1;
+    }
+  }
+}
+
+// First stage (P = 1, no twiddles) with its inputs gathered from src[ci]
+// (ci from stage_in_index with the same parameters; zero where negative),
+// results stored by st(t, e, v), closing barrier as in fft_stage_ls.
+template <typename T, int N, int R, int SIGN, int NT, int MAXCNT, bool TFAST, class St>
+__device__ __forceinline__ void fft_stage_gather(int cnt, const int (&ci)[(MAXCNT * (N / R) + NT - 1) / NT][R],
+                                                 const cplx<T>* __restrict__ src, St st) {
+  constexpr int M = N / R;
+  constexpr int MAXB = (MAXCNT * M + NT - 1) / NT;
+  const int nb = cnt * M;
+  cplx<T> v[MAXB][R];
+#pragma unroll
+  for (int k = 0; k < MAXB; ++k) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = ci[k][r];
+      const cplx<T> x = src[c >= 0 ? c : 0];   // src[0] exists; its value is discarded
+      v[k][r] = c >= 0 ? x : cplx<T>{0, 0};
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MAXB; ++k) {
+    const int b = threadIdx.x + k * NT;
+    if (b < nb) {
+      int t, i;
+      if (TFAST) { t = b % cnt; i = b / cnt; } else { i = b % M; t = b / M; }
+      Dft<R, SIGN, T>::run(v[k]);
+      const int j = i * R;
+#pragma unroll
+      for (int r = 0; r < R; ++r) st(t, j + r, v[k][r]);
+    }
+  }
+  __syncthreads();
+}
+
+// Last stage with its outputs scattered to dst[ci] (ci from stage_out_index
+// with the same parameters, loaded ahead by the caller; negative: dropped).
+// No closing barrier: nothing in the workgroup reads the results.
+template <typename T, int N, int R, int P, int SIGN, int NT, int MAXCNT, bool TFAST, class Ld>
+__device__ __forceinline__ void fft_stage_scatter(const cplx<T>* tw, int cnt, Ld ld,
+                                                  const int (&ci)[(MAXCNT * (N / R) + NT - 1) / NT][R],
+                                                  cplx<T>* __restrict__ dst) {
+  constexpr int M = N / R;
+  constexpr int MAXB = (MAXCNT * M + NT - 1) / NT;
+  constexpr int TWS = N / (P * R);
+  const int nb = cnt * M;
+  cplx<T> v[MAXB][R];
+#pragma unroll
+  for (int k = 0; k < MAXB; ++k) {
+    const int b = threadIdx.x + k * NT;
+    if (b < nb) {
+      int t, i;
+      if (TFAST) { t = b % cnt; i = b / cnt; } else { i = b % M; t = b / M; }
+      const int kk = i % P;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k][r] = ld(t, i + r * M);
+      if (P > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cplx<T> w = tw[r * kk * TWS];
+          if (SIGN > 0) w.y = -w.y;
+          v[k][r] = v[k][r] * w;
+        }
+      }
+      Dft<R, SIGN, T>::run(v[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MAXB; ++k) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (ci[k][r] >= 0) dst[ci[k][r]] = v[k][r];
+  }
+}
+
 template <typename T, int N, int R, int P, int SIGN, int NT, int MAXCNT, bool TFAST, class Addr>
 __device__ __forceinline__ void fft_stage(cplx<T>* buf, const cplx<T>* tw, int cnt, Addr addr) {
   fft_stage_ls<T, N, R, P, SIGN, NT, MAXCNT, TFAST, true>(

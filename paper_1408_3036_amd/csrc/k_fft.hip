@@ -14,14 +14,59 @@ constexpr int kZCols = 32;           // z-columns per workgroup in column passes
 #endif
 template <int N> constexpr int plane_threads() { return N >= 64 ? 512 : (N == 48 ? LGW_PLANE_THREADS_48 : 256); }
 
+// every kernel here runs at least 256 threads, more than the longest table
 template <typename T, int N>
 __device__ __forceinline__ void load_tw(cplx<T>* tw_s, const cplx<T>* tw) {
-  for (int i = threadIdx.x; i < N; i += blockDim.x) tw_s[i] = tw[i];
+  static_assert(N <= 256, "one table entry per thread");
+  if (threadIdx.x < N) tw_s[threadIdx.x] = tw[threadIdx.x];
+}
+
+// The same in two halves, so that a kernel can issue the load ahead of its
+// other loads and store it once it is needed (a load and its LDS store in one
+// place make every later load wait for it).  Threads past the table load
+// entry 0 and drop it.
+template <typename T, int N>
+__device__ __forceinline__ cplx<T> get_tw(const cplx<T>* tw) {
+  static_assert(N <= 256, "one table entry per thread");
+  return tw[threadIdx.x < N ? threadIdx.x : 0];
+}
+template <typename T, int N>
+__device__ __forceinline__ void put_tw(cplx<T>* tw_s, cplx<T> v) {
+  if (threadIdx.x < N) tw_s[threadIdx.x] = v;
 }
 
 // sequence t of a pruned set {-h..h} mapped to its index mod N
 template <int N>
 __device__ __forceinline__ int pruned(int t, int h) { return t <= h ? t : t + N - 2 * h - 1; }
+
+// buf[cl * LDZ + skew(z)] = src[z * ld + c0 + cl] for z < N, cl < nc, in two
+// halves: all of a thread's loads (zcols_load), later its LDS stores
+// (zcols_store); a loop that stores each value before the next load waits on
+// memory once per element.
+template <int N> constexpr int zcols_per_thread() { return (N * kZCols + 255) / 256; }
+template <typename T, int N>
+__device__ __forceinline__ void zcols_load(const cplx<T>* __restrict__ src, long ld, int c0, int nc,
+                                           cplx<T> (&v)[zcols_per_thread<N>()]) {
+#pragma unroll
+  for (int k = 0; k < zcols_per_thread<N>(); ++k) {
+    const int i = threadIdx.x + k * 256;
+    const int ii = i < N * nc ? i : 0;   // element (0, 0) exists; its copy is not stored
+    const int z = ii / nc, cl = ii - z * nc;
+    v[k] = src[(long)z * ld + c0 + cl];
+  }
+}
+template <typename T, int N>
+__device__ __forceinline__ void zcols_store(cplx<T>* buf, int nc, const cplx<T> (&v)[zcols_per_thread<N>()]) {
+  constexpr int LDZ = skew(N) + 1;
+#pragma unroll
+  for (int k = 0; k < zcols_per_thread<N>(); ++k) {
+    const int i = threadIdx.x + k * 256;
+    if (i < N * nc) {
+      const int z = i / nc, cl = i - z * nc;
+      buf[cl * LDZ + skew(z)] = v[k];
+    }
+  }
+}
 
 // ------------------------------------------------------------------ zinv
 // With partial projector sums (f.part != null) X is the direction D, and the
@@ -31,10 +76,14 @@ __device__ __forceinline__ int pruned(int t, int h) { return t <= h ? t : t + N 
 // registers.
 template <typename T, int N, bool FED>
 __global__ void __launch_bounds__(256)
-k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, long ldx,
+k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* X, long ldx,
        cplx<T>* __restrict__ Tb, long ldt, T scale, const int* __restrict__ act, ProjFeed<T> f,
        cplx<T>* __restrict__ Xout) {
   constexpr int LDZ = skew(N) + 1;
+  // points of the block's run per thread whose loads are issued ahead
+  constexpr int KZ = sizeof(T) == 4 ? 4 : 2;
+  // partial sums per lane loaded ahead (at most 64 slices over 8 lanes)
+  constexpr int KP = 8;
   __shared__ cplx<T> buf[kZCols * LDZ];
   __shared__ cplx<T> tws[N];
   __shared__ cplx<T> Cs[kMaxBands];
@@ -45,21 +94,65 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
   cplx<T>* Ts = Tb + (long)sys * ldt;
   __shared__ int cs[kZCols + 1];
   __shared__ int ch[kZCols];
-  load_tw<T, N>(tws, tw);
-  if (threadIdx.x < nc) {
-    cs[threadIdx.x] = g.col_start[c0 + threadIdx.x];
-    ch[threadIdx.x] = g.col_h[c0 + threadIdx.x];
+  // the block's columns are one contiguous run [run0, run1) of the sphere vector
+  const int run0 = g.col_start[c0];
+  const int run1 = c0 + nc < g.ncols ? g.col_start[c0 + nc] : g.npw;
+  // Everything a thread reads from global memory that does not depend on
+  // another load is issued first, in the order it is needed (the memory
+  // latency is paid about once rather than once per dependent step): the
+  // twiddles and column table, the partial sums and the scalars of the
+  // direction update, the fed transform's point data.  Out-of-range slots
+  // load a valid element (entry 0, column c0, run0, slice 0) and drop it.
+  const cplx<T> twv = get_tw<T, N>(tw);
+  const int cq = threadIdx.x < nc ? threadIdx.x : 0;
+  const int csv = g.col_start[c0 + cq], chv = g.col_h[c0 + cq];
+  T th = T(-1), rrv = T(1);
+  cplx<T> cpv{0, 0};
+  cplx<T> pp[KP];
+  cplx<T> pf_ph[KZ][8], pf_r[KZ], pf_d[KZ];
+  T pf_sc[KZ];
+  [[maybe_unused]] const int v = threadIdx.x >> 3, l = threadIdx.x & 7;
+  if constexpr (FED) {
+    static_assert(kMaxBands * 8 == 256, "eight lanes per band over the workgroup");
+    if (f.r) {
+      th = f.theta[sys];
+      rrv = f.rr[sys];
+      if (l == 0 && v < f.nv) cpv = f.Cp[(long)sys * f.nv + v];
+    }
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+      const int k = l + 8 * q;
+      const bool ok = v < f.nv && k < f.nsplit;
+      pp[q] = f.part[ok ? ((long)k * f.ntot + sys) * f.nv + v : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < KZ; ++k) {
+      const int gi = run0 + threadIdx.x + k * 256;
+      const int gs = gi < run1 ? gi : run0;
+      pf_sc[k] = f.pre ? f.pre[gs] : T(1);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pf_ph[k][u] = u < f.nv ? f.Phi[(long)u * f.ldphi + gs] : cplx<T>{0, 0};
+      pf_d[k] = Xs[gs];
+      pf_r[k] = f.r ? f.r[(long)sys * ldx + gs] : cplx<T>{0, 0};
+    }
   }
-  if (threadIdx.x == 0) cs[nc] = c0 + nc < g.ncols ? g.col_start[c0 + nc] : g.npw;
+  put_tw<T, N>(tws, twv);
+  if (threadIdx.x < nc) {
+    cs[threadIdx.x] = csv;
+    ch[threadIdx.x] = chv;
+  }
+  if (threadIdx.x == 0) cs[nc] = run1;
   for (int i = threadIdx.x; i < kZCols * LDZ; i += 256) buf[i] = cplx<T>{0, 0};
   if constexpr (FED) {
     // this system's projector coefficients, the sum of its slices: eight
     // lanes per band (kMaxBands * 8 = 256 threads), then a shuffle tree
-    static_assert(kMaxBands * 8 == 256, "eight lanes per band over the workgroup");
-    const int v = threadIdx.x >> 3, l = threadIdx.x & 7;
     cplx<T> a{0, 0};
-    if (v < f.nv)
-      for (int k = l; k < f.nsplit; k += 8) a = a + f.part[((long)k * f.ntot + sys) * f.nv + v];
+    if (v < f.nv) {
+#pragma unroll
+      for (int q = 0; q < KP; ++q)
+        if (l + 8 * q < f.nsplit) a = a + pp[q];
+      for (int k = l + 8 * KP; k < f.nsplit; k += 8) a = a + f.part[((long)k * f.ntot + sys) * f.nv + v];
+    }
 #pragma unroll
     for (int o = 4; o > 0; o >>= 1) {
       a.x += __shfl_xor(a.x, o, 64);
@@ -68,52 +161,63 @@ k_zinv(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ X, lo
     if (l == 0 && v < f.nv) {
       // with the direction update, part holds the residual's sums:
       // C(p) = C(r) + beta C(p_old)
-      if (f.r && f.theta[sys] >= T(0)) a = a + (f.theta[sys] / f.rr[sys]) * f.Cp[(long)sys * f.nv + v];
+      if (f.r && th >= T(0)) a = a + (th / rrv) * cpv;
       Cs[v] = a;
       if (f.r && blockIdx.x == 0) f.Cn[(long)sys * f.nv + v] = a;
     }
   }
   // direction update: p = r + beta p while a new norm is parked in theta
+  // (with r set, the direction X is p itself)
   bool upd = false;
   T beta = T(0);
   if constexpr (FED) {
-    upd = f.r && f.theta[sys] >= T(0);
-    if (upd) beta = f.theta[sys] / f.rr[sys];
+    upd = f.r && th >= T(0);
+    if (upd) beta = th / rrv;
   }
   __syncthreads();
-  // the block's columns are one contiguous run of the sphere vector
-  for (int gi = cs[0] + threadIdx.x; gi < cs[nc]; gi += 256) {
+  // one point of the run: the column it belongs to, its value, its slot in
+  // the column buffer
+  auto put = [&](int gi, cplx<T> xv) {
     int lo = 0, hi = nc;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (cs[mid] <= gi) lo = mid; else hi = mid;
     }
     const int mz = gi - cs[lo] - ch[lo];
-    cplx<T> xv;
-    if constexpr (FED) {
-      // the loads of a point come before its stores (the compiler may not
-      // move them across the store to p)
-      cplx<T> ph[8];
-      const T sc = f.pre ? f.pre[gi] : T(1);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) ph[u] = u < f.nv ? f.Phi[(long)u * f.ldphi + gi] : cplx<T>{0, 0};
+    buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)] = xv;
+  };
+  if constexpr (FED) {
+    auto fed_point = [&](int gi, const cplx<T> (&ph)[8], T sc, cplx<T> rv, cplx<T> dv) {
+      cplx<T> xv;
       if (upd) {
-        const long o = (long)sys * ldx + gi;
-        xv = f.r[o] + beta * f.p[o];
-        f.p[o] = xv;
+        xv = rv + beta * dv;
+        f.p[(long)sys * ldx + gi] = xv;
       } else {
-        xv = Xs[gi];
+        xv = dv;
       }
       xv = sc * xv;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (u < f.nv) xv = xv - Cs[u] * ph[u];
-      for (int v = 8; v < f.nv; ++v) xv = xv - Cs[v] * f.Phi[(long)v * f.ldphi + gi];
+      for (int w = 8; w < f.nv; ++w) xv = xv - Cs[w] * f.Phi[(long)w * f.ldphi + gi];
       Xout[(long)sys * ldx + gi] = xv;
-    } else {
-      xv = Xs[gi];
+      put(gi, xv);
+    };
+#pragma unroll
+    for (int k = 0; k < KZ; ++k) {
+      const int gi = run0 + threadIdx.x + k * 256;
+      if (gi < run1) fed_point(gi, pf_ph[k], pf_sc[k], pf_r[k], pf_d[k]);
     }
-    buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)] = xv;
+    for (int gi = run0 + threadIdx.x + KZ * 256; gi < run1; gi += 256) {
+      cplx<T> ph[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ph[u] = u < f.nv ? f.Phi[(long)u * f.ldphi + gi] : cplx<T>{0, 0};
+      const T sc = f.pre ? f.pre[gi] : T(1);
+      const cplx<T> rv = f.r ? f.r[(long)sys * ldx + gi] : cplx<T>{0, 0};
+      fed_point(gi, ph, sc, rv, Xs[gi]);
+    }
+  } else {
+    for (int gi = run0 + threadIdx.x; gi < run1; gi += 256) put(gi, Xs[gi]);
   }
   __syncthreads();
   fft_lds<T, N, +1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + skew(e); });
@@ -146,6 +250,9 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
   constexpr bool DOT = MODE == 1;
   constexpr bool PDOT = MODE == 2;
   constexpr int LDZ = skew(N) + 1;
+  // points of the block's run per thread whose operands are loaded before
+  // the transform (not with PDOT, whose band rows would take the registers)
+  constexpr int KZ = PDOT ? 0 : (sizeof(T) == 4 ? 4 : 2);
   __shared__ cplx<T> buf[kZCols * LDZ];
   __shared__ cplx<T> tws[N];
   const int sys = sys_of(act, blockIdx.y);
@@ -154,47 +261,64 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
   const cplx<T>* Ts = Tb + (long)sys * ldt;
   __shared__ int cs[kZCols + 1];
   __shared__ int ch[kZCols];
-  load_tw<T, N>(tws, tw);
-  if (threadIdx.x < nc) {
-    cs[threadIdx.x] = g.col_start[c0 + threadIdx.x];
-    ch[threadIdx.x] = g.col_h[c0 + threadIdx.x];
-  }
-  if (threadIdx.x == 0) cs[nc] = c0 + nc < g.ncols ? g.col_start[c0 + nc] : g.npw;
-  for (int i = threadIdx.x; i < N * nc; i += 256) {
-    const int z = i / nc, cl = i - z * nc;
-    buf[cl * LDZ + skew(z)] = Ts[(long)z * g.ncols + c0 + cl];
-  }
-  __syncthreads();
-  fft_lds<T, N, -1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + skew(e); });
+  const int run0 = g.col_start[c0];
+  const int run1 = c0 + nc < g.ncols ? g.col_start[c0 + nc] : g.npw;
+  // loads issued in the order they are needed (see k_zinv)
+  const cplx<T> twv = get_tw<T, N>(tw);
+  const int cq = threadIdx.x < nc ? threadIdx.x : 0;
+  const int csv = g.col_start[c0 + cq], chv = g.col_h[c0 + cq];
+  cplx<T> colv[zcols_per_thread<N>()];
+  zcols_load<T, N>(Ts, g.ncols, c0, nc, colv);
   const cplx<T>* Xs = X ? X + (long)sys * ldx : nullptr;
   const cplx<T>* Es = E ? E + (long)sys * lde : nullptr;
   cplx<T>* Ys = Y + (long)sys * ldy;
   const cplx<T> sh = shift ? shift[sys] : cplx<T>{0, 0};
   const T ec = ecoef ? ecoef[sys] : T(0);
   const cplx<T>* Ps = DOT ? cd.p + (long)sys * cd.ldp : nullptr;
+  // the pointwise operands of this thread's first points, loaded while the
+  // columns are gathered and transformed (out-of-range slots load point run0)
+  cplx<T> pf_p[KZ > 0 ? KZ : 1], pf_x[KZ > 0 ? KZ : 1], pf_e[KZ > 0 ? KZ : 1];
+  T pf_k[KZ > 0 ? KZ : 1], pf_o[KZ > 0 ? KZ : 1];
+#pragma unroll
+  for (int k = 0; k < KZ; ++k) {
+    const int i = run0 + threadIdx.x + k * 256;
+    const int is = i < run1 ? i : run0;
+    pf_p[k] = DOT ? Ps[is] : cplx<T>{0, 0};
+    pf_x[k] = Xs ? Xs[is] : cplx<T>{0, 0};
+    pf_k[k] = Xs ? static_cast<T>(g.kin[is]) : T(0);
+    pf_e[k] = Es ? Es[is] : cplx<T>{0, 0};
+    pf_o[k] = dout ? dout[is] : T(1);
+  }
+  put_tw<T, N>(tws, twv);
+  if (threadIdx.x < nc) {
+    cs[threadIdx.x] = csv;
+    ch[threadIdx.x] = chv;
+  }
+  if (threadIdx.x == 0) cs[nc] = run1;
+  zcols_store<T, N>(buf, nc, colv);
+  __syncthreads();
+  fft_lds<T, N, -1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + skew(e); });
   T pap = T(0);
   cplx<T> pc[8];
   if constexpr (PDOT) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) pc[u] = cplx<T>{0, 0};
   }
-  for (int i = cs[0] + threadIdx.x; i < cs[nc]; i += 256) {
+  // one point: y = scale FFT(...) [+ (kin - shift) x] [+ ec E], times dout
+  auto point = [&](int i, cplx<T> pv, cplx<T> xv, T kn, cplx<T> ev, T dv) {
     int lo = 0, hi = nc;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
       if (cs[mid] <= i) lo = mid; else hi = mid;
     }
     const int mz = i - cs[lo] - ch[lo];
-    cplx<T> pv{0, 0};
-    if constexpr (DOT) pv = Ps[i];
     cplx<T> v = scale * buf[lo * LDZ + skew(mz < 0 ? mz + N : mz)];
     if (Xs) {
-      const cplx<T> xv = Xs[i];
-      const cplx<T> k = cplx<T>{static_cast<T>(g.kin[i]) - sh.x, -sh.y};
+      const cplx<T> k = cplx<T>{kn - sh.x, -sh.y};
       v = v + k * xv;
     }
-    if (Es) v = v + ec * Es[i];
-    if (dout) v = dout[i] * v;
+    if (Es) v = v + ec * ev;
+    if (dout) v = dv * v;
     Ys[i] = v;
     if constexpr (DOT) pap += pv.x * v.x + pv.y * v.y;
     if constexpr (PDOT) {
@@ -202,7 +326,15 @@ k_zfwd(Geom g, const cplx<T>* __restrict__ tw, const cplx<T>* __restrict__ Tb, l
       for (int u = 0; u < 8; ++u)
         if (u < pp.nv) pc[u] = pc[u] + cmulc(pp.Phi[(long)u * pp.ldphi + i], v);
     }
+  };
+#pragma unroll
+  for (int k = 0; k < KZ; ++k) {
+    const int i = run0 + threadIdx.x + k * 256;
+    if (i < run1) point(i, pf_p[k], pf_x[k], pf_k[k], pf_e[k], pf_o[k]);
   }
+  for (int i = run0 + threadIdx.x + KZ * 256; i < run1; i += 256)
+    point(i, DOT ? Ps[i] : cplx<T>{0, 0}, Xs ? Xs[i] : cplx<T>{0, 0}, Xs ? static_cast<T>(g.kin[i]) : T(0),
+          Es ? Es[i] : cplx<T>{0, 0}, dout ? dout[i] : T(1));
   if constexpr (PDOT) {
     // the workgroup's sums: over each wave by shuffles, then over the 4 waves
     __shared__ cplx<T> red[4][8];
@@ -268,18 +400,21 @@ k_plane_hv(Geom g, const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ Tb, lon
   const int sys = sys_of(act, blockIdx.y);
   cplx<T>* Ts = Tb + (long)sys * ldt + (long)z * g.ncols;
   const int* __restrict__ colof = g.col_of;
-  load_tw<T, N>(tws, tw);   // first read after the first stage's closing barrier
   const int hy = g.hy;
   const int ny = 2 * hy + 1;
   auto col = [hy](int t, int e) { return e * LD + pruned<N>(t, hy); };
+  auto sphere_col = [colof, hy](int t, int e) { return colof[e * N + pruned<N>(t, hy)]; };
+  // loads in the order they are needed: twiddles (first read after the first
+  // stage's closing barrier), the first stage's column indices, the last
+  // stage's (in flight while the transform runs), then the first stage's values
+  const cplx<T> twv = get_tw<T, N>(tw);
+  int cin[(N * (N / A) + NT - 1) / NT][A];
+  stage_in_index<N, A, NT, N, true>(ny, sphere_col, cin);
+  int cout[(N * (N / B) + NT - 1) / NT][B];
+  stage_out_index<N, B, A, NT, N, true>(ny, sphere_col, cout);
+  put_tw<T, N>(tws, twv);
   // x-inverse stage 1 (radix A, no twiddles) from the sphere columns
-  fft_stage_ls<T, N, A, 1, +1, NT, N, true, false>(
-      tws, ny,
-      [&](int t, int e) {
-        const int ci = colof[e * N + pruned<N>(t, hy)];
-        return ci >= 0 ? Ts[ci] : cplx<T>{0, 0};
-      },
-      [&](int t, int e, cplx<T> v) { pl[col(t, e)] = v; });
+  fft_stage_gather<T, N, A, +1, NT, N, true>(ny, cin, Ts, [&](int t, int e, cplx<T> v) { pl[col(t, e)] = v; });
   // x-inverse stage 2 (radix B after A)
   fft_stage<T, N, B, A, +1, NT, N, true>(pl, tws, ny, col);
   const T* Vz = Vt + (long)z * N * N;
@@ -288,12 +423,7 @@ k_plane_hv(Geom g, const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ Tb, lon
   // x-forward stage 1
   fft_stage<T, N, A, 1, -1, NT, N, true>(pl, tws, ny, col);
   // x-forward stage 2, stored to the sphere columns
-  fft_stage_ls<T, N, B, A, -1, NT, N, true, false>(
-      tws, ny, [&](int t, int e) { return pl[col(t, e)]; },
-      [&](int t, int e, cplx<T> v) {
-        const int ci = colof[e * N + pruned<N>(t, hy)];
-        if (ci >= 0) Ts[ci] = v;
-      });
+  fft_stage_scatter<T, N, B, A, -1, NT, N, true>(tws, ny, [&](int t, int e) { return pl[col(t, e)]; }, cout, Ts);
 }
 
 // --------------------------------------------------------- plane_pair_fwd
@@ -398,11 +528,11 @@ k_zfull_mul(const cplx<T>* __restrict__ tw, cplx<T>* __restrict__ G, long ldg,
   const int c0 = blockIdx.x * kZCols;
   const int nc = min(kZCols, NN - c0);
   cplx<T>* Gs = G + (long)blockIdx.y * ldg;
-  load_tw<T, N>(tws, tw);
-  for (int i = threadIdx.x; i < N * nc; i += 256) {
-    const int z = i / nc, cl = i - z * nc;
-    buf[cl * LDZ + skew(z)] = Gs[(long)z * NN + c0 + cl];
-  }
+  const cplx<T> twv = get_tw<T, N>(tw);
+  cplx<T> colv[zcols_per_thread<N>()];
+  zcols_load<T, N>(Gs, NN, c0, nc, colv);
+  put_tw<T, N>(tws, twv);
+  zcols_store<T, N>(buf, nc, colv);
   __syncthreads();
   fft_lds<T, N, -1, 256, kZCols, false>(buf, tws, nc, [](int t, int e) { return t * LDZ + skew(e); });
   for (int i = threadIdx.x; i < N * nc; i += 256) {

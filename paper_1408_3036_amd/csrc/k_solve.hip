@@ -1496,17 +1496,13 @@ template <typename T>
 __global__ void __launch_bounds__(NT)
 k_cg_split2f(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int nsplit, const T* __restrict__ dots,
              int ndots, T* __restrict__ part2, ProjFeed<T> f) {
+  // points per thread whose loads are issued together (a slice of about 1024
+  // points over 256 threads); partial sums of p^H A p loaded side by side
+  constexpr int KB = sizeof(T) == 4 ? 5 : 2;
+  constexpr int KD = sizeof(T) == 4 ? 32 : 16;
   __shared__ T sm[16 * (NT / 64)];
   const int slot = blockIdx.y;
   const int sys = sys_of(act, slot);
-  if (v.flag[sys]) return;
-  T pAp = T(0);
-  for (int k = 0; k < ndots; ++k) pAp += dots[(long)slot * ndots + k];
-  if (!(pAp > T(0))) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) v.flag[sys] = FLAG_BREAK;
-    return;
-  }
-  const T alpha = v.rr[sys] / pAp;
   int i0, i1;
   slice_of<T>(npw, nsplit, i0, i1);
   const long off = (long)sys * v.ld;
@@ -1514,16 +1510,46 @@ k_cg_split2f(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int n
   cplx<T>* r = v.r + off;
   const cplx<T>* p = v.p + off;
   const cplx<T>* Ap = v.Ap + off;
+  // Every load that depends only on the system is issued before the flag,
+  // alpha and the stores are decided: the memory latency is paid about once
+  // instead of once per dependent step (a point's stores would otherwise
+  // hold back the next point's loads).  Slots past the slice read its first
+  // point (point 0 for an empty slice) and drop it.
+  const int base = i0 < i1 ? i0 : 0;
+  const int flag = v.flag[sys];
+  const T rr = v.rr[sys];
+  T dv[KD];
+#pragma unroll
+  for (int k = 0; k < KD; ++k) dv[k] = dots[(long)slot * ndots + (k < ndots ? k : 0)];
+  cplx<T> pv[KB], av[KB], rv[KB], xv[KB], ph[KB][8];
+  T scv[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int i = i0 + threadIdx.x + k * NT;
+    const int is = i < i1 ? i : base;
+    pv[k] = p[is];
+    av[k] = Ap[is];
+    rv[k] = r[is];
+    xv[k] = x[is];
+    scv[k] = f.pre ? f.pre[is] : T(1);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ph[k][u] = u < f.nv ? f.Phi[(long)u * f.ldphi + is] : cplx<T>{0, 0};
+  }
+  if (flag) return;
+  T pAp = T(0);
+#pragma unroll
+  for (int k = 0; k < KD; ++k)
+    if (k < ndots) pAp += dv[k];
+  for (int k = KD; k < ndots; ++k) pAp += dots[(long)slot * ndots + k];
+  if (!(pAp > T(0))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) v.flag[sys] = FLAG_BREAK;
+    return;
+  }
+  const T alpha = rr / pAp;
   T acc[1] = {T(0)};
   T fa[16];
   feed_zero(fa);
-  for (int i = i0 + threadIdx.x; i < i1; i += NT) {
-    // every load of the step before its stores
-    const cplx<T> pi = p[i], ai = Ap[i], ri = r[i], xi = x[i];
-    cplx<T> ph[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) ph[u] = u < f.nv ? f.Phi[(long)u * f.ldphi + i] : cplx<T>{0, 0};
-    const T sc = f.pre ? f.pre[i] : T(1);
+  auto step = [&](int i, cplx<T> pi, cplx<T> ai, cplx<T> ri, cplx<T> xi, T sc, const cplx<T> (&phi)[8]) {
     x[i] = xi + alpha * pi;
     const cplx<T> rn = ri - alpha * ai;
     r[i] = rn;
@@ -1531,9 +1557,22 @@ k_cg_split2f(SolveVecs<T> v, int npw, T tol2, const int* __restrict__ act, int n
     const cplx<T> y = sc * rn;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      fa[2 * u] += ph[u].x * y.x + ph[u].y * y.y;
-      fa[2 * u + 1] += ph[u].x * y.y - ph[u].y * y.x;
+      fa[2 * u] += phi[u].x * y.x + phi[u].y * y.y;
+      fa[2 * u + 1] += phi[u].x * y.y - phi[u].y * y.x;
     }
+  };
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int i = i0 + threadIdx.x + k * NT;
+    if (i < i1) step(i, pv[k], av[k], rv[k], xv[k], scv[k], ph[k]);
+  }
+  for (int i = i0 + threadIdx.x + KB * NT; i < i1; i += NT) {
+    // every load of the point before its stores
+    const cplx<T> pi = p[i], ai = Ap[i], ri = r[i], xi = x[i];
+    cplx<T> phi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) phi[u] = u < f.nv ? f.Phi[(long)u * f.ldphi + i] : cplx<T>{0, 0};
+    step(i, pi, ai, ri, xi, f.pre ? f.pre[i] : T(1), phi);
   }
   block_sum<T, 1>(acc, sm);
   feed_store(f, 0, blockIdx.x, sys, fa, sm);

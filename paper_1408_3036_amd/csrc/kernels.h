@@ -29,6 +29,7 @@ struct ProjFeed {
   // residual r, and while theta[sys] >= 0 the transform first sets
   // p = r + beta p (beta = theta / rr) and uses C = sum(part) + beta Cp;
   // its workgroup 0 leaves C in Cn (the last transform moves it to Cp).
+  // With r set, the direction D given to the transform must be p.
   const cplx<T>* r = nullptr;
   cplx<T>* p = nullptr;           // the directions, updated in place
   const T* rr = nullptr;

@@ -434,6 +434,8 @@ void happly(lgw_ctx* c, const cplx<T>* X, long ldx, cplx<T>* Y, long ldy, const 
   const long ldt = (long)c->N * c->ncols;
   const double e = 2.0 * sizeof(T);   // bytes of one complex value
   const double cols = (double)nsys * c->N * c->ncols, sph = (double)nsys * c->npw;
+  // the fed transform reads the direction once, as p when it updates it
+  if (fed && fed->r && D != fed->p) throw Fail{LGW_EINVAL, "internal: fed direction is not the CG direction"};
   hipEvent_t t0 = c->begin(nsys);
   if (fed)
     launch_zinv_fed<T>(c->geom, tw_of<T>(c), *fed, D, Xw, ldx, Tb, ldt, act, nsys, c->stream);
