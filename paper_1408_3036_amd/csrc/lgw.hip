@@ -243,8 +243,10 @@ struct lgw_ctx {
       pool.pop_back();
       return e;
     }
+    // timing only, read after a stream synchronisation: no system-scope fence
+    // (its cache writeback and invalidation would be timed with the kernel)
     hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     return e;
   }
   // bracket one launch: call begin() before it and end() after it.  Only
