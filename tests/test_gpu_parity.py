@@ -153,6 +153,33 @@ def test_lanczos_matches_oracle(sysc1):
     assert np.abs(Q.conj() @ Q.T - np.eye(k)).max() < 1e-13
 
 
+def test_lanczos_past_the_fused_gram_schmidt_limit(sysc1):
+    """520 steps on the small box: past 512 earlier vectors the Gram-Schmidt
+    passes take their unfused form (coefficients summed in one kernel, the
+    update in another).  Alpha and beta against the oracle's recursion from
+    the same seed (stored, tests/golden/lanczos520_oracle.json), the basis
+    orthonormal."""
+    import json
+    import os
+    w, b, s, lg = sysc1
+    d = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "lanczos520_oracle.json")))
+    k = d["k"]
+    q0 = torch.from_numpy(random_potentials(w.N, 1, 97)[0])
+    a, be, Q, kd = lg.lanczos(q0, k)
+    assert kd == d["k_done"] == k
+    ra, rb = np.array(d["alpha"]), np.array(d["beta"])
+    a, be = a.cpu().numpy(), be.cpu().numpy()
+    scale = np.abs(ra).max()
+    da, db = np.abs(a - ra) / scale, np.abs(be - rb) / scale
+    Qh = Q.cpu().numpy()
+    orth = np.abs(Qh.conj() @ Qh.T - np.eye(k)).max()
+    print(f"520 steps: alpha {da.max():.1e} (first 512: {da[:512].max():.1e}), beta {db.max():.1e}, "
+          f"Q^H Q - I {orth:.1e}")
+    assert da.max() <= 1e-10 and db.max() <= 1e-10
+    assert orth < 1e-12
+
+
 def test_lanczos_resumes_from_a_prior_state(sysc1):
     """A recursion checkpointed after 4 steps and resumed to 8 gives the
     uninterrupted 8-step result (the library's reductions are in fixed order,
