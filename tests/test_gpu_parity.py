@@ -15,7 +15,7 @@ from oracle.pw import Basis
 from oracle.sos import SOS
 from oracle import lanczos as olz
 from synthetic import make_workload, random_potentials
-from tests.gpu_common import lib_order, rel, colwise_rel, tridiag_of
+from tests.gpu_common import lib_order, rel, colwise_rel, tridiag_of, block_tridiag_of
 
 
 @pytest.fixture(scope="module")
@@ -292,6 +292,53 @@ def test_block_lanczos_matches_oracle(sysc1):
     assert np.abs(B - RB).max() <= 1e-10 * scale
     assert colwise_rel(Q, RQ) < 1e-10
     assert np.abs(Q.conj() @ Q.T - np.eye(12)).max() < 1e-13
+
+
+def test_block_lanczos_largest_block_matches_oracle(sysc1):
+    """The largest block the library takes (16 vectors), two block steps,
+    against the oracle; a 17-vector block is refused."""
+    from paper_1408_3036_amd.lgw import LgwError
+    w, b, s, lg = sysc1
+    Q0 = random_potentials(w.N, 16, 41)
+    A, B, Q, nd = lg.block_lanczos(torch.from_numpy(Q0), 2)
+    RA, RB, RQ = olz.block_lanczos(lambda v: s.M(0.0, v), Q0, 2)
+    assert nd == 2
+    A, B, Q = A.cpu().numpy(), B.cpu().numpy(), Q.cpu().numpy()
+    scale = np.abs(RA).max()
+    print(f"block lanczos b=16: A {np.abs(A - RA).max() / scale:.2e} B {np.abs(B - RB).max() / scale:.2e} "
+          f"Q {colwise_rel(Q, RQ):.2e}")
+    assert np.abs(A - RA).max() <= 1e-10 * scale
+    assert np.abs(B - RB).max() <= 1e-10 * scale
+    assert colwise_rel(Q, RQ) < 1e-10
+    assert np.abs(Q.conj() @ Q.T - np.eye(32)).max() < 1e-13
+    with pytest.raises(LgwError) as e:
+        lg.block_lanczos(torch.from_numpy(random_potentials(w.N, 17, 42)), 1)
+    assert e.value.name == "LGW_EINVAL"
+
+
+def test_block_lanczos_rank_deficient_seed_block(sysc1):
+    """A seed block whose fourth vector repeats its second: the dependent
+    column is deflated (replaced by a fixed-seed random direction, which the
+    library and the oracle draw from different generators).  Unique, and
+    compared with the oracle: the first block's entries among the three
+    columns orthonormalised before the dependent one.  Checked as properties:
+    the basis orthonormal, E(0) on it the block tridiagonal."""
+    w, b, s, lg = sysc1
+    Q0 = random_potentials(w.N, 6, 43)
+    Q0[3] = Q0[1]
+    A, B, Q, nd = lg.block_lanczos(torch.from_numpy(Q0), 2)
+    RA, RB, RQ = olz.block_lanczos(lambda v: s.M(0.0, v), Q0, 2)
+    assert nd == 2
+    E0 = lg.project(Q, [0.0]).cpu().numpy()[0]
+    A, B, Q = A.cpu().numpy(), B.cpu().numpy(), Q.cpu().numpy()
+    scale = np.abs(RA).max()
+    a3 = np.abs(A[0, :3, :3] - RA[0, :3, :3]).max() / scale
+    q3 = colwise_rel(Q[:3], RQ[:3])
+    T = block_tridiag_of(A, B)
+    print(f"rank-deficient block: A[0][:3,:3] {a3:.2e}, Q[:3] {q3:.2e}, E(0) - T {np.abs(E0 - T).max() / scale:.2e}")
+    assert a3 <= 1e-10 and q3 < 1e-10
+    assert np.abs(Q.conj() @ Q.T - np.eye(12)).max() < 1e-12
+    assert np.abs(E0 - T).max() <= 1e-9 * scale
 
 
 def test_block_lanczos_one_vector_equals_lanczos(sysc1):
